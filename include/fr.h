@@ -1,0 +1,205 @@
+/*
+ * fr.h -- C ABI of the MI355X flux reconstruction (FR) solver library.
+ *
+ * The library advances the compressible Navier-Stokes equations of the
+ * paper's Section 2.1 (Eqs. (1)-(7): conserved variables rho, rho u_i,
+ * rho E; F = F_inv - F_vis with F_vis,j = (0, tau_ij, u_i tau_ij - q_j);
+ * ideal gas; Stokes stress; heat flux from the enthalpy gradient) on
+ * quadrilateral (2D) or hexahedral (3D) elements with an FR discretisation
+ * (Huynh 2007, named in the paper's Section 1 for its solver) and classic
+ * RK4 in time.  The design evaluation of the paper's Algorithm 1 needs the
+ * flow advanced on one candidate mesh and the time-averaged lift and drag
+ * (Section 4, objective function); these calls are exactly that.
+ *
+ * Scheme (fixed): Gauss-Legendre solution points (tensor product), flux
+ * points where the solution-point lines meet the faces, g_DG (Radau)
+ * correction functions, Rusanov inviscid common flux, BR1 common solution
+ * and viscous flux, periodic faces by translation, Riemann-invariant far
+ * field, no-slip adiabatic wall.
+ *
+ * Conventions shared by every array below
+ *   - Reference element [-1,1]^dim.  Geometry nodes of an element are the
+ *     (q+1)^dim equispaced Lagrange nodes, lexicographic with xi fastest:
+ *     node a = a0 + (q+1) a1 + (q+1)^2 a2 at xi_k = -1 + 2 a_k / q.
+ *   - Solution point i = i0 + n i1 + n^2 i2 (n = order + 1), xi fastest.
+ *   - Local face f = 2k + s lies on axis k at xi_k = -1 (s = 0) or +1
+ *     (s = 1).  Flux point q = f * nfp + m, nfp = n^(dim-1); m runs over the
+ *     remaining axes in increasing axis order, the lower axis fastest.
+ *   - States are conserved variables in FP64, canonical layout
+ *     [element][solution point][variable], variables (rho, rho u, rho v,
+ *     [rho w,] rho E).
+ *
+ * Errors: every call returns an fr_status; FR_OK is 0 and errors are
+ * negative.  fr_last_error() returns a thread-local message for the last
+ * failing call of the calling thread.  No C++ exception crosses the ABI.
+ *
+ * Ownership: input arrays are caller-owned, read during the call and never
+ * retained.  A handle owns its device memory (allocated through the
+ * optional alloc/free callbacks, else hipMalloc/hipFree) until destroyed.
+ *
+ * Threading: a handle is not thread-safe; distinct handles may be used
+ * from distinct threads.  Work is ordered on the handle's stream.
+ */
+#ifndef FR_H
+#define FR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fr_mesh fr_mesh;
+typedef struct fr_pool fr_pool;
+
+typedef enum {
+  FR_OK = 0,
+  FR_E_ARG = -1,         /* invalid argument or descriptor */
+  FR_E_MESH = -2,        /* unmatched face, bad connectivity or non-positive Jacobian */
+  FR_E_NOMEM = -3,       /* allocation failed, or a pool request does not fit its budget */
+  FR_E_DEVICE = -4,      /* HIP runtime error */
+  FR_E_NONFINITE = -5,   /* a step produced a non-finite state (left in place) */
+  FR_E_STATE = -6,       /* call not valid in the current state (e.g. no state set) */
+  FR_E_UNSUPPORTED = -7  /* order, dimension or precision not compiled in */
+} fr_status;
+
+enum { FR_FP64 = 0, FR_FP32 = 1 };        /* state, operator and flux precision */
+enum { FR_BC_WALL = 1, FR_BC_FARFIELD = 2 };
+
+typedef void *(*fr_alloc_fn)(size_t bytes, void *ctx, void *stream);
+typedef void (*fr_free_fn)(void *ptr, void *ctx, void *stream);
+
+/* One mesh and its flow constants.  All pointers are host pointers. */
+typedef struct {
+  int32_t dim;             /* 2 or 3 */
+  int32_t order;           /* polynomial order p, 1..4 */
+  int32_t geom_order;      /* q = 1 (straight) or 2 (quadratic, curved) */
+  int32_t precision;       /* FR_FP64 or FR_FP32 (metrics and force sums are FP64 in both) */
+  int64_t n_nodes;
+  const double *nodes;     /* [n_nodes][dim] */
+  int64_t n_elems;
+  const int64_t *elem_nodes; /* [n_elems][(q+1)^dim] node ids */
+  int32_t n_periodic;
+  const double *periodic_shift; /* [n_periodic][dim] translations pairing periodic faces */
+  int64_t n_bfaces;
+  const int64_t *bfaces;   /* [n_bfaces][3] = {element, local face, FR_BC_*} */
+  double gamma, prandtl, mu; /* ratio of specific heats, Prandtl number, constant viscosity */
+  double freestream[5];    /* rho, u, v, w, p: far-field state and force normalisation */
+  double ref_area;         /* C = F . dir / (0.5 rho |U|^2 ref_area) */
+  double lift_dir[3], drag_dir[3];
+  double dt;               /* fixed RK4 step */
+  int32_t device;          /* HIP device ordinal */
+  void *stream;            /* hipStream_t to order work on, or NULL for the default stream */
+  fr_alloc_fn alloc;       /* optional device allocator (e.g. a framework's caching allocator) */
+  fr_free_fn free;
+  void *alloc_ctx;
+} fr_mesh_desc;
+
+/* Build a solver for one mesh: connectivity (faces matched by node ids,
+ * periodic faces by the listed translations, flux points by position),
+ * FP64 metrics, operators, device arrays.  FR_E_MESH if a face is neither
+ * matched nor listed as a boundary, or a Jacobian is not positive. */
+fr_status fr_mesh_create(const fr_mesh_desc *desc, fr_mesh **out);
+
+/* Several meshes (candidate designs) advanced together by every kernel
+ * launch: the layer of parallelism that runs the 2n poll designs of the
+ * paper's Algorithm 1 concurrently.  All descriptors must share dim,
+ * order, precision, gamma, prandtl, mu, device and stream; dt, free stream
+ * and force normalisation are per design.  State arrays of the batch are
+ * the designs' canonical arrays concatenated in descriptor order. */
+fr_status fr_batch_create(const fr_mesh_desc *descs, int32_t n_designs, fr_mesh **out);
+
+void fr_mesh_destroy(fr_mesh *m);
+
+/* info[0..9] = dim, order, n_designs, total elements, solution points per
+ * element, flux points per element, variables, precision, element blocks,
+ * device bytes held. */
+fr_status fr_mesh_info(const fr_mesh *m, int64_t *info);
+
+/* Elements of design d and their offset in the concatenated arrays. */
+fr_status fr_design_range(const fr_mesh *m, int32_t design, int64_t *first, int64_t *count);
+
+/* Physical coordinates of the solution points, [elements][n_u][3] (z = 0 in 2D). */
+fr_status fr_solution_points(const fr_mesh *m, double *xyz);
+
+/* Partner of every flux point, [elements][n_f]: e' * n_f + q' for an
+ * interior or periodic face, -kind for a boundary face (element indices
+ * are positions in the concatenated arrays). */
+fr_status fr_neighbours(const fr_mesh *m, int64_t *nbr);
+
+/* Host-only variant of the neighbour table for a single descriptor: runs
+ * the connectivity and geometry checks without touching a device.  nbr is
+ * [n_elems][n_f] as for fr_neighbours; xyz (may be NULL) receives the
+ * solution points [n_elems][n_u][3]. */
+fr_status fr_connectivity(const fr_mesh_desc *desc, int64_t *nbr, double *xyz);
+
+/* Set / get the conserved state (host, FP64, canonical layout).  Setting
+ * the state also clears the running lift and drag means. */
+fr_status fr_set_state(fr_mesh *m, const double *u);
+fr_status fr_get_state(const fr_mesh *m, double *u);
+
+/* Advance n RK4 steps of dt on the device and wait for them.  After each
+ * step the wall force of the new state is added to the running means.
+ * FR_E_NONFINITE if any step produced a non-finite value. */
+fr_status fr_step(fr_mesh *m, int64_t n);
+
+/* Enqueue n steps without waiting (the state stays in device memory). */
+fr_status fr_step_async(fr_mesh *m, int64_t n);
+/* Wait for enqueued work; reports FR_E_NONFINITE like fr_step. */
+fr_status fr_sync(fr_mesh *m);
+
+/* out[0..7] = C_L, C_D, F_x, F_y, F_z of the last step; mean C_L, mean C_D
+ * over the steps since the state was set; number of steps averaged.
+ * Lift and drag come from the wall traction integral of (p n - tau . n). */
+fr_status fr_forces(const fr_mesh *m, int32_t design, double *out);
+
+/* Test hook: R(u) = dU/dt of the semi-discretisation, host FP64 canonical
+ * arrays in and out.  Leaves the current state untouched. */
+fr_status fr_residual(fr_mesh *m, const double *u, double *r);
+
+/* Device pointer and layout of the state, for callers that keep data on
+ * the device: layout [block][n_u padded to 16][variables][16 elements]. */
+fr_status fr_state_device(const fr_mesh *m, void **ptr, int64_t *bytes);
+
+/* Kernel-timing hook for benchmarks: records HIP events around the launches
+ * of the named kernel (0 = all) in the next fr_step call and returns the
+ * summed milliseconds and launch count.  kernel ids: 1 face, 2 gradient and
+ * flux, 3 viscous trace, 4 divergence and RK update, 5 interpolation. */
+fr_status fr_profile_kernels(fr_mesh *m, int64_t steps, double *ms_per_kernel, int64_t *launches);
+
+/* ---- served requests: continuous batching under an HBM budget ---------- */
+
+/* A pool admits solve requests while their device footprint fits in
+ * hbm_budget bytes; admitted requests run concurrently on the device. */
+fr_status fr_pool_create(size_t hbm_budget, int32_t device, fr_pool **out);
+void fr_pool_destroy(fr_pool *p);
+
+/* Bytes of device memory a request with this descriptor would hold. */
+fr_status fr_footprint(const fr_mesh_desc *desc, size_t *bytes);
+
+/* Admit a request that runs `steps` RK4 steps from state u0 (canonical
+ * FP64, may be NULL for the uniform free stream).  FR_E_NOMEM if it does
+ * not fit now; nothing is allocated then.  *slot identifies it. */
+fr_status fr_pool_admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, int64_t steps,
+                        int64_t *slot);
+
+/* Enqueue up to k further steps for every running request and wait for
+ * them.  Slots that have finished are written to done[0..*n_done-1]
+ * (capacity max_done). */
+fr_status fr_pool_tick(fr_pool *p, int64_t k, int64_t *done, int32_t max_done, int32_t *n_done);
+
+/* Result of a finished request (fr_forces layout) and its state if u is
+ * not NULL; frees the slot and its device memory. */
+fr_status fr_pool_result(fr_pool *p, int64_t slot, double *out, double *u);
+
+/* used[0] = bytes held, used[1] = running requests. */
+fr_status fr_pool_usage(const fr_pool *p, int64_t *used);
+
+const char *fr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FR_H */

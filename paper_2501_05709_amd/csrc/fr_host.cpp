@@ -1,0 +1,1067 @@
+// Host side of the FR library: basis and operator construction, mesh
+// connectivity, FP64 geometry, block packing, HIP graphs and the C ABI of
+// include/fr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fr.h"
+#include "fr_internal.hpp"
+
+using namespace fr;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct FrError {
+  fr_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(fr_status c, const std::string &m) { throw FrError{c, m}; }
+
+void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) fail(FR_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class F> fr_status guarded(F &&f) {
+  try {
+    f();
+    return FR_OK;
+  } catch (const FrError &e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_err = "host allocation failed";
+    return FR_E_NOMEM;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    return FR_E_ARG;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1D basis: Gauss-Legendre points, barycentric Lagrange algebra, Radau g'
+// ---------------------------------------------------------------------------
+struct Basis1D {
+  int n;
+  std::vector<double> x, w, bw;   // nodes, weights, barycentric weights
+  std::vector<double> D;          // D[i*n+j] = l_j'(x_i)
+  std::vector<double> lm, lp;     // l_j(-1), l_j(+1)
+  std::vector<double> gLd, gRd;   // g_L'(x_i), g_R'(x_i)
+
+  static void legendre_pair(int k, double t, double &P, double &Pm1) {
+    // P_k(t) and P_{k-1}(t) by Bonnet's recursion
+    double a = 1.0, b = t;
+    if (k == 0) { P = 1.0; Pm1 = 0.0; return; }
+    for (int m = 1; m < k; ++m) {
+      const double c = ((2 * m + 1) * t * b - m * a) / (m + 1);
+      a = b;
+      b = c;
+    }
+    P = b;
+    Pm1 = a;
+  }
+  // derivative of P_k from (t^2 - 1) P_k' = k (t P_k - P_{k-1}); interior t only
+  static double legendre_d(int k, double t) {
+    if (k == 0) return 0.0;
+    double P, Pm1;
+    legendre_pair(k, t, P, Pm1);
+    return k * (t * P - Pm1) / (t * t - 1.0);
+  }
+
+  explicit Basis1D(int order) : n(order + 1) {
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+      // Newton on P_n from the Chebyshev-Gauss guess, ascending order
+      double t = -std::cos(M_PI * (4.0 * i + 3.0) / (4.0 * n + 2.0));
+      for (int it = 0; it < 60; ++it) {
+        double P, Pm1;
+        legendre_pair(n, t, P, Pm1);
+        const double dP = n * (t * P - Pm1) / (t * t - 1.0);
+        const double step = P / dP;
+        t -= step;
+        if (std::fabs(step) < 4e-17) break;
+      }
+      x[i] = t;
+      const double dP = legendre_d(n, t);
+      w[i] = 2.0 / ((1.0 - t * t) * dP * dP);
+    }
+    bw.assign(n, 1.0);
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k)
+        if (k != j) bw[j] /= (x[j] - x[k]);
+    D.assign(n * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      double diag = 0.0;
+      for (int j = 0; j < n; ++j) {
+        if (j == i) continue;
+        D[i * n + j] = (bw[j] / bw[i]) / (x[i] - x[j]);
+        diag -= D[i * n + j];
+      }
+      D[i * n + i] = diag;
+    }
+    lm = eval_all(-1.0);
+    lp = eval_all(1.0);
+    gRd.resize(n);
+    gLd.resize(n);
+    for (int i = 0; i < n; ++i) {
+      gRd[i] = 0.5 * (legendre_d(order, x[i]) + legendre_d(order + 1, x[i]));
+      gLd[i] = -0.5 * (legendre_d(order, -x[i]) + legendre_d(order + 1, -x[i]));
+    }
+  }
+  // l_j(t) for all j, barycentric form of the second kind
+  std::vector<double> eval_all(double t) const {
+    std::vector<double> out(n, 0.0);
+    for (int j = 0; j < n; ++j)
+      if (t == x[j]) { out[j] = 1.0; return out; }
+    double den = 0.0;
+    for (int j = 0; j < n; ++j) den += bw[j] / (t - x[j]);
+    for (int j = 0; j < n; ++j) out[j] = bw[j] / (t - x[j]) / den;
+    return out;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// reference-element index maps (conventions of include/fr.h)
+// ---------------------------------------------------------------------------
+struct RefElem {
+  int dim, n, nu, nfp, nf;
+  RefElem(int d, int order) : dim(d), n(order + 1) {
+    nu = d == 2 ? n * n : n * n * n;
+    nfp = d == 2 ? n : n * n;
+    nf = 2 * d * nfp;
+  }
+  // the two axes spanning face axis k, lower first
+  std::array<int, 2> face_axes(int k) const {
+    if (dim == 2) return {1 - k, -1};
+    if (k == 0) return {1, 2};
+    if (k == 1) return {0, 2};
+    return {0, 1};
+  }
+  std::array<int, 3> upt_idx(int i) const { return {i % n, (i / n) % n, dim == 3 ? i / (n * n) : 0}; }
+  int upt(const std::array<int, 3> &c) const { return c[0] + n * c[1] + (dim == 3 ? n * n * c[2] : 0); }
+  // solution point on the line through face point m of a face on axis k, at position j
+  int line_point(int k, int m, int j) const {
+    std::array<int, 3> c{0, 0, 0};
+    auto ax = face_axes(k);
+    c[k] = j;
+    c[ax[0]] = m % n;
+    if (dim == 3) c[ax[1]] = m / n;
+    return upt(c);
+  }
+  int face_index(int i, int k) const {  // face point m of solution point i for axis k
+    auto c = upt_idx(i);
+    auto ax = face_axes(k);
+    return dim == 2 ? c[ax[0]] : c[ax[0]] + n * c[ax[1]];
+  }
+  std::array<double, 3> fpt_ref(const Basis1D &b, int f, int m) const {
+    const int k = f / 2;
+    std::array<double, 3> r{0, 0, 0};
+    r[k] = (f & 1) ? 1.0 : -1.0;
+    auto ax = face_axes(k);
+    r[ax[0]] = b.x[m % n];
+    if (dim == 3) r[ax[1]] = b.x[m / n];
+    return r;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// dense operators
+// ---------------------------------------------------------------------------
+struct Operators {
+  Dims dm;
+  std::vector<double> Mint, Mgrad, Mgcorr, MdivS, Mcorr;  // row-major
+  int nu, nf, dim;
+  Operators(int d, int order) : dm(d, order) {
+    Basis1D b(order);
+    RefElem R(d, order);
+    nu = R.nu;
+    nf = R.nf;
+    dim = d;
+    const int n = R.n, nfp = R.nfp;
+    Mint.assign(size_t(nf) * nu, 0.0);
+    Mgrad.assign(size_t(d) * nu * nu, 0.0);
+    Mgcorr.assign(size_t(d) * nu * nf, 0.0);
+    std::vector<double> Mdiv(size_t(nu) * d * nu, 0.0), Mnint(size_t(nf) * d * nu, 0.0);
+    Mcorr.assign(size_t(nu) * nf, 0.0);
+    for (int f = 0; f < 2 * d; ++f) {
+      const int k = f / 2;
+      const double sg = (f & 1) ? 1.0 : -1.0;
+      const auto &l = (f & 1) ? b.lp : b.lm;
+      for (int m = 0; m < nfp; ++m) {
+        const int q = f * nfp + m;
+        for (int j = 0; j < n; ++j) {
+          const int i = R.line_point(k, m, j);
+          Mint[size_t(q) * nu + i] = l[j];
+          Mnint[size_t(q) * d * nu + k * nu + i] = sg * l[j];
+        }
+      }
+    }
+    for (int i = 0; i < nu; ++i) {
+      const auto c = R.upt_idx(i);
+      for (int k = 0; k < d; ++k) {
+        const int m = R.face_index(i, k), ik = c[k];
+        for (int j = 0; j < n; ++j) {
+          const int jj = R.line_point(k, m, j);
+          Mgrad[(size_t(k) * nu + i) * nu + jj] += b.D[ik * n + j];
+          Mdiv[size_t(i) * d * nu + k * nu + jj] += b.D[ik * n + j];
+        }
+        const int qp = (2 * k + 1) * nfp + m, qm = 2 * k * nfp + m;
+        Mgcorr[(size_t(k) * nu + i) * nf + qp] = b.gRd[ik];
+        Mgcorr[(size_t(k) * nu + i) * nf + qm] = b.gLd[ik];
+        Mcorr[size_t(i) * nf + qp] = b.gRd[ik];
+        Mcorr[size_t(i) * nf + qm] = -b.gLd[ik];
+      }
+    }
+    // strong-form divergence: the interpolated normal flux correction folded in
+    MdivS = Mdiv;
+    for (int i = 0; i < nu; ++i)
+      for (int q = 0; q < nf; ++q) {
+        const double c = Mcorr[size_t(i) * nf + q];
+        if (c == 0.0) continue;
+        for (int col = 0; col < d * nu; ++col) MdivS[size_t(i) * d * nu + col] -= c * Mnint[size_t(q) * d * nu + col];
+      }
+  }
+};
+
+// MFMA A-operand order: tile (rt, kt), lane l -> M[rt*16 + l%16][kt*4 + l/16]
+template <class Get>
+void swizzle(std::vector<double> &out, int rtiles, int ktiles, Get get) {
+  for (int rt = 0; rt < rtiles; ++rt)
+    for (int kt = 0; kt < ktiles; ++kt)
+      for (int l = 0; l < 64; ++l) out.push_back(get(rt * 16 + l % 16, kt * 4 + l / 16));
+}
+
+// ---------------------------------------------------------------------------
+// per-design host geometry and connectivity
+// ---------------------------------------------------------------------------
+struct HostMesh {
+  int dim, order, q;
+  int64_t E;
+  std::vector<double> S, detJ, xu;      // [E][nu][dim*dim], [E][nu], [E][nu][3]
+  std::vector<double> fn, fA, fx;       // [E][nf][dim], [E][nf], [E][nf][3]
+  std::vector<int64_t> nbr;             // [E][nf]: e'*nf + q' or -kind
+};
+
+void shape_q(int q, double t, double *N, double *dN) {
+  if (q == 1) {
+    N[0] = 0.5 * (1.0 - t); N[1] = 0.5 * (1.0 + t);
+    dN[0] = -0.5; dN[1] = 0.5;
+  } else {
+    N[0] = 0.5 * t * (t - 1.0); N[1] = 1.0 - t * t; N[2] = 0.5 * t * (t + 1.0);
+    dN[0] = t - 0.5; dN[1] = -2.0 * t; dN[2] = t + 0.5;
+  }
+}
+
+// x(r) and the columns a_k = dx/dr_k
+void geom_map(const fr_mesh_desc &d, int64_t e, const std::array<double, 3> &r, double x[3], double a[3][3]) {
+  const int dim = d.dim, q = d.geom_order, na = q + 1;
+  double N[3][3], dN[3][3];
+  for (int k = 0; k < dim; ++k) shape_q(q, r[k], N[k], dN[k]);
+  for (int i = 0; i < 3; ++i) {
+    x[i] = 0.0;
+    for (int k = 0; k < 3; ++k) a[k][i] = 0.0;
+  }
+  const int nn = dim == 2 ? na * na : na * na * na;
+  const int64_t *en = d.elem_nodes + e * nn;
+  for (int c2 = 0; c2 < (dim == 3 ? na : 1); ++c2)
+    for (int c1 = 0; c1 < na; ++c1)
+      for (int c0 = 0; c0 < na; ++c0) {
+        const int aidx = c0 + na * c1 + na * na * c2;
+        const double *X = d.nodes + en[aidx] * dim;
+        const int cc[3] = {c0, c1, c2};
+        double val = 1.0;
+        for (int k = 0; k < dim; ++k) val *= N[k][cc[k]];
+        for (int i = 0; i < dim; ++i) x[i] += val * X[i];
+        for (int k = 0; k < dim; ++k) {
+          double dv = 1.0;
+          for (int kk = 0; kk < dim; ++kk) dv *= (kk == k) ? dN[kk][cc[kk]] : N[kk][cc[kk]];
+          for (int i = 0; i < dim; ++i) a[k][i] += dv * X[i];
+        }
+      }
+}
+
+// S rows: S_k = a_{k+1} x a_{k+2} (3D) so that S = |J| J^-1; returns |J|
+double metric_rows(int dim, double a[3][3], double S[3][3]) {
+  if (dim == 2) {
+    S[0][0] = a[1][1]; S[0][1] = -a[1][0];
+    S[1][0] = -a[0][1]; S[1][1] = a[0][0];
+    return a[0][0] * a[1][1] - a[0][1] * a[1][0];
+  }
+  for (int k = 0; k < 3; ++k) {
+    const double *u = a[(k + 1) % 3], *v = a[(k + 2) % 3];
+    S[k][0] = u[1] * v[2] - u[2] * v[1];
+    S[k][1] = u[2] * v[0] - u[0] * v[2];
+    S[k][2] = u[0] * v[1] - u[1] * v[0];
+  }
+  return a[0][0] * S[0][0] + a[0][1] * S[0][1] + a[0][2] * S[0][2];
+}
+
+struct KeyHash {
+  size_t operator()(const std::array<int64_t, 4> &k) const {
+    size_t h = 1469598103934665603ull;
+    for (auto v : k) h = (h ^ size_t(v)) * 1099511628211ull;
+    return h;
+  }
+};
+
+HostMesh build_host_mesh(const fr_mesh_desc &d) {
+  const int dim = d.dim, order = d.order, q = d.geom_order;
+  RefElem R(dim, order);
+  Basis1D b(order);
+  HostMesh H;
+  H.dim = dim; H.order = order; H.q = q; H.E = d.n_elems;
+  const int64_t E = d.n_elems;
+  const int nu = R.nu, nf = R.nf, nfp = R.nfp, na = q + 1;
+  const int nn = dim == 2 ? na * na : na * na * na;
+  for (int64_t i = 0; i < E * nn; ++i)
+    if (d.elem_nodes[i] < 0 || d.elem_nodes[i] >= d.n_nodes) fail(FR_E_ARG, "element node id out of range");
+  H.S.resize(size_t(E) * nu * dim * dim);
+  H.detJ.resize(size_t(E) * nu);
+  H.xu.assign(size_t(E) * nu * 3, 0.0);
+  H.fn.resize(size_t(E) * nf * dim);
+  H.fA.resize(size_t(E) * nf);
+  H.fx.assign(size_t(E) * nf * 3, 0.0);
+  bool bad = false;
+  for (int64_t e = 0; e < E; ++e) {
+    for (int i = 0; i < nu; ++i) {
+      auto c = R.upt_idx(i);
+      std::array<double, 3> r{b.x[c[0]], b.x[c[1]], dim == 3 ? b.x[c[2]] : 0.0};
+      double x[3], a[3][3], S[3][3];
+      geom_map(d, e, r, x, a);
+      const double det = metric_rows(dim, a, S);
+      if (!(det > 0.0)) bad = true;
+      H.detJ[e * nu + i] = det;
+      for (int k = 0; k < dim; ++k)
+        for (int j = 0; j < dim; ++j) H.S[(size_t(e) * nu + i) * dim * dim + k * dim + j] = S[k][j];
+      for (int j = 0; j < dim; ++j) H.xu[(size_t(e) * nu + i) * 3 + j] = x[j];
+    }
+    for (int f = 0; f < 2 * dim; ++f)
+      for (int m = 0; m < nfp; ++m) {
+        const int qq = f * nfp + m, k = f / 2;
+        auto r = R.fpt_ref(b, f, m);
+        double x[3], a[3][3], S[3][3];
+        geom_map(d, e, r, x, a);
+        const double det = metric_rows(dim, a, S);
+        if (!(det > 0.0)) bad = true;
+        double nrm = 0.0;
+        for (int j = 0; j < dim; ++j) nrm += S[k][j] * S[k][j];
+        nrm = std::sqrt(nrm);
+        const double sg = (f & 1) ? 1.0 : -1.0;
+        H.fA[size_t(e) * nf + qq] = nrm;
+        for (int j = 0; j < dim; ++j) {
+          H.fn[(size_t(e) * nf + qq) * dim + j] = sg * S[k][j] / nrm;
+          H.fx[(size_t(e) * nf + qq) * 3 + j] = x[j];
+        }
+      }
+  }
+  if (bad) fail(FR_E_MESH, "non-positive Jacobian");
+
+  // ---- connectivity: faces by corner node ids, then by periodic translation
+  const int nfe = 2 * dim, nc = dim == 2 ? 2 : 4;
+  auto corner_local = [&](int f, int c) {
+    const int k = f / 2;
+    std::array<int, 3> a{0, 0, 0};
+    a[k] = (f & 1) * q;
+    auto ax = R.face_axes(k);
+    a[ax[0]] = (c & 1) * q;
+    if (dim == 3) a[ax[1]] = ((c >> 1) & 1) * q;
+    return a[0] + na * a[1] + na * na * a[2];
+  };
+  H.nbr.assign(size_t(E) * nf, INT64_MIN);
+  std::vector<char> done(size_t(E) * nfe, 0);
+  struct Pair { int64_t a, b; double shift[3]; };
+  std::vector<Pair> pairs;
+  {
+    std::unordered_map<std::array<int64_t, 4>, int64_t, KeyHash> seen;
+    seen.reserve(size_t(E) * nfe);
+    for (int64_t e = 0; e < E; ++e)
+      for (int f = 0; f < nfe; ++f) {
+        std::array<int64_t, 4> key{-1, -1, -1, -1};
+        for (int c = 0; c < nc; ++c) key[c] = d.elem_nodes[e * nn + corner_local(f, c)];
+        std::sort(key.begin(), key.begin() + nc);
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+          seen.emplace(key, e * nfe + f);
+        } else {
+          if (it->second < 0) fail(FR_E_MESH, "face shared by more than two elements");
+          pairs.push_back({it->second, e * nfe + f, {0, 0, 0}});
+          done[it->second] = done[e * nfe + f] = 1;
+          it->second = -1;
+        }
+      }
+  }
+  for (int64_t i = 0; i < d.n_bfaces; ++i) {
+    const int64_t e = d.bfaces[3 * i], f = d.bfaces[3 * i + 1], kind = d.bfaces[3 * i + 2];
+    if (e < 0 || e >= E || f < 0 || f >= nfe || (kind != FR_BC_WALL && kind != FR_BC_FARFIELD))
+      fail(FR_E_ARG, "invalid boundary face entry");
+    if (done[e * nfe + f]) fail(FR_E_MESH, "boundary face is also an interior face");
+    done[e * nfe + f] = 2;
+    for (int m = 0; m < nfp; ++m) H.nbr[size_t(e) * nf + f * nfp + m] = -kind;
+  }
+  // periodic: hash face centroids on a fine grid; look the translated centroid up
+  {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < d.n_nodes; ++i)
+      for (int k = 0; k < dim; ++k) {
+        lo[k] = std::min(lo[k], d.nodes[i * dim + k]);
+        hi[k] = std::max(hi[k], d.nodes[i * dim + k]);
+      }
+    double ext = 0.0;
+    for (int k = 0; k < dim; ++k) ext = std::max(ext, hi[k] - lo[k]);
+    const double tol = 1e-9 * ext, cell = 1e-6 * ext;
+    std::vector<int64_t> open;
+    for (int64_t fi = 0; fi < E * nfe; ++fi)
+      if (!done[fi]) open.push_back(fi);
+    auto centroid = [&](int64_t fi, double c[3]) {
+      const int64_t e = fi / nfe;
+      const int f = int(fi % nfe);
+      c[0] = c[1] = c[2] = 0.0;
+      for (int cc = 0; cc < nc; ++cc) {
+        const double *X = d.nodes + d.elem_nodes[e * nn + corner_local(f, cc)] * dim;
+        for (int k = 0; k < dim; ++k) c[k] += X[k] / nc;
+      }
+    };
+    std::map<std::array<int64_t, 3>, std::vector<int64_t>> grid;
+    auto cellkey = [&](const double c[3]) {
+      return std::array<int64_t, 3>{int64_t(std::floor(c[0] / cell)), int64_t(std::floor(c[1] / cell)),
+                                    int64_t(std::floor(c[2] / cell))};
+    };
+    for (auto fi : open) {
+      double c[3];
+      centroid(fi, c);
+      grid[cellkey(c)].push_back(fi);
+    }
+    for (auto fi : open) {
+      if (done[fi]) continue;
+      double c[3];
+      centroid(fi, c);
+      bool found = false;
+      for (int p = 0; p < d.n_periodic && !found; ++p)
+        for (int sg = -1; sg <= 1 && !found; sg += 2) {
+          double t[3] = {0, 0, 0}, ct[3];
+          for (int k = 0; k < dim; ++k) t[k] = sg * d.periodic_shift[p * dim + k];
+          for (int k = 0; k < 3; ++k) ct[k] = c[k] + t[k];
+          auto base = cellkey(ct);
+          for (int dz = -1; dz <= 1 && !found; ++dz)
+            for (int dy = -1; dy <= 1 && !found; ++dy)
+              for (int dx = -1; dx <= 1 && !found; ++dx) {
+                auto it = grid.find({base[0] + dx, base[1] + dy, base[2] + dz});
+                if (it == grid.end()) continue;
+                for (auto fj : it->second) {
+                  if (fj == fi || done[fj]) continue;
+                  double c2[3];
+                  centroid(fj, c2);
+                  bool same = true;
+                  for (int k = 0; k < dim; ++k)
+                    if (std::fabs(c2[k] - ct[k]) > tol) same = false;
+                  if (!same) continue;
+                  pairs.push_back({fi, fj, {t[0], t[1], t[2]}});
+                  done[fi] = done[fj] = 1;
+                  found = true;
+                  break;
+                }
+              }
+        }
+      if (!found) fail(FR_E_MESH, "face is neither matched, periodic nor a listed boundary");
+    }
+  }
+  // flux points of a matched face pair: nearest partner point by position
+  for (const auto &P : pairs) {
+    const int64_t eA = P.a / nfe, eB = P.b / nfe;
+    const int fA = int(P.a % nfe), fB = int(P.b % nfe);
+    double hA = 0.0;
+    for (int m = 0; m < nfp; ++m)
+      for (int k = 0; k < dim; ++k)
+        hA = std::max(hA, std::fabs(H.fx[(size_t(eA) * nf + fA * nfp + m) * 3 + k] -
+                                    H.fx[(size_t(eA) * nf + fA * nfp) * 3 + k]));
+    const double ptol = 1e-7 * std::max(hA, 1e-300);
+    for (int m = 0; m < nfp; ++m) {
+      const double *xa = &H.fx[(size_t(eA) * nf + fA * nfp + m) * 3];
+      int best = -1;
+      double bd = 1e300;
+      for (int m2 = 0; m2 < nfp; ++m2) {
+        const double *xb = &H.fx[(size_t(eB) * nf + fB * nfp + m2) * 3];
+        double dd = 0.0;
+        for (int k = 0; k < dim; ++k) dd = std::max(dd, std::fabs(xa[k] + P.shift[k] - xb[k]));
+        if (dd < bd) { bd = dd; best = m2; }
+      }
+      if (bd > ptol) fail(FR_E_MESH, "flux points of a matched face do not coincide");
+      const int64_t ga = eA * nf + fA * nfp + m, gb = eB * nf + fB * nfp + best;
+      if (H.nbr[ga] != INT64_MIN || H.nbr[gb] != INT64_MIN) fail(FR_E_MESH, "flux point matched twice");
+      H.nbr[ga] = gb;
+      H.nbr[gb] = ga;
+    }
+  }
+  for (auto v : H.nbr)
+    if (v == INT64_MIN) fail(FR_E_MESH, "unmatched flux point");
+  return H;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the solver handle
+// ---------------------------------------------------------------------------
+struct DesignInfo {
+  int64_t e0 = 0, E = 0, blk0 = 0, nblk = 0, wall0 = 0, nwall = 0;
+  double dt = 0, fs[5] = {0, 0, 0, 0, 0}, ref_area = 1, lift[3] = {0, 0, 0}, drag[3] = {0, 0, 0};
+};
+
+struct fr_mesh {
+  int dim = 3, order = 3, prec = 0, device = 0;
+  Dims dm{3, 3};
+  int64_t E = 0, nblk = 0, nwall = 0;
+  std::vector<DesignInfo> designs;
+  std::vector<int64_t> nbr_canon;   // [E][nf]
+  std::vector<double> xu;           // [E][nu][3]
+  double gamma = 1.4, prandtl = 0.72, mu = 0.0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  fr_alloc_fn alloc = nullptr;
+  fr_free_fn dfree = nullptr;
+  void *alloc_ctx = nullptr;
+  std::vector<void *> allocations;
+  size_t bytes = 0;
+  DevArrays a;
+  LaunchCfg cfg;
+  bool state_set = false;
+  hipGraphExec_t graph_first = nullptr, graph_rest = nullptr;
+
+  size_t real_size() const { return prec == FR_FP32 ? 4 : 8; }
+
+  void *dalloc(size_t n) {
+    if (n == 0) n = 256;
+    void *p = nullptr;
+    if (alloc) {
+      p = alloc(n, alloc_ctx, stream);
+      if (!p) fail(FR_E_NOMEM, "device allocation callback failed");
+    } else {
+      if (hipMalloc(&p, n) != hipSuccess) fail(FR_E_NOMEM, "hipMalloc failed");
+    }
+    allocations.push_back(p);
+    bytes += n;
+    if (hipMemsetAsync(p, 0, n, stream) != hipSuccess) fail(FR_E_DEVICE, "hipMemsetAsync failed");
+    return p;
+  }
+  template <class T> T *upload(const std::vector<T> &v) {
+    T *p = (T *)dalloc(v.size() * sizeof(T));
+    hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, stream), "upload");
+    return p;
+  }
+  ~fr_mesh() {
+    if (graph_first) hipGraphExecDestroy(graph_first);
+    if (graph_rest) hipGraphExecDestroy(graph_rest);
+    if (stream) hipStreamSynchronize(stream);
+    for (void *p : allocations) {
+      if (dfree)
+        dfree(p, alloc_ctx, stream);
+      else
+        hipFree(p);
+    }
+    if (own_stream && stream) hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+void validate_desc(const fr_mesh_desc *d) {
+  if (!d) fail(FR_E_ARG, "null descriptor");
+  if (d->dim != 2 && d->dim != 3) fail(FR_E_ARG, "dim must be 2 or 3");
+  if (d->geom_order != 1 && d->geom_order != 2) fail(FR_E_ARG, "geom_order must be 1 or 2");
+  if (d->precision != FR_FP64 && d->precision != FR_FP32) fail(FR_E_ARG, "unknown precision");
+  if (!kernels_available(d->precision, d->dim, d->order)) fail(FR_E_UNSUPPORTED, "order not compiled in (1..4)");
+  if (d->n_elems <= 0 || !d->elem_nodes || d->n_nodes <= 0 || !d->nodes) fail(FR_E_ARG, "empty mesh");
+  if (d->n_periodic < 0 || (d->n_periodic > 0 && !d->periodic_shift)) fail(FR_E_ARG, "bad periodic list");
+  if (d->n_bfaces < 0 || (d->n_bfaces > 0 && !d->bfaces)) fail(FR_E_ARG, "bad boundary list");
+  if (!(d->gamma > 1.0) || !(d->prandtl > 0.0) || !(d->mu >= 0.0)) fail(FR_E_ARG, "bad gas constants");
+  if (!(d->dt > 0.0) || !std::isfinite(d->dt)) fail(FR_E_ARG, "dt must be positive");
+}
+
+void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
+  const fr_mesh_desc &d0 = descs[0];
+  M->dim = d0.dim;
+  M->order = d0.order;
+  M->prec = d0.precision;
+  M->device = d0.device;
+  M->dm = Dims(d0.dim, d0.order);
+  M->gamma = d0.gamma;
+  M->prandtl = d0.prandtl;
+  M->mu = d0.mu;
+  M->alloc = d0.alloc;
+  M->dfree = d0.free;
+  M->alloc_ctx = d0.alloc_ctx;
+  hip_check(hipSetDevice(d0.device), "hipSetDevice");
+  if (d0.stream) {
+    M->stream = (hipStream_t)d0.stream;
+  } else {
+    hip_check(hipStreamCreateWithFlags(&M->stream, hipStreamNonBlocking), "hipStreamCreate");
+    M->own_stream = true;
+  }
+  const Dims &D = M->dm;
+  const int dim = M->dim, nu = D.nu, nf = D.nf, nv = D.nv, NUP = D.nup, NFPAD = D.nfpad;
+  // per-design host meshes
+  std::vector<HostMesh> hm;
+  hm.reserve(nd);
+  int64_t e0 = 0, blk0 = 0, w0 = 0;
+  for (int i = 0; i < nd; ++i) {
+    hm.push_back(build_host_mesh(descs[i]));
+    DesignInfo di;
+    di.e0 = e0;
+    di.E = descs[i].n_elems;
+    di.blk0 = blk0;
+    di.nblk = (di.E + EB - 1) / EB;
+    di.dt = descs[i].dt;
+    for (int k = 0; k < 5; ++k) di.fs[k] = descs[i].freestream[k];
+    di.ref_area = descs[i].ref_area;
+    for (int k = 0; k < 3; ++k) {
+      di.lift[k] = descs[i].lift_dir[k];
+      di.drag[k] = descs[i].drag_dir[k];
+    }
+    di.wall0 = w0;
+    for (auto v : hm.back().nbr)
+      if (v == -FR_BC_WALL) ++di.nwall;
+    w0 += di.nwall;
+    e0 += di.E;
+    blk0 += di.nblk;
+    M->designs.push_back(di);
+  }
+  M->E = e0;
+  M->nblk = blk0;
+  M->nwall = w0;
+  const int64_t NB = M->nblk;
+  // canonical neighbour table and solution points (concatenated)
+  M->nbr_canon.resize(size_t(M->E) * nf);
+  M->xu.resize(size_t(M->E) * nu * 3);
+  // block-layout geometry and tables
+  std::vector<double> SM(size_t(NB) * NUP * dim * dim * EB, 0.0), IJ(size_t(NB) * NUP * EB, 0.0);
+  std::vector<double> FN(size_t(NB) * NFPAD * dim * EB, 0.0), FA(size_t(NB) * NFPAD * EB, 0.0);
+  std::vector<int> NBt(size_t(NB) * NFPAD * EB, 0);
+  std::vector<int> bcount(NB), bdesign(NB);
+  std::vector<int64_t> bcanon(NB), wall_first(nd + 1);
+  std::vector<double> bdt(NB), fsd(size_t(nd) * 5);
+  auto dev_slot = [&](int64_t g) {  // canonical element -> (block, slot)
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (M->designs[mid].e0 <= g) lo = mid; else hi = mid - 1;
+    }
+    const auto &di = M->designs[lo];
+    const int64_t le = g - di.e0;
+    return std::pair<int64_t, int>(di.blk0 + le / EB, int(le % EB));
+  };
+  if (int64_t(NB) * NFPAD * EB >= (int64_t(1) << 31)) fail(FR_E_UNSUPPORTED, "mesh too large for 32-bit tables");
+  for (int di = 0; di < nd; ++di) {
+    const auto &H = hm[di];
+    const auto &ds = M->designs[di];
+    wall_first[di] = ds.wall0;
+    for (int k = 0; k < 5; ++k) fsd[di * 5 + k] = ds.fs[k];
+    for (int64_t b = 0; b < ds.nblk; ++b) {
+      const int64_t blk = ds.blk0 + b;
+      bcount[blk] = int(std::min<int64_t>(EB, ds.E - b * EB));
+      bdesign[blk] = di;
+      bcanon[blk] = ds.e0 + b * EB;
+      bdt[blk] = ds.dt;
+    }
+    int64_t widx = ds.wall0;
+    for (int64_t e = 0; e < ds.E; ++e) {
+      const int64_t g = ds.e0 + e;
+      const int64_t blk = ds.blk0 + e / EB;
+      const int s = int(e % EB);
+      for (int i = 0; i < nu; ++i) {
+        for (int c = 0; c < dim * dim; ++c)
+          SM[((size_t(blk) * NUP + i) * dim * dim + c) * EB + s] = H.S[(size_t(e) * nu + i) * dim * dim + c];
+        IJ[(size_t(blk) * NUP + i) * EB + s] = 1.0 / H.detJ[size_t(e) * nu + i];
+        for (int c = 0; c < 3; ++c) M->xu[(size_t(g) * nu + i) * 3 + c] = H.xu[(size_t(e) * nu + i) * 3 + c];
+      }
+      for (int qq = 0; qq < nf; ++qq) {
+        const size_t hq = size_t(e) * nf + qq;
+        for (int c = 0; c < dim; ++c) FN[((size_t(blk) * NFPAD + qq) * dim + c) * EB + s] = H.fn[hq * dim + c];
+        FA[(size_t(blk) * NFPAD + qq) * EB + s] = H.fA[hq];
+        const int64_t p = H.nbr[hq];
+        int code;
+        if (p >= 0) {
+          const int64_t gp = ds.e0 + p / nf;
+          const int qp = int(p % nf);
+          auto bs = dev_slot(gp);
+          code = int((bs.first * NFPAD + qp) * EB + bs.second);
+          M->nbr_canon[size_t(g) * nf + qq] = gp * nf + qp;
+        } else {
+          const int kind = int(-p);
+          code = kind == FR_BC_WALL ? -int(kind | (widx++ << 2)) : -kind;
+          M->nbr_canon[size_t(g) * nf + qq] = p;
+        }
+        NBt[(size_t(blk) * NFPAD + qq) * EB + s] = code;
+      }
+    }
+  }
+  wall_first[nd] = M->nwall;
+  // operators
+  Operators op(dim, M->order);
+  const int RTU = NUP / 16, RTF = NFPAD / 16, KTU = D.ku / 4, KTF = D.kf / 4;
+  std::vector<double> sInt, sGrad, sGcorr, sDivS, sCorr;
+  swizzle(sInt, RTF, KTU, [&](int r, int c) { return (r < nf && c < nu) ? op.Mint[size_t(r) * nu + c] : 0.0; });
+  for (int k = 0; k < dim; ++k) {
+    swizzle(sGrad, RTU, KTU, [&](int r, int c) {
+      return (r < nu && c < nu) ? op.Mgrad[(size_t(k) * nu + r) * nu + c] : 0.0;
+    });
+    swizzle(sGcorr, RTU, KTF, [&](int r, int c) {
+      return (r < nu && c < nf) ? op.Mgcorr[(size_t(k) * nu + r) * nf + c] : 0.0;
+    });
+  }
+  for (int rt = 0; rt < RTU; ++rt)
+    for (int k = 0; k < dim; ++k)
+      for (int kt = 0; kt < KTU; ++kt)
+        for (int l = 0; l < 64; ++l) {
+          const int r = rt * 16 + l % 16, c = kt * 4 + l / 16;
+          sDivS.push_back((r < nu && c < nu) ? op.MdivS[size_t(r) * dim * nu + k * nu + c] : 0.0);
+        }
+  swizzle(sCorr, RTU, KTF, [&](int r, int c) { return (r < nu && c < nf) ? op.Mcorr[size_t(r) * nf + c] : 0.0; });
+  auto upload_real = [&](const std::vector<double> &v) -> void * {
+    if (M->prec == FR_FP64) return M->upload(v);
+    std::vector<float> f(v.begin(), v.end());
+    return M->upload(f);
+  };
+  DevArrays &a = M->a;
+  a.opInt = upload_real(sInt);
+  a.opGrad = upload_real(sGrad);
+  a.opGcorr = upload_real(sGcorr);
+  a.opDivS = upload_real(sDivS);
+  a.opCorr = upload_real(sCorr);
+  a.SM = M->upload(SM);
+  a.IJ = M->upload(IJ);
+  a.FN = M->upload(FN);
+  a.FA = M->upload(FA);
+  a.NB = M->upload(NBt);
+  a.bcount = M->upload(bcount);
+  a.bdesign = M->upload(bdesign);
+  a.bcanon = M->upload(bcanon);
+  a.bdt = M->upload(bdt);
+  a.fsd = M->upload(fsd);
+  a.wall_first = M->upload(wall_first);
+  {
+    Basis1D b(M->order);
+    RefElem R(dim, M->order);
+    std::vector<double> wf(NFPAD, 0.0);
+    for (int f = 0; f < 2 * dim; ++f)
+      for (int m = 0; m < R.nfp; ++m) wf[f * R.nfp + m] = dim == 2 ? b.w[m] : b.w[m % R.n] * b.w[m / R.n];
+    a.wface = M->upload(wf);
+  }
+  const size_t rs = M->real_size();
+  const size_t nU = size_t(NB) * NUP * nv * EB, nF = size_t(NB) * NFPAD * nv * EB, nG = size_t(NB) * NUP * dim * nv * EB;
+  a.U = M->dalloc(nU * rs);
+  a.US = M->dalloc(nU * rs);
+  a.ACC = M->dalloc(nU * rs);
+  a.RES = M->dalloc(nU * rs);
+  a.UF = M->dalloc(nF * rs);
+  a.DU = M->dalloc(nF * rs);
+  a.FI = M->dalloc(nF * rs);
+  a.PV = M->dalloc(nF * rs);
+  a.GU = M->dalloc(nG * rs);
+  a.FT = M->dalloc(nG * rs);
+  a.FC = (double *)M->dalloc(std::max<int64_t>(M->nwall, 1) * 3 * sizeof(double));
+  a.fsum = (double *)M->dalloc(size_t(nd) * 8 * sizeof(double));
+  a.flag = (int *)M->dalloc(sizeof(int));
+  a.stage64 = (double *)M->dalloc(size_t(M->E) * nu * nv * sizeof(double));
+  LaunchCfg &c = M->cfg;
+  c.prec = M->prec;
+  c.dim = dim;
+  c.order = M->order;
+  c.nblk = NB;
+  c.ndesign = nd;
+  c.n_canon = M->E;
+  c.gamma = M->gamma;
+  c.mu = M->mu;
+  c.prandtl = M->prandtl;
+  c.stream = M->stream;
+  hip_check(hipStreamSynchronize(M->stream), "mesh upload");
+}
+
+void lk(fr_mesh *M, int kernel, int stage, int mode, bool forces) {
+  hip_check(launch_kernel(kernel, M->cfg, M->a, stage, mode, forces), "kernel launch");
+}
+
+// one RK4 step; force terms of the step's input state are reduced if `forces`
+void enqueue_step(fr_mesh *M, bool forces) {
+  for (int s = 0; s < 4; ++s) {
+    const bool f = forces && s == 0 && M->nwall > 0;
+    lk(M, K_FACE, s, 0, false);
+    lk(M, K_GRAD, s, 0, false);
+    lk(M, K_VISC, s, 0, f);
+    if (f) hip_check(launch_force_reduce(M->cfg, M->a), "force reduce");
+    lk(M, K_DIVRK, s, s, false);
+    // trace of the next stage input: US for stages 1..3, U after the update
+    lk(M, K_INTERP, s < 3 ? 1 : 0, 0, false);
+  }
+}
+
+hipGraphExec_t capture_step(fr_mesh *M, bool forces) {
+  hipGraph_t g = nullptr;
+  hip_check(hipStreamBeginCapture(M->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  try {
+    enqueue_step(M, forces);
+  } catch (...) {
+    hipStreamEndCapture(M->stream, &g);
+    if (g) hipGraphDestroy(g);
+    throw;
+  }
+  hip_check(hipStreamEndCapture(M->stream, &g), "end capture");
+  hipGraphExec_t ex = nullptr;
+  hip_check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate");
+  hipGraphDestroy(g);
+  return ex;
+}
+
+void step_async(fr_mesh *M, int64_t n) {
+  if (!M->state_set) fail(FR_E_STATE, "no state set");
+  if (n < 0) fail(FR_E_ARG, "negative step count");
+  if (n == 0) return;
+  hip_check(hipSetDevice(M->device), "hipSetDevice");
+  if (!M->graph_first) M->graph_first = capture_step(M, false);
+  if (!M->graph_rest) M->graph_rest = capture_step(M, true);
+  hip_check(launch_clear_flag(M->cfg, M->a), "clear flag");
+  lk(M, K_INTERP, 0, 0, false);
+  for (int64_t s = 0; s < n; ++s)
+    hip_check(hipGraphLaunch(s == 0 ? M->graph_first : M->graph_rest, M->stream), "graph launch");
+  if (M->nwall > 0) {  // wall force of the final state
+    lk(M, K_FACE, 0, 0, false);
+    lk(M, K_GRAD, 0, 0, false);
+    lk(M, K_VISC, 0, 0, true);
+    hip_check(launch_force_reduce(M->cfg, M->a), "force reduce");
+  }
+}
+
+void sync_check(fr_mesh *M) {
+  int flag = 0;
+  hip_check(hipMemcpyAsync(&flag, M->a.flag, sizeof(int), hipMemcpyDeviceToHost, M->stream), "flag copy");
+  hip_check(hipStreamSynchronize(M->stream), "stream sync");
+  if (flag) fail(FR_E_NONFINITE, "non-finite state after a step");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *fr_last_error(void) { return g_err.c_str(); }
+
+fr_status fr_batch_create(const fr_mesh_desc *descs, int32_t n, fr_mesh **out) {
+  return guarded([&] {
+    if (!out) fail(FR_E_ARG, "null output");
+    *out = nullptr;
+    if (!descs || n <= 0) fail(FR_E_ARG, "no descriptors");
+    for (int i = 0; i < n; ++i) {
+      validate_desc(&descs[i]);
+      const auto &a = descs[0], &b = descs[i];
+      if (a.dim != b.dim || a.order != b.order || a.precision != b.precision || a.gamma != b.gamma ||
+          a.prandtl != b.prandtl || a.mu != b.mu || a.device != b.device || a.stream != b.stream)
+        fail(FR_E_ARG, "batched designs must share dim, order, precision, gas constants, device and stream");
+    }
+    std::unique_ptr<fr_mesh> M(new fr_mesh());
+    build_solver(M.get(), descs, n);
+    *out = M.release();
+  });
+}
+
+fr_status fr_mesh_create(const fr_mesh_desc *desc, fr_mesh **out) { return fr_batch_create(desc, 1, out); }
+
+void fr_mesh_destroy(fr_mesh *m) { delete m; }
+
+fr_status fr_mesh_info(const fr_mesh *m, int64_t *info) {
+  return guarded([&] {
+    if (!m || !info) fail(FR_E_ARG, "null argument");
+    info[0] = m->dim; info[1] = m->order; info[2] = int64_t(m->designs.size()); info[3] = m->E;
+    info[4] = m->dm.nu; info[5] = m->dm.nf; info[6] = m->dm.nv; info[7] = m->prec; info[8] = m->nblk;
+    info[9] = int64_t(m->bytes);
+  });
+}
+
+fr_status fr_design_range(const fr_mesh *m, int32_t design, int64_t *first, int64_t *count) {
+  return guarded([&] {
+    if (!m || !first || !count || design < 0 || design >= int(m->designs.size())) fail(FR_E_ARG, "bad design");
+    *first = m->designs[design].e0;
+    *count = m->designs[design].E;
+  });
+}
+
+fr_status fr_solution_points(const fr_mesh *m, double *xyz) {
+  return guarded([&] {
+    if (!m || !xyz) fail(FR_E_ARG, "null argument");
+    std::memcpy(xyz, m->xu.data(), m->xu.size() * sizeof(double));
+  });
+}
+
+fr_status fr_neighbours(const fr_mesh *m, int64_t *nbr) {
+  return guarded([&] {
+    if (!m || !nbr) fail(FR_E_ARG, "null argument");
+    std::memcpy(nbr, m->nbr_canon.data(), m->nbr_canon.size() * sizeof(int64_t));
+  });
+}
+
+fr_status fr_connectivity(const fr_mesh_desc *desc, int64_t *nbr, double *xyz) {
+  return guarded([&] {
+    if (!nbr) fail(FR_E_ARG, "null argument");
+    validate_desc(desc);
+    HostMesh H = build_host_mesh(*desc);
+    std::memcpy(nbr, H.nbr.data(), H.nbr.size() * sizeof(int64_t));
+    if (xyz) std::memcpy(xyz, H.xu.data(), H.xu.size() * sizeof(double));
+  });
+}
+
+fr_status fr_set_state(fr_mesh *m, const double *u) {
+  return guarded([&] {
+    if (!m || !u) fail(FR_E_ARG, "null argument");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    const size_t n = size_t(m->E) * m->dm.nu * m->dm.nv;
+    hip_check(hipMemcpyAsync(m->a.stage64, u, n * sizeof(double), hipMemcpyHostToDevice, m->stream), "state upload");
+    hip_check(launch_pack(m->cfg, m->a, true, m->a.U), "pack");
+    hip_check(hipMemsetAsync(m->a.fsum, 0, m->designs.size() * 8 * sizeof(double), m->stream), "clear sums");
+    hip_check(hipStreamSynchronize(m->stream), "set state");
+    m->state_set = true;
+  });
+}
+
+fr_status fr_get_state(const fr_mesh *m, double *u) {
+  return guarded([&] {
+    if (!m || !u) fail(FR_E_ARG, "null argument");
+    if (!m->state_set) fail(FR_E_STATE, "no state set");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    const size_t n = size_t(m->E) * m->dm.nu * m->dm.nv;
+    hip_check(launch_pack(m->cfg, m->a, false, m->a.U), "unpack");
+    hip_check(hipMemcpyAsync(u, m->a.stage64, n * sizeof(double), hipMemcpyDeviceToHost, m->stream), "state download");
+    hip_check(hipStreamSynchronize(m->stream), "get state");
+  });
+}
+
+fr_status fr_step_async(fr_mesh *m, int64_t n) {
+  return guarded([&] {
+    if (!m) fail(FR_E_ARG, "null mesh");
+    step_async(m, n);
+  });
+}
+
+fr_status fr_sync(fr_mesh *m) {
+  return guarded([&] {
+    if (!m) fail(FR_E_ARG, "null mesh");
+    sync_check(m);
+  });
+}
+
+fr_status fr_step(fr_mesh *m, int64_t n) {
+  return guarded([&] {
+    if (!m) fail(FR_E_ARG, "null mesh");
+    step_async(m, n);
+    sync_check(m);
+  });
+}
+
+fr_status fr_forces(const fr_mesh *m, int32_t design, double *out) {
+  return guarded([&] {
+    if (!m || !out || design < 0 || design >= int(m->designs.size())) fail(FR_E_ARG, "bad argument");
+    double s[8];
+    hip_check(hipMemcpyAsync(s, m->a.fsum + 8 * design, sizeof(s), hipMemcpyDeviceToHost, m->stream), "forces");
+    hip_check(hipStreamSynchronize(m->stream), "forces");
+    const auto &d = m->designs[design];
+    double U2 = 0.0;
+    for (int k = 1; k <= 3; ++k) U2 += d.fs[k] * d.fs[k];
+    const double qref = 0.5 * d.fs[0] * U2 * d.ref_area;
+    auto proj = [&](const double *F, const double *dir) {
+      return (F[0] * dir[0] + F[1] * dir[1] + F[2] * dir[2]) / qref;
+    };
+    const double cnt = s[3];
+    out[0] = proj(s + 4, d.lift);
+    out[1] = proj(s + 4, d.drag);
+    out[2] = s[4]; out[3] = s[5]; out[4] = s[6];
+    double mean[3] = {0, 0, 0};
+    if (cnt > 0)
+      for (int k = 0; k < 3; ++k) mean[k] = s[k] / cnt;
+    out[5] = cnt > 0 ? proj(mean, d.lift) : 0.0;
+    out[6] = cnt > 0 ? proj(mean, d.drag) : 0.0;
+    out[7] = cnt;
+  });
+}
+
+fr_status fr_residual(fr_mesh *m, const double *u, double *r) {
+  return guarded([&] {
+    if (!m || !u || !r) fail(FR_E_ARG, "null argument");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    const size_t n = size_t(m->E) * m->dm.nu * m->dm.nv;
+    hip_check(hipMemcpyAsync(m->a.stage64, u, n * sizeof(double), hipMemcpyHostToDevice, m->stream), "upload");
+    hip_check(launch_pack(m->cfg, m->a, true, m->a.US), "pack");
+    lk(m, K_INTERP, 1, 0, false);
+    lk(m, K_FACE, 1, 0, false);
+    lk(m, K_GRAD, 1, 0, false);
+    lk(m, K_VISC, 1, 0, false);
+    lk(m, K_DIVRK, 1, MODE_RESID, false);
+    hip_check(launch_pack(m->cfg, m->a, false, m->a.RES), "unpack");
+    hip_check(hipMemcpyAsync(r, m->a.stage64, n * sizeof(double), hipMemcpyDeviceToHost, m->stream), "download");
+    hip_check(hipStreamSynchronize(m->stream), "residual");
+  });
+}
+
+fr_status fr_state_device(const fr_mesh *m, void **ptr, int64_t *bytes) {
+  return guarded([&] {
+    if (!m || !ptr || !bytes) fail(FR_E_ARG, "null argument");
+    *ptr = m->a.U;
+    *bytes = int64_t(m->nblk) * m->dm.nup * m->dm.nv * EB * int64_t(m->real_size());
+  });
+}
+
+fr_status fr_profile_kernels(fr_mesh *m, int64_t steps, double *ms, int64_t *launches) {
+  return guarded([&] {
+    if (!m || !ms || !launches || steps <= 0) fail(FR_E_ARG, "bad argument");
+    if (!m->state_set) fail(FR_E_STATE, "no state set");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    for (int k = 0; k < 6; ++k) { ms[k] = 0.0; launches[k] = 0; }
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kid;
+    auto timed = [&](int kernel, int stage, int mode, bool forces) {
+      hipEvent_t a, b;
+      hip_check(hipEventCreate(&a), "event");
+      hip_check(hipEventCreate(&b), "event");
+      hip_check(hipEventRecord(a, m->stream), "event");
+      lk(m, kernel, stage, mode, forces);
+      hip_check(hipEventRecord(b, m->stream), "event");
+      ev.push_back(a);
+      ev.push_back(b);
+      kid.push_back(kernel);
+    };
+    hip_check(launch_clear_flag(m->cfg, m->a), "clear flag");
+    lk(m, K_INTERP, 0, 0, false);
+    for (int64_t s = 0; s < steps; ++s)
+      for (int st = 0; st < 4; ++st) {
+        timed(K_FACE, st, 0, false);
+        timed(K_GRAD, st, 0, false);
+        timed(K_VISC, st, 0, false);
+        timed(K_DIVRK, st, st, false);
+        timed(K_INTERP, st < 3 ? 1 : 0, 0, false);
+      }
+    sync_check(m);
+    for (size_t i = 0; i < kid.size(); ++i) {
+      float t = 0.f;
+      hip_check(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]), "elapsed");
+      ms[kid[i]] += t;
+      ms[0] += t;
+      launches[kid[i]] += 1;
+      launches[0] += 1;
+    }
+    for (auto e : ev) hipEventDestroy(e);
+  });
+}
+
+}  // extern "C"

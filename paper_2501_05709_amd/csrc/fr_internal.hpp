@@ -1,0 +1,87 @@
+// Internal interface between the host library (fr_host.cpp) and the gfx950
+// kernels (fr_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fr {
+
+constexpr int EB = 16;  // elements per block: the N extent of one MFMA tile
+
+// Packed boundary code stored in the neighbour table: -(kind | index << 2),
+// index = position of a wall flux point in the compact wall list.
+constexpr int BC_WALL = 1;
+constexpr int BC_FARFIELD = 2;
+
+enum Kernel {
+  K_FACE = 1,    // common solution and Rusanov flux at every flux point
+  K_GRAD = 2,    // corrected gradient, physical gradient, transformed flux
+  K_VISC = 3,    // gradient trace, viscous normal flux (and wall force terms)
+  K_DIVRK = 4,   // corrected divergence, residual, fused RK4 stage update
+  K_INTERP = 5,  // solution trace at flux points
+};
+
+// Modes of K_DIVRK
+enum { MODE_RK0 = 0, MODE_RK1 = 1, MODE_RK2 = 2, MODE_RK3 = 3, MODE_RESID = 4 };
+
+struct DevArrays {
+  // state and stage arrays, element type = real of the form (float or double)
+  void *U = nullptr, *US = nullptr, *ACC = nullptr, *UF = nullptr, *DU = nullptr, *FI = nullptr;
+  void *GU = nullptr, *FT = nullptr, *PV = nullptr, *RES = nullptr;
+  // operators (real), swizzled into MFMA A-operand order
+  void *opInt = nullptr, *opGrad = nullptr, *opGcorr = nullptr, *opDivS = nullptr, *opCorr = nullptr;
+  // FP64 geometry
+  double *SM = nullptr;  // [blk][NUP][dim*dim][EB]  S = |J| J^-1
+  double *IJ = nullptr;  // [blk][NUP][EB]          1/|J|
+  double *FN = nullptr;  // [blk][NFPAD][dim][EB]   outward unit normal
+  double *FA = nullptr;  // [blk][NFPAD][EB]        |S^T n_hat|
+  int *NB = nullptr;     // [blk][NFPAD][EB]        partner (blk*NFPAD+q)*EB+slot, or boundary code
+  int *bcount = nullptr;   // [blk] valid elements in the block
+  int *bdesign = nullptr;  // [blk]
+  int64_t *bcanon = nullptr;  // [blk] canonical element index of slot 0
+  double *bdt = nullptr;   // [blk]
+  double *fsd = nullptr;   // [design][5] free stream
+  double *wface = nullptr; // [NFPAD] face quadrature weight per flux point
+  double *FC = nullptr;    // [n_wall][3] wall force contributions
+  int64_t *wall_first = nullptr;  // [design + 1] compact wall ranges
+  double *fsum = nullptr;  // [design][8]: sum Fx,Fy,Fz, count, last Fx,Fy,Fz, spare
+  int *flag = nullptr;     // non-finite flag
+  double *stage64 = nullptr;  // canonical FP64 staging [E][nu][nv]
+};
+
+struct LaunchCfg {
+  int prec = 0, dim = 3, order = 3;
+  int64_t nblk = 0;
+  int ndesign = 1;
+  int64_t n_canon = 0;  // canonical elements
+  double gamma = 1.4, mu = 0.0, prandtl = 0.72;
+  hipStream_t stream = nullptr;
+};
+
+// Shape constants for a (dim, order) pair
+struct Dims {
+  int n, nu, nfp, nf, nv, nup, nfpad, ku, kf;
+  Dims(int dim, int order) {
+    n = order + 1;
+    nu = dim == 2 ? n * n : n * n * n;
+    nfp = dim == 2 ? n : n * n;
+    nf = 2 * dim * nfp;
+    nv = dim + 2;
+    nup = (nu + 15) / 16 * 16;
+    nfpad = (nf + 15) / 16 * 16;
+    ku = (nu + 3) / 4 * 4;
+    kf = (nf + 3) / 4 * 4;
+  }
+};
+
+// Launchers (fr_kernels.hip).  Return hipSuccess or the launch error.
+bool kernels_available(int prec, int dim, int order);
+hipError_t launch_kernel(int kernel, const LaunchCfg &c, const DevArrays &a, int stage, int mode,
+                         bool forces);
+hipError_t launch_pack(const LaunchCfg &c, const DevArrays &a, bool to_device_layout, void *dst_res);
+hipError_t launch_force_reduce(const LaunchCfg &c, const DevArrays &a);
+hipError_t launch_clear_flag(const LaunchCfg &c, const DevArrays &a);
+
+}  // namespace fr

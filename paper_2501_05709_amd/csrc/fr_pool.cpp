@@ -1,0 +1,205 @@
+// Served requests: a pool of independent solves that share one GPU.
+//
+// Each admitted request is its own solver handle on one of a few HIP
+// streams (all at the default priority), so requests that arrive while
+// others run are admitted as soon as their device footprint fits in the
+// budget, and their kernels overlap on the device.  A tick enqueues up to k
+// steps for every running request, then waits; finished requests keep their
+// results until collected.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fr.h"
+#include "fr_internal.hpp"
+
+namespace {
+thread_local std::string g_pool_err;
+}
+
+extern "C" const char *fr_last_error(void);
+
+struct fr_pool {
+  size_t budget = 0, used = 0;
+  int device = 0;
+  std::vector<hipStream_t> streams;
+  struct Req {
+    fr_mesh *m = nullptr;
+    int64_t left = 0, total = 0;
+    size_t bytes = 0;
+    bool done = false;
+    fr_status status = FR_OK;
+  };
+  std::map<int64_t, Req> reqs;
+  int64_t next_slot = 0, rr = 0;
+};
+
+extern "C" {
+
+fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
+  if (!d || !bytes || d->n_elems <= 0 || (d->dim != 2 && d->dim != 3) || d->order < 1) return FR_E_ARG;
+  const fr::Dims D(d->dim, d->order);
+  const size_t rs = d->precision == FR_FP32 ? 4 : 8;
+  const int64_t nblk = (d->n_elems + fr::EB - 1) / fr::EB;
+  int64_t nwall = 0;
+  for (int64_t i = 0; i < d->n_bfaces; ++i)
+    if (d->bfaces[3 * i + 2] == FR_BC_WALL) nwall += D.nfp;
+  auto r256 = [](size_t n) { return n == 0 ? size_t(256) : n; };
+  const int dim = d->dim, nv = D.nv;
+  const int RTU = D.nup / 16, RTF = D.nfpad / 16, KTU = D.ku / 4, KTF = D.kf / 4;
+  size_t b = 0;
+  // operators
+  b += r256(size_t(RTF) * KTU * 64 * rs) + r256(size_t(dim) * RTU * KTU * 64 * rs) +
+       r256(size_t(dim) * RTU * KTF * 64 * rs) + r256(size_t(RTU) * dim * KTU * 64 * rs) +
+       r256(size_t(RTU) * KTF * 64 * rs);
+  // geometry and tables
+  b += size_t(nblk) * D.nup * dim * dim * fr::EB * 8 + size_t(nblk) * D.nup * fr::EB * 8;
+  b += size_t(nblk) * D.nfpad * dim * fr::EB * 8 + size_t(nblk) * D.nfpad * fr::EB * 8;
+  b += size_t(nblk) * D.nfpad * fr::EB * 4;
+  b += r256(nblk * 4) * 2 + r256(nblk * 8) * 2 + r256(5 * 8) + r256(2 * 8) + r256(D.nfpad * 8);
+  // state and stage arrays
+  const size_t nU = size_t(nblk) * D.nup * nv * fr::EB, nF = size_t(nblk) * D.nfpad * nv * fr::EB;
+  const size_t nG = size_t(nblk) * D.nup * dim * nv * fr::EB;
+  b += 4 * nU * rs + 4 * nF * rs + 2 * nG * rs;
+  b += r256(size_t(std::max<int64_t>(nwall, 1)) * 3 * 8) + r256(8 * 8) + r256(4);
+  b += size_t(d->n_elems) * D.nu * nv * 8;
+  *bytes = b;
+  return FR_OK;
+}
+
+fr_status fr_pool_create(size_t budget, int32_t device, fr_pool **out) {
+  if (!out || budget == 0) return FR_E_ARG;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return FR_E_DEVICE;
+  fr_pool *p = new fr_pool();
+  p->budget = budget;
+  p->device = device;
+  for (int i = 0; i < 4; ++i) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      for (auto t : p->streams) hipStreamDestroy(t);
+      delete p;
+      return FR_E_DEVICE;
+    }
+    p->streams.push_back(s);
+  }
+  *out = p;
+  return FR_OK;
+}
+
+void fr_pool_destroy(fr_pool *p) {
+  if (!p) return;
+  for (auto &kv : p->reqs) fr_mesh_destroy(kv.second.m);
+  for (auto s : p->streams) {
+    hipStreamSynchronize(s);
+    hipStreamDestroy(s);
+  }
+  delete p;
+}
+
+fr_status fr_pool_admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, int64_t steps, int64_t *slot) {
+  if (!p || !desc || !slot || steps <= 0) return FR_E_ARG;
+  size_t need = 0;
+  fr_status st = fr_footprint(desc, &need);
+  if (st != FR_OK) return st;
+  if (need > p->budget - std::min(p->budget, p->used)) return FR_E_NOMEM;
+  fr_mesh_desc d = *desc;
+  d.device = p->device;
+  d.stream = p->streams[p->rr++ % p->streams.size()];
+  fr_mesh *m = nullptr;
+  st = fr_mesh_create(&d, &m);
+  if (st != FR_OK) return st;
+  int64_t info[10];
+  fr_mesh_info(m, info);
+  const int64_t n = info[3] * info[4] * info[6];
+  std::vector<double> u;
+  if (!u0) {
+    u.resize(size_t(n));
+    const int dim = desc->dim;
+    const double *fs = desc->freestream;
+    double ke = 0.0;
+    for (int k = 0; k < dim; ++k) ke += fs[1 + k] * fs[1 + k];
+    for (int64_t i = 0; i < n / (dim + 2); ++i) {
+      double *x = &u[size_t(i) * (dim + 2)];
+      x[0] = fs[0];
+      for (int k = 0; k < dim; ++k) x[1 + k] = fs[0] * fs[1 + k];
+      x[dim + 1] = fs[4] / (desc->gamma - 1.0) + 0.5 * fs[0] * ke;
+    }
+    u0 = u.data();
+  }
+  st = fr_set_state(m, u0);
+  if (st != FR_OK) {
+    fr_mesh_destroy(m);
+    return st;
+  }
+  fr_pool::Req r;
+  r.m = m;
+  r.left = r.total = steps;
+  r.bytes = size_t(info[9]);
+  p->used += r.bytes;
+  *slot = p->next_slot++;
+  p->reqs[*slot] = r;
+  return FR_OK;
+}
+
+fr_status fr_pool_tick(fr_pool *p, int64_t k, int64_t *done, int32_t max_done, int32_t *n_done) {
+  if (!p || k <= 0 || !n_done) return FR_E_ARG;
+  *n_done = 0;
+  std::vector<int64_t> ran;
+  for (auto &kv : p->reqs) {
+    auto &r = kv.second;
+    if (r.done) continue;
+    const int64_t n = std::min(k, r.left);
+    const fr_status st = fr_step_async(r.m, n);
+    if (st != FR_OK) {
+      r.done = true;
+      r.status = st;
+      continue;
+    }
+    r.left -= n;
+    ran.push_back(kv.first);
+  }
+  for (auto slot : ran) {
+    auto &r = p->reqs[slot];
+    const fr_status st = fr_sync(r.m);
+    if (st != FR_OK) {
+      r.done = true;
+      r.status = st;
+    } else if (r.left == 0) {
+      r.done = true;
+    }
+    if (r.done && done && *n_done < max_done) done[(*n_done)++] = slot;
+  }
+  return FR_OK;
+}
+
+fr_status fr_pool_result(fr_pool *p, int64_t slot, double *out, double *u) {
+  if (!p) return FR_E_ARG;
+  auto it = p->reqs.find(slot);
+  if (it == p->reqs.end()) return FR_E_ARG;
+  auto &r = it->second;
+  if (!r.done) return FR_E_STATE;
+  fr_status st = r.status;
+  if (st == FR_OK && out) st = fr_forces(r.m, 0, out);
+  if (st == FR_OK && u) st = fr_get_state(r.m, u);
+  fr_mesh_destroy(r.m);
+  p->used -= std::min(p->used, r.bytes);
+  p->reqs.erase(it);
+  return st;
+}
+
+fr_status fr_pool_usage(const fr_pool *p, int64_t *used) {
+  if (!p || !used) return FR_E_ARG;
+  used[0] = int64_t(p->used);
+  int64_t running = 0;
+  for (auto &kv : p->reqs)
+    if (!kv.second.done) ++running;
+  used[1] = running;
+  return FR_OK;
+}
+
+}  // extern "C"

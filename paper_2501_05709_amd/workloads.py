@@ -130,8 +130,11 @@ def naca_ogrid(m, pc, t, ni, nj, nk, span=0.2, radius=20.0, ratio=1.1, q=2, orde
     nIq, nJq, nKq = ni * q, nj * q + 1, nk * q + 1
     theta = 2.0 * np.pi * np.arange(nIq) / nIq
     xs, ys = naca4(m, pc, t, theta)
-    ox = 0.5 + radius * np.cos(theta)
-    oy = -radius * np.sin(theta)
+    # outer points turn with the trailing-edge bisector (camber slope at x = 1)
+    # so that the rays leaving the trailing edge split its wedge
+    phi = math.atan(-2.0 * m / (1.0 - pc)) if m > 0.0 else 0.0
+    ox = 0.5 + radius * np.cos(phi - theta)
+    oy = radius * np.sin(phi - theta)
     jj = np.arange(nJq) / q
     frac = (ratio ** jj - 1.0) / (ratio ** nj - 1.0)
     X = xs[None, :] + frac[:, None] * (ox - xs)[None, :]

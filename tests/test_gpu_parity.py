@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (relative L2 per physical field -- density, the momentum vector,
+total energy -- max over the three fields; the momentum vector is one field
+so that the measure does not depend on the coordinate axes, and a momentum
+component that is zero in the reference, as rho w in a spanwise-uniform
+flow, is not divided by its own vanishing norm):
+  * FP64 residual and FP64 state: 1e-12;
+  * FP32 form (FP32 operators, fluxes and state; FP64 metrics): 1e-5 after
+    100 steps;
+  * index work (neighbour tables): bit for bit;
+  * batch and pool members against their solo runs: bit for bit.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleMesh
+from paper_2501_05709_amd import _lib
+from paper_2501_05709_amd import workloads as W
+from paper_2501_05709_amd.solver import FRMesh, FRPool
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_err(x, ref):
+    nv = ref.shape[-1]
+    x = x.reshape(-1, nv)
+    ref = ref.reshape(-1, nv)
+    errs = []
+    for cols in ([0], list(range(1, nv - 1)), [nv - 1]):
+        errs.append(np.linalg.norm(x[:, cols] - ref[:, cols]) / np.linalg.norm(ref[:, cols]))
+    return max(errs)
+
+
+def perturbed(o, mesh, amp=0.1, seed=0):
+    """A non-trivial smooth state: the mesh's initial state plus a smooth perturbation."""
+    x = o.solution_points()
+    u = o.initial_state() if "init" in mesh else None
+    if u is None:
+        fs = mesh["freestream"]
+        u = W.uniform_state(o.E * o.nu, fs[0], fs[1:1 + o.dim], fs[4]).reshape(o.shape)
+    rng = np.random.default_rng(seed)
+    k = rng.uniform(0.5, 2.0, size=3)
+    s = np.sin(k[0] * x[..., 0] + 0.3) * np.cos(k[1] * x[..., 1] - 0.2) * np.cos(k[2] * x[..., 2] + 0.1)
+    u = u.copy()
+    u[..., 0] *= 1.0 + amp * s
+    u[..., -1] *= 1.0 + amp * s
+    return u
+
+
+def case(name):
+    if name == "vortex2d_p3":
+        return W.config_vortex(0)
+    if name == "box2d_curved_p2":
+        m = W.box_mesh(2, (5, 4), (0, 0), (1, 1), q=2, warp=0.05, order=2)
+        m.update(gamma=1.4, prandtl=0.72, mu=0.02, freestream=np.array([1.0, 0.3, -0.2, 0.0, 1.0]), dt=1e-3)
+        return m
+    if name.startswith("tgv"):
+        nel, order = {"tgv_p1": (6, 1), "tgv_p2": (5, 2), "tgv_p3": (4, 3), "tgv_p4": (3, 4)}[name]
+        return W.config_tgv(nel=nel, order=order)
+    if name == "airfoil_p3":
+        return W.config_airfoil(1, ni=24, nj=5, nk=2)
+    if name == "airfoil_p2":
+        return W.config_airfoil(2, ni=16, nj=4, nk=3, order=2)
+    raise KeyError(name)
+
+
+CASES = ["vortex2d_p3", "box2d_curved_p2", "tgv_p1", "tgv_p2", "tgv_p3", "tgv_p4", "airfoil_p3", "airfoil_p2"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_residual_fp64_matches_oracle(name):
+    m = case(name)
+    o = OracleMesh(m)
+    u = perturbed(o, m)
+    ref = o.residual(u)
+    g = FRMesh(m, "fp64")
+    assert np.array_equal(g.neighbours(), o.neighbours())
+    r = g.residual(u)
+    err = rel_err(r, ref)
+    print(f"{name}: fp64 residual rel L2 {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["vortex2d_p3", "tgv_p3", "airfoil_p3"])
+def test_residual_fp32_close_to_oracle(name):
+    m = case(name)
+    o = OracleMesh(m)
+    u = perturbed(o, m)
+    ref = o.residual(u)
+    r = FRMesh(m, "fp32").residual(u)
+    err = rel_err(r, ref)
+    print(f"{name}: fp32 residual rel L2 {err:.3e}")
+    # a residual is a difference quotient of O(1) fluxes: FP32 rounding of the
+    # fluxes (~6e-8) is amplified by |F|/(h |R|); the state bar (1e-5 after
+    # 100 steps) is the one the FP32 form is held to
+    assert err <= 1e-3
+
+
+def test_vortex_state_after_100_steps():
+    """Isentropic vortex, 16x16 periodic quads, p = 3, 100 RK4 steps of 1e-3."""
+    m = W.config_vortex(0)
+    o = OracleMesh(m)
+    u0 = o.initial_state()
+    ref = o.rk4(u0, m["dt"], 100)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        g = FRMesh(m, prec)
+        g.set_state(u0)
+        g.step(100)
+        err = rel_err(g.get_state(), ref)
+        print(f"vortex 100 steps {prec}: rel L2 {err:.3e}")
+        assert err <= tol
+
+
+def test_tgv_state_after_steps():
+    m = W.config_tgv(nel=6, order=3)
+    o = OracleMesh(m)
+    u0 = o.initial_state()
+    ref = o.rk4(u0, m["dt"], 100)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        g = FRMesh(m, prec)
+        g.set_state(u0)
+        g.step(100)
+        err = rel_err(g.get_state(), ref)
+        print(f"tgv 6^3 100 steps {prec}: rel L2 {err:.3e}")
+        assert err <= tol
+
+
+def test_airfoil_state_and_forces():
+    m = W.config_airfoil(3, ni=24, nj=5, nk=2)
+    o = OracleMesh(m)
+    u0 = o.initial_state()
+    n = 20
+    ref, hist = o.rk4(u0, m["dt"], n, forces=True)
+    g = FRMesh(m, "fp64")
+    g.set_state(u0)
+    g.step(n)
+    err = rel_err(g.get_state(), ref)
+    print(f"airfoil fp64 {n} steps: rel L2 {err:.3e}")
+    assert err <= 1e-12
+    f = g.forces()
+    qref = 0.5 * 1.0 * 1.0 * m["ref_area"]
+    cl_ref = hist[-1] @ m["lift_dir"] / qref
+    cd_ref = hist[-1] @ m["drag_dir"] / qref
+    mean = hist.mean(axis=0)
+    scale = np.abs(hist).max() / qref
+    assert f[7] == n
+    assert abs(f[0] - cl_ref) <= 1e-10 * scale and abs(f[1] - cd_ref) <= 1e-10 * scale
+    assert abs(f[5] - mean @ m["lift_dir"] / qref) <= 1e-10 * scale
+    assert abs(f[6] - mean @ m["drag_dir"] / qref) <= 1e-10 * scale
+    assert np.allclose(f[2:5], hist[-1], rtol=0, atol=1e-10 * np.abs(hist).max())
+
+
+def test_set_get_roundtrip_and_resume_bit_identical():
+    m = W.config_airfoil(4, ni=16, nj=4, nk=2)
+    o = OracleMesh(m)
+    u0 = perturbed(o, m)
+    g = FRMesh(m, "fp64")
+    g.set_state(u0)
+    assert np.array_equal(g.get_state(), u0)
+    g.step(6)
+    a = g.get_state()
+    g.set_state(u0)
+    g.step(3)
+    mid = g.get_state()
+    g.set_state(mid)
+    g.step(3)
+    assert np.array_equal(g.get_state(), a)
+
+
+def test_nonfinite_state_is_reported():
+    m = W.config_vortex(1)
+    g = FRMesh(m, "fp32")
+    o = OracleMesh(m)
+    u = o.initial_state()
+    u[3, 2, 0] = np.nan
+    g.set_state(u)
+    with pytest.raises(_lib.FRError) as ei:
+        g.step(2)
+    assert ei.value.code == _lib.FR_E_NONFINITE
+
+
+def test_batch_members_bit_identical_to_solo():
+    meshes = [W.config_airfoil(10 + i, ni=12 + 4 * i, nj=3 + i, nk=1 + i % 2) for i in range(3)]
+    b = FRMesh(meshes, "fp32")
+    us = []
+    for m in meshes:
+        o = OracleMesh(m)
+        us.append(perturbed(o, m, seed=len(us)))
+    b.set_state(np.concatenate(us, axis=0))
+    b.step(8)
+    ub = b.get_state()
+    for i, m in enumerate(meshes):
+        g = FRMesh(m, "fp32")
+        g.set_state(us[i])
+        g.step(8)
+        e0, ne = b.design_range(i)
+        assert np.array_equal(ub[e0:e0 + ne], g.get_state())
+        assert np.array_equal(b.forces(i), g.forces())
+
+
+def test_pool_results_bit_identical_to_solo():
+    reqs = [W.config_airfoil(20 + i, ni=12, nj=3 + i, nk=2, order=2 + i % 3) for i in range(4)]
+    pool = FRPool(8 << 30)
+    slots = {}
+    for i, m in enumerate(reqs):
+        s = pool.admit(m, steps=7 + i, precision="fp32", u0=OracleMesh(m).initial_state())
+        assert s is not None
+        slots[s] = i
+    done = []
+    while len(done) < len(reqs):
+        done += pool.tick(3)
+    for s in done:
+        i = slots[s]
+        m = reqs[i]
+        o = OracleMesh(m)
+        out, u = pool.result(s, shape=o.shape)
+        g = FRMesh(m, "fp32")
+        g.set_state(o.initial_state())
+        g.step(7 + i)
+        assert np.array_equal(u, g.get_state())
+        assert np.array_equal(out, g.forces())
+    assert pool.usage() == (0, 0)
