@@ -9,7 +9,7 @@
  * (Huynh 2007, named in the paper's Section 1 for its solver) and classic
  * RK4 in time.  The design evaluation of the paper's Algorithm 1 needs the
  * flow advanced on one candidate mesh and the time-averaged lift and drag
- * (Section 4, objective function); these calls are exactly that.
+ * (Section 3.4, objective function); these calls are exactly that.
  *
  * Scheme (fixed): Gauss-Legendre solution points (tensor product), flux
  * points where the solution-point lines meet the faces, g_DG (Radau)

@@ -6,7 +6,7 @@ the inputs that both the GPU library and the independent CPU oracle consume:
 * ``box_mesh``      periodic straight (optionally warped, quadratic) boxes;
 * ``naca_ogrid``    spanwise-periodic O-grids of quadratic hexahedra around a
                     NACA 4-digit profile (the airfoil family of the paper's
-                    Section 3 and its design vector, Section 4);
+                    Section 3 and its design vector, Section 3.4);
 * initial states    the isentropic vortex, the Taylor-Green vortex and a
                     uniform free stream;
 * ``config_*``      the five benchmark workloads (vortex, Taylor-Green,
