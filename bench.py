@@ -29,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"hbm": 8000.0, "mfma_f32": 157.3, "mfma_f64": 78.6}  # GB/s, TFLOP/s
-KERNEL_NAMES = {1: "k_face", 2: "k_grad", 3: "k_visc", 4: "k_divrk", 5: "k_interp"}
+KERNEL_NAMES = {1: "k_face", 2: "k_grad", 3: "k_visc", 4: "k_divrk", 5: "k_interp", 6: "k_stage_a",
+                7: "k_stage_b"}
 
 
 def per_element_cost(dim, order, real_bytes):
@@ -53,6 +54,14 @@ def per_element_cost(dim, order, real_bytes):
                 bytes=nu * dim * nv * s + 3 * nf * nv * s + nf * 8 + nf * 4 + nu * 8 + 2 * nu * nv * s
                 + 2 * nu * nv * s),
         5: dict(flops=2 * nv * nf * nu, bytes=nu * nv * s + nf * nv * s),
+        # fused stage a: stage state, partner traces, normals, neighbour codes, S and 1/|J|
+        # in; Q, P and the volume divergence out
+        6: dict(flops=0, bytes=nu * nv * s + nf * nv * s + nf * dim * 8 + nf * 4 + nu * (dim * dim + 1) * 8
+                + 2 * nf * nv * s + nu * nv * s),
+        # fused stage b: Q, partner P, codes, areas, divergence, 1/|J|, u_n, acc in; acc,
+        # next stage state and its trace out
+        7: dict(flops=0, bytes=2 * nf * nv * s + nf * 4 + nf * 8 + nu * nv * s + nu * 8 + 2 * nu * nv * s
+                + 2 * nu * nv * s + nf * nv * s),
     }
     return cost, nu * nv
 
@@ -153,8 +162,14 @@ def main():
                "sample": f"{n_sample} RK4 steps of the full {desc['workload']} mesh, FP64, "
                          f"OpenMP over elements, {tc:.1f} s"}
 
-    # --- plain FP64 GPU path
+    # --- autotune the operator back-end of every kernel (dense MFMA vs sum factorised)
+    g32.set_state(u0)
+    mask32 = g32.autotune(3)
     g64 = FRMesh(m, "fp64")
+    g64.set_state(u0)
+    mask64 = g64.autotune(3)
+
+    # --- plain FP64 GPU path
     err64_oracle = err32_oracle = None
     if ref_sample is not None:
         g64.set_state(u0)
@@ -171,22 +186,47 @@ def main():
     u32 = g32.get_state()
     err32_vs64 = rel_l2(u32, u64)
 
+    # --- the all-dense-MFMA operator back-end, for comparison
+    g32.select_kernels(0)
+    t32_dense = timed_run(g32, u0, args.steps, args.warmup)
+    g64.select_kernels(0)
+    t64_dense = timed_run(g64, u0, args.steps, args.warmup)
+    g32.select_kernels(mask32)
+
     # --- per-kernel times (HIP events on the solver's stream) and roofline
     g32.set_state(u0)
     ms, nl = g32.profile_kernels(5)
     cost, dof_per_elem = per_element_cost(g32.dim, g32.order, 4)
     kernels = {}
-    for k in range(1, 6):
+    fused = bool(mask32 & 1)
+    for k in ((6, 7) if fused else range(1, 6)):
+        if k >= 6:
+            variant = "fused, sum-factorised"
+        else:
+            variant = "face" if k == 1 else ("sum-factorised" if (mask32 >> k) & 1 else "dense-mfma")
         avg_ms = ms[k] / max(nl[k], 1)
         fl = cost[k]["flops"] * g32.E
         by = cost[k]["bytes"] * g32.E
         kernels[KERNEL_NAMES[k]] = {
-            "avg_us": round(avg_ms * 1e3, 2), "share": round(ms[k] / ms[0], 3),
-            "tflops": round(fl / (avg_ms * 1e-3) / 1e12, 2) if fl else 0.0,
+            "variant": variant, "avg_us": round(avg_ms * 1e3, 2), "share": round(ms[k] / ms[0], 3),
+            "dense_equiv_tflops": round(fl / (avg_ms * 1e-3) / 1e12, 2) if fl else 0.0,
             "gbs": round(by / (avg_ms * 1e-3) / 1e9, 1)}
-    dom = max(range(1, 6), key=lambda k: ms[k])
+    # the same table for the all-dense-MFMA back-end (MFMA utilisation evidence)
+    g32.select_kernels(0)
+    g32.set_state(u0)
+    msd, nld = g32.profile_kernels(5)
+    g32.select_kernels(mask32)
+    dense_kernels = {}
+    for k in range(2, 6):
+        avg_ms = msd[k] / max(nld[k], 1)
+        fl = cost[k]["flops"] * g32.E
+        dense_kernels[KERNEL_NAMES[k]] = {
+            "avg_us": round(avg_ms * 1e3, 2), "tflops": round(fl / (avg_ms * 1e-3) / 1e12, 2),
+            "mfma_frac": round(fl / (avg_ms * 1e-3) / 1e12 / PEAK["mfma_f32"], 4)}
+    dom = max(range(1, 8), key=lambda k: ms[k])
     avg_s = ms[dom] / nl[dom] * 1e-3
-    if cost[dom]["flops"]:
+    dom_dense = dom in (2, 3, 4, 5) and not (mask32 >> dom) & 1
+    if dom_dense:
         achieved = cost[dom]["flops"] * g32.E / avg_s / 1e12
         peak = PEAK["mfma_f32"]
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
@@ -220,8 +260,15 @@ def main():
         "fp32_rel_l2_vs_fp64_gpu": err32_vs64,
         "oracle_sample_steps": n_sample if ref_sample is not None else None,
         "speedup_fp32_over_fp64": round(t64 / t32, 3),
+        "kernel_variants": {"fp32_mask": mask32, "fp64_mask": mask64,
+                            "note": "bit 0: fused two-launch stage (sum-factorised); else bit k set: "
+                                    "split kernel k sum-factorised, clear: dense MFMA "
+                                    "(2 grad, 3 visc, 4 divrk, 5 interp)"},
+        "dense_mfma_only": {"fp32_value": round(dof * args.steps / t32_dense, 1),
+                            "fp64_value": round(dof * args.steps / t64_dense, 1)},
         "kernels": kernels,
         "roofline": roof,
+        "dense_mfma_kernels_fp32": dense_kernels,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -162,11 +162,33 @@ fr_status fr_residual(fr_mesh *m, const double *u, double *r);
  * the device: layout [block][n_u padded to 16][variables][16 elements]. */
 fr_status fr_state_device(const fr_mesh *m, void **ptr, int64_t *bytes);
 
-/* Kernel-timing hook for benchmarks: records HIP events around the launches
- * of the named kernel (0 = all) in the next fr_step call and returns the
- * summed milliseconds and launch count.  kernel ids: 1 face, 2 gradient and
- * flux, 3 viscous trace, 4 divergence and RK update, 5 interpolation. */
+/* Kernel-timing hook for benchmarks: runs `steps` RK4 steps with HIP events
+ * around every launch on the handle's stream and returns, per kernel id, the
+ * summed milliseconds and the launch count in ms_per_kernel[0..7] and
+ * launches[0..7] (index 0 = all kernels).  Kernel ids: 1 face, 2 gradient
+ * and flux, 3 viscous trace, 4 divergence and RK update, 5 interpolation,
+ * 6 fused stage part a, 7 fused stage part b. */
 fr_status fr_profile_kernels(fr_mesh *m, int64_t steps, double *ms_per_kernel, int64_t *launches);
+
+/* Kernel structure and operator back-end.  Bit 0 set: each RK stage is two
+ * fused launches (faces, gradient, fluxes and volume divergence; then the
+ * flux correction, RK update and next trace), with the operators applied by
+ * sum factorisation along the solution-point lines.  Bit 0 clear: five
+ * launches per stage (face, gradient/flux, viscous trace, divergence/RK
+ * update, interpolation); bit k (k = 2, 3, 4, 5 for those four operator
+ * kernels) set selects sum factorisation (VALU, LDS-staged inputs), clear
+ * the dense element-batched MFMA contraction.  Every choice gives the same
+ * result to round-off.  The default is the last autotuned choice for this
+ * (precision, dim, order) in the process, else the fused stage. */
+fr_status fr_select_kernels(fr_mesh *m, int32_t mask);
+fr_status fr_selected_kernels(const fr_mesh *m, int32_t *mask);
+
+/* Autotuner: times the fused stage and both variants of every split
+ * operator kernel for `steps` steps on this mesh with HIP events (the state
+ * is saved and restored), keeps the fastest configuration, records it for
+ * later meshes of the same precision, dimension and order, and returns the
+ * mask. */
+fr_status fr_autotune(fr_mesh *m, int64_t steps, int32_t *mask_out);
 
 /* ---- served requests: continuous batching under an HBM budget ---------- */
 

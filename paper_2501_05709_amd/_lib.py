@@ -58,6 +58,9 @@ SIGNATURES = {
     "fr_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
     "fr_residual": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
     "fr_state_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), _i64p]),
+    "fr_select_kernels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "fr_selected_kernels": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "fr_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
     "fr_profile_kernels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp, _i64p]),
     "fr_pool_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "fr_pool_destroy": (None, [ctypes.c_void_p]),

@@ -591,6 +591,18 @@ void validate_desc(const fr_mesh_desc *d) {
   if (!(d->dt > 0.0) || !std::isfinite(d->dt)) fail(FR_E_ARG, "dt must be positive");
 }
 
+// kernels (bit = enum Kernel) that run the sum-factorised variant unless tuned otherwise
+std::map<int, unsigned> g_tuned;  // key prec*100 + dim*10 + order
+unsigned default_variants(int prec, int dim, int order) {
+  auto it = g_tuned.find(prec * 100 + dim * 10 + order);
+  if (it != g_tuned.end()) return it->second;
+  return 1u | (1u << K_INTERP);  // fused stage, sum-factorised trace
+}
+
+constexpr unsigned FUSED = 1u;  // variant-mask bit 0: two fused launches per stage
+
+void drop_graphs(fr_mesh *M);
+
 void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
   const fr_mesh_desc &d0 = descs[0];
   M->dim = d0.dim;
@@ -741,6 +753,15 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
   a.opGcorr = upload_real(sGcorr);
   a.opDivS = upload_real(sDivS);
   a.opCorr = upload_real(sCorr);
+  {
+    Basis1D b(M->order);
+    std::vector<double> bv(b.D);
+    bv.insert(bv.end(), b.lm.begin(), b.lm.end());
+    bv.insert(bv.end(), b.lp.begin(), b.lp.end());
+    bv.insert(bv.end(), b.gLd.begin(), b.gLd.end());
+    bv.insert(bv.end(), b.gRd.begin(), b.gRd.end());
+    a.basis = upload_real(bv);
+  }
   a.SM = M->upload(SM);
   a.IJ = M->upload(IJ);
   a.FN = M->upload(FN);
@@ -787,7 +808,16 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
   c.mu = M->mu;
   c.prandtl = M->prandtl;
   c.stream = M->stream;
+  c.variant_mask = default_variants(c.prec, dim, M->order);
   hip_check(hipStreamSynchronize(M->stream), "mesh upload");
+}
+
+void profile_steps(fr_mesh *m, int64_t steps, double *ms, int64_t *launches);
+
+void drop_graphs(fr_mesh *M) {
+  if (M->graph_first) hipGraphExecDestroy(M->graph_first);
+  if (M->graph_rest) hipGraphExecDestroy(M->graph_rest);
+  M->graph_first = M->graph_rest = nullptr;
 }
 
 void lk(fr_mesh *M, int kernel, int stage, int mode, bool forces) {
@@ -796,6 +826,15 @@ void lk(fr_mesh *M, int kernel, int stage, int mode, bool forces) {
 
 // one RK4 step; force terms of the step's input state are reduced if `forces`
 void enqueue_step(fr_mesh *M, bool forces) {
+  if (M->cfg.variant_mask & FUSED) {
+    for (int s = 0; s < 4; ++s) {
+      const bool f = forces && s == 0 && M->nwall > 0;
+      lk(M, K_STAGE_A, s, 0, f);
+      if (f) hip_check(launch_force_reduce(M->cfg, M->a), "force reduce");
+      lk(M, K_STAGE_B, s, s, false);
+    }
+    return;
+  }
   for (int s = 0; s < 4; ++s) {
     const bool f = forces && s == 0 && M->nwall > 0;
     lk(M, K_FACE, s, 0, false);
@@ -837,9 +876,13 @@ void step_async(fr_mesh *M, int64_t n) {
   for (int64_t s = 0; s < n; ++s)
     hip_check(hipGraphLaunch(s == 0 ? M->graph_first : M->graph_rest, M->stream), "graph launch");
   if (M->nwall > 0) {  // wall force of the final state
-    lk(M, K_FACE, 0, 0, false);
-    lk(M, K_GRAD, 0, 0, false);
-    lk(M, K_VISC, 0, 0, true);
+    if (M->cfg.variant_mask & FUSED) {
+      lk(M, K_STAGE_A, 0, 0, true);
+    } else {
+      lk(M, K_FACE, 0, 0, false);
+      lk(M, K_GRAD, 0, 0, false);
+      lk(M, K_VISC, 0, 0, true);
+    }
     hip_check(launch_force_reduce(M->cfg, M->a), "force reduce");
   }
 }
@@ -1004,10 +1047,15 @@ fr_status fr_residual(fr_mesh *m, const double *u, double *r) {
     hip_check(hipMemcpyAsync(m->a.stage64, u, n * sizeof(double), hipMemcpyHostToDevice, m->stream), "upload");
     hip_check(launch_pack(m->cfg, m->a, true, m->a.US), "pack");
     lk(m, K_INTERP, 1, 0, false);
-    lk(m, K_FACE, 1, 0, false);
-    lk(m, K_GRAD, 1, 0, false);
-    lk(m, K_VISC, 1, 0, false);
-    lk(m, K_DIVRK, 1, MODE_RESID, false);
+    if (m->cfg.variant_mask & FUSED) {
+      lk(m, K_STAGE_A, 1, 0, false);
+      lk(m, K_STAGE_B, 1, MODE_RESID, false);
+    } else {
+      lk(m, K_FACE, 1, 0, false);
+      lk(m, K_GRAD, 1, 0, false);
+      lk(m, K_VISC, 1, 0, false);
+      lk(m, K_DIVRK, 1, MODE_RESID, false);
+    }
     hip_check(launch_pack(m->cfg, m->a, false, m->a.RES), "unpack");
     hip_check(hipMemcpyAsync(r, m->a.stage64, n * sizeof(double), hipMemcpyDeviceToHost, m->stream), "download");
     hip_check(hipStreamSynchronize(m->stream), "residual");
@@ -1022,12 +1070,71 @@ fr_status fr_state_device(const fr_mesh *m, void **ptr, int64_t *bytes) {
   });
 }
 
+fr_status fr_select_kernels(fr_mesh *m, int32_t mask) {
+  return guarded([&] {
+    if (!m) fail(FR_E_ARG, "null mesh");
+    m->cfg.variant_mask = unsigned(mask) & (FUSED | (1u << K_INTERP) | (1u << K_GRAD) | (1u << K_VISC) | (1u << K_DIVRK));
+    drop_graphs(m);
+  });
+}
+
+fr_status fr_selected_kernels(const fr_mesh *m, int32_t *mask) {
+  return guarded([&] {
+    if (!m || !mask) fail(FR_E_ARG, "null argument");
+    *mask = int32_t(m->cfg.variant_mask);
+  });
+}
+
+fr_status fr_autotune(fr_mesh *m, int64_t steps, int32_t *mask_out) {
+  return guarded([&] {
+    if (!m || steps <= 0) fail(FR_E_ARG, "bad argument");
+    if (!m->state_set) fail(FR_E_STATE, "no state set");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    const size_t nb = size_t(m->nblk) * m->dm.nup * m->dm.nv * EB * m->real_size();
+    // keep the state: time on a copy, restore it afterwards
+    hip_check(hipMemcpyAsync(m->a.RES, m->a.U, nb, hipMemcpyDeviceToDevice, m->stream), "save state");
+    const unsigned all = (1u << K_INTERP) | (1u << K_GRAD) | (1u << K_VISC) | (1u << K_DIVRK);
+    double ms_dense[8], ms_tensor[8], ms_fused[8];
+    int64_t n[8];
+    m->cfg.variant_mask = 0;
+    profile_steps(m, steps, ms_dense, n);
+    hip_check(hipMemcpyAsync(m->a.U, m->a.RES, nb, hipMemcpyDeviceToDevice, m->stream), "restore state");
+    m->cfg.variant_mask = all;
+    profile_steps(m, steps, ms_tensor, n);
+    hip_check(hipMemcpyAsync(m->a.U, m->a.RES, nb, hipMemcpyDeviceToDevice, m->stream), "restore state");
+    m->cfg.variant_mask = FUSED | (1u << K_INTERP);
+    profile_steps(m, steps, ms_fused, n);
+    hip_check(hipMemcpyAsync(m->a.U, m->a.RES, nb, hipMemcpyDeviceToDevice, m->stream), "restore state");
+    unsigned mask = 0;
+    double split = ms_dense[K_FACE];
+    for (int k : {int(K_INTERP), int(K_GRAD), int(K_VISC), int(K_DIVRK)}) {
+      if (ms_tensor[k] < ms_dense[k]) mask |= 1u << k;
+      split += std::min(ms_tensor[k], ms_dense[k]);
+    }
+    if (ms_fused[K_STAGE_A] + ms_fused[K_STAGE_B] < split) mask = FUSED | (1u << K_INTERP);
+    m->cfg.variant_mask = mask;
+    g_tuned[m->prec * 100 + m->dim * 10 + m->order] = mask;
+    drop_graphs(m);
+    hip_check(hipStreamSynchronize(m->stream), "autotune");
+    if (mask_out) *mask_out = int32_t(mask);
+  });
+}
+
 fr_status fr_profile_kernels(fr_mesh *m, int64_t steps, double *ms, int64_t *launches) {
   return guarded([&] {
     if (!m || !ms || !launches || steps <= 0) fail(FR_E_ARG, "bad argument");
     if (!m->state_set) fail(FR_E_STATE, "no state set");
     hip_check(hipSetDevice(m->device), "hipSetDevice");
-    for (int k = 0; k < 6; ++k) { ms[k] = 0.0; launches[k] = 0; }
+    profile_steps(m, steps, ms, launches);
+  });
+}
+
+}  // extern "C"
+
+namespace {
+void profile_steps(fr_mesh *m, int64_t steps, double *ms, int64_t *launches) {
+  {
+    for (int k = 0; k < 8; ++k) { ms[k] = 0.0; launches[k] = 0; }
     std::vector<hipEvent_t> ev;
     std::vector<int> kid;
     auto timed = [&](int kernel, int stage, int mode, bool forces) {
@@ -1045,6 +1152,11 @@ fr_status fr_profile_kernels(fr_mesh *m, int64_t steps, double *ms, int64_t *lau
     lk(m, K_INTERP, 0, 0, false);
     for (int64_t s = 0; s < steps; ++s)
       for (int st = 0; st < 4; ++st) {
+        if (m->cfg.variant_mask & FUSED) {
+          timed(K_STAGE_A, st, 0, false);
+          timed(K_STAGE_B, st, st, false);
+          continue;
+        }
         timed(K_FACE, st, 0, false);
         timed(K_GRAD, st, 0, false);
         timed(K_VISC, st, 0, false);
@@ -1061,7 +1173,6 @@ fr_status fr_profile_kernels(fr_mesh *m, int64_t steps, double *ms, int64_t *lau
       launches[0] += 1;
     }
     for (auto e : ev) hipEventDestroy(e);
-  });
+  }
 }
-
-}  // extern "C"
+}  // namespace

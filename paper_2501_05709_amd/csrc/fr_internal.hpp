@@ -21,6 +21,8 @@ enum Kernel {
   K_VISC = 3,    // gradient trace, viscous normal flux (and wall force terms)
   K_DIVRK = 4,   // corrected divergence, residual, fused RK4 stage update
   K_INTERP = 5,  // solution trace at flux points
+  K_STAGE_A = 6, // fused: faces, gradient, fluxes, viscous half-flux, volume divergence
+  K_STAGE_B = 7, // fused: flux correction, RK4 stage update, next trace
 };
 
 // Modes of K_DIVRK
@@ -32,6 +34,8 @@ struct DevArrays {
   void *GU = nullptr, *FT = nullptr, *PV = nullptr, *RES = nullptr;
   // operators (real), swizzled into MFMA A-operand order
   void *opInt = nullptr, *opGrad = nullptr, *opGcorr = nullptr, *opDivS = nullptr, *opCorr = nullptr;
+  // 1D basis (real): D[n][n], l(-1)[n], l(+1)[n], g_L'[n], g_R'[n]
+  void *basis = nullptr;
   // FP64 geometry
   double *SM = nullptr;  // [blk][NUP][dim*dim][EB]  S = |J| J^-1
   double *IJ = nullptr;  // [blk][NUP][EB]          1/|J|
@@ -58,6 +62,8 @@ struct LaunchCfg {
   int64_t n_canon = 0;  // canonical elements
   double gamma = 1.4, mu = 0.0, prandtl = 0.72;
   hipStream_t stream = nullptr;
+  // bit k set: kernel k (enum Kernel) runs its sum-factorised variant, else dense MFMA
+  unsigned variant_mask = 0;
 };
 
 // Shape constants for a (dim, order) pair

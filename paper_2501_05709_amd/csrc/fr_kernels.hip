@@ -71,7 +71,7 @@ template <int DIM, int ORDER> struct Shape {
 
 template <typename T> struct KArgs {
   T *U, *US, *ACC, *UF, *DU, *FI, *GU, *FT, *PV, *RES;
-  const T *opInt, *opGrad, *opGcorr, *opDivS, *opCorr;
+  const T *opInt, *opGrad, *opGcorr, *opDivS, *opCorr, *basis;
   const double *SM, *IJ, *FN, *FA, *bdt, *fsd, *wface;
   double *FC, *fsum, *stage64;
   const int *NB, *bcount, *bdesign;
@@ -237,7 +237,245 @@ __device__ inline size_t at(int64_t blk, int pt, int ch, int e, int NPT, int NCH
 }
 
 // ---------------------------------------------------------------------------
-// K_INTERP: u_f = M_int u
+// reference-element index maps (conventions of include/fr.h)
+// ---------------------------------------------------------------------------
+template <int DIM, int N> struct Ref {
+  // solution point on the line through face point m of a face on axis k, at position j
+  __device__ static inline int line(int k, int m, int j) {
+    if (DIM == 2) return k == 0 ? j + N * m : m + N * j;
+    const int a = m % N, b = m / N;
+    return k == 0 ? j + N * (a + N * b) : (k == 1 ? a + N * (j + N * b) : a + N * (b + N * j));
+  }
+  // position along axis k and face-point index of solution point i
+  __device__ static inline void locate(int i, int k, int &ik, int &m) {
+    const int c0 = i % N, c1 = (i / N) % N, c2 = i / (N * N);
+    if (DIM == 2) {
+      ik = k == 0 ? c0 : c1;
+      m = k == 0 ? c1 : c0;
+      return;
+    }
+    if (k == 0) { ik = c0; m = c1 + N * c2; }
+    else if (k == 1) { ik = c1; m = c0 + N * c2; }
+    else { ik = c2; m = c0 + N * c1; }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// epilogues shared by the dense-MFMA and the sum-factorised kernels
+// ---------------------------------------------------------------------------
+
+// physical gradient grad u = S^T G / |J| and transformed flux F~ = S (F_inv - F_vis)
+// at solution point i of element slot e; G is the corrected reference gradient
+template <typename T, int DIM, int ORDER>
+__device__ inline void grad_epilogue(const KArgs<T> &a, const Gas<T, DIM> &gas, int64_t blk, int i, int e,
+                                     const T *u, const T G[DIM][DIM + 2]) {
+  using S = Shape<DIM, ORDER>;
+  double Sm[DIM][DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k)
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) Sm[k][c] = a.SM[at(blk, i, k * DIM + c, e, S::NUP, DIM * DIM)];
+  const double ij = a.IJ[(size_t(blk) * S::NUP + i) * EB + e];
+  T gu[DIM][S::NV];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) s += Sm[k][c] * double(G[k][v]);
+      gu[c][v] = T(s * ij);
+    }
+  T Fi[DIM][S::NV], Fv[DIM][S::NV];
+  gas.flux_inv(u, Fi);
+  gas.flux_vis(u, gu, Fv, false);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) a.GU[at(blk, i, c * S::NV + v, e, S::NUP, S::NG)] = gu[c][v];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k)
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) s += Sm[k][c] * double(Fi[c][v] - Fv[c][v]);
+      a.FT[at(blk, i, k * S::NV + v, e, S::NUP, S::NG)] = T(s);
+    }
+}
+
+// viscous part of the common flux at flux point q from the gradient trace gf:
+// interior -> half the own viscous normal flux; boundary -> the full common flux
+template <typename T, int DIM, int ORDER>
+__device__ inline void visc_epilogue(const KArgs<T> &a, const Gas<T, DIM> &gas, int64_t blk, int q, int e,
+                                     const T gf[DIM][DIM + 2], int forces) {
+  using S = Shape<DIM, ORDER>;
+  T uf[S::NV], n[DIM], Fv[DIM][S::NV], pv[S::NV];
+#pragma unroll
+  for (int v = 0; v < S::NV; ++v) uf[v] = a.UF[at(blk, q, v, e, S::NFPAD, S::NV)];
+  double nd[DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    nd[c] = a.FN[at(blk, q, c, e, S::NFPAD, DIM)];
+    n[c] = T(nd[c]);
+  }
+  const int nb = a.NB[(size_t(blk) * S::NFPAD + q) * EB + e];
+  if (nb >= 0) {
+    gas.flux_vis(uf, gf, Fv, false);
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) s += Fv[c][v] * n[c];
+      pv[v] = T(0.5) * s;
+    }
+  } else {
+    const int code = -nb;
+    T ub[S::NV];
+    if ((code & 3) == BC_FARFIELD) {
+      gas.farfield(uf, n, a.fsd + 5 * a.bdesign[blk], ub);
+      gas.flux_vis(ub, gf, Fv, false);
+    } else {
+      gas.wall_common(uf, ub);
+      gas.flux_vis(ub, gf, Fv, true);
+    }
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) s += Fv[c][v] * n[c];
+      pv[v] = a.FI[at(blk, q, v, e, S::NFPAD, S::NV)] - s;
+    }
+    if (forces && (code & 3) == BC_WALL) {
+      // traction of the fluid on the body: W A (p n - tau . n), interior trace
+      T Fw[DIM][S::NV];
+      gas.flux_vis(uf, gf, Fw, false);
+      const double p = double(gas.pressure(uf));
+      const double wA = a.wface[q] * a.FA[(size_t(blk) * S::NFPAD + q) * EB + e];
+      const int64_t w = code >> 2;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        double tn = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) tn += double(Fw[c][1 + i]) * nd[c];
+        a.FC[w * 3 + i] = wA * (p * nd[i] - tn);
+      }
+      if (DIM == 2) a.FC[w * 3 + 2] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < S::NV; ++v) a.PV[at(blk, q, v, e, S::NFPAD, S::NV)] = pv[v];
+}
+
+// transformed outward common normal flux at flux point q: A (F_I* - P + P_nbr), or A P at a boundary
+template <typename T, int DIM, int ORDER>
+__device__ inline void common_flux(const KArgs<T> &a, int64_t blk, int q, int e, T *b) {
+  using S = Shape<DIM, ORDER>;
+  const size_t fq = (size_t(blk) * S::NFPAD + q) * EB + e;
+  const int nb = a.NB[fq];
+  const double A = a.FA[fq];
+  if (nb >= 0) {
+    const size_t base = size_t(nb / EB) * S::NV * EB + (nb % EB);
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) {
+      const T f = a.FI[at(blk, q, v, e, S::NFPAD, S::NV)] - a.PV[at(blk, q, v, e, S::NFPAD, S::NV)] +
+                  a.PV[base + v * EB];
+      b[v] = T(A * double(f));
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) b[v] = T(A * double(a.PV[at(blk, q, v, e, S::NFPAD, S::NV)]));
+  }
+}
+
+// R = -div / |J| and the RK4 stage update at solution point i
+template <typename T, int DIM, int ORDER>
+__device__ inline void rk_epilogue(const KArgs<T> &a, int64_t blk, int i, int e, const T *div, int mode, int &bad) {
+  using S = Shape<DIM, ORDER>;
+  const double ij = a.IJ[(size_t(blk) * S::NUP + i) * EB + e];
+  const T dt = T(a.bdt[blk]);
+#pragma unroll
+  for (int v = 0; v < S::NV; ++v) {
+    const size_t x = at(blk, i, v, e, S::NUP, S::NV);
+    const T r = T(-double(div[v]) * ij);
+    if (mode == MODE_RESID) {
+      a.RES[x] = r;
+    } else if (mode == MODE_RK0) {
+      a.ACC[x] = r;
+      a.US[x] = a.U[x] + T(0.5) * dt * r;
+    } else if (mode == MODE_RK1) {
+      a.ACC[x] += T(2) * r;
+      a.US[x] = a.U[x] + T(0.5) * dt * r;
+    } else if (mode == MODE_RK2) {
+      a.ACC[x] += T(2) * r;
+      a.US[x] = a.U[x] + dt * r;
+    } else {
+      const T un = a.U[x] + dt / T(6) * (a.ACC[x] + r);
+      a.U[x] = un;
+      bad |= !isfinite(un);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K_FACE: common solution and Rusanov flux, one thread per element flux point
+// ---------------------------------------------------------------------------
+// u_c - u_f (BR1 mean, far-field ghost or wall value) and the Rusanov flux at
+// flux point q, from the element's own trace uf and its partner's trace
+template <typename T, int DIM, int ORDER>
+__device__ inline void face_common(const KArgs<T> &a, const Gas<T, DIM> &gas, int64_t blk, int q, int e,
+                                   const T *uf, T *du, T *fi) {
+  using S = Shape<DIM, ORDER>;
+  T ur[S::NV], n[DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) n[j] = T(a.FN[at(blk, q, j, e, S::NFPAD, DIM)]);
+  const int nb = a.NB[(size_t(blk) * S::NFPAD + q) * EB + e];
+  if (nb >= 0) {
+    const size_t base = size_t(nb / EB) * S::NV * EB + (nb % EB);
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) {
+      ur[v] = a.UF[base + v * EB];
+      du[v] = T(0.5) * (ur[v] - uf[v]);
+    }
+  } else if (((-nb) & 3) == BC_FARFIELD) {
+    gas.farfield(uf, n, a.fsd + 5 * a.bdesign[blk], ur);
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) du[v] = ur[v] - uf[v];
+  } else {
+    T uc[S::NV];
+    gas.wall_common(uf, uc);
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) du[v] = uc[v] - uf[v];
+    ur[0] = uf[0];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) ur[1 + i] = -uf[1 + i];
+    ur[DIM + 1] = uf[DIM + 1];
+  }
+  gas.rusanov(uf, ur, n, fi);
+}
+
+template <typename T, int DIM, int ORDER>
+__global__ __launch_bounds__(256) void k_face(KArgs<T> a) {
+  using S = Shape<DIM, ORDER>;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int e = int(t & 15);
+  const int q = int((t >> 4) % S::NFPAD);
+  const int64_t blk = (t >> 4) / S::NFPAD;
+  if (blk >= a.nblk || q >= S::NF || e >= a.bcount[blk]) return;
+  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
+  T uf[S::NV], du[S::NV], fi[S::NV];
+#pragma unroll
+  for (int v = 0; v < S::NV; ++v) uf[v] = a.UF[at(blk, q, v, e, S::NFPAD, S::NV)];
+  face_common<T, DIM, ORDER>(a, gas, blk, q, e, uf, du, fi);
+#pragma unroll
+  for (int v = 0; v < S::NV; ++v) {
+    a.DU[at(blk, q, v, e, S::NFPAD, S::NV)] = du[v];
+    a.FI[at(blk, q, v, e, S::NFPAD, S::NV)] = fi[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dense-MFMA kernels: one wave = one 16-row tile of an operator x 16 elements
 // ---------------------------------------------------------------------------
 template <typename T, int DIM, int ORDER>
 __global__ __launch_bounds__(256) void k_interp(KArgs<T> a, const T *__restrict__ X) {
@@ -271,58 +509,6 @@ __global__ __launch_bounds__(256) void k_interp(KArgs<T> a, const T *__restrict_
   }
 }
 
-// ---------------------------------------------------------------------------
-// K_FACE: common solution and Rusanov flux, one thread per element flux point
-// ---------------------------------------------------------------------------
-template <typename T, int DIM, int ORDER>
-__global__ __launch_bounds__(256) void k_face(KArgs<T> a) {
-  using S = Shape<DIM, ORDER>;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int e = int(t & 15);
-  const int q = int((t >> 4) % S::NFPAD);
-  const int64_t blk = (t >> 4) / S::NFPAD;
-  if (blk >= a.nblk || q >= S::NF || e >= a.bcount[blk]) return;
-  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
-  T uf[S::NV], ur[S::NV], du[S::NV], fi[S::NV], n[DIM];
-#pragma unroll
-  for (int v = 0; v < S::NV; ++v) uf[v] = a.UF[at(blk, q, v, e, S::NFPAD, S::NV)];
-#pragma unroll
-  for (int j = 0; j < DIM; ++j) n[j] = T(a.FN[at(blk, q, j, e, S::NFPAD, DIM)]);
-  const int nb = a.NB[(size_t(blk) * S::NFPAD + q) * EB + e];
-  if (nb >= 0) {
-    const size_t base = size_t(nb / EB) * S::NV * EB + (nb % EB);
-#pragma unroll
-    for (int v = 0; v < S::NV; ++v) {
-      ur[v] = a.UF[base + v * EB];
-      du[v] = T(0.5) * (ur[v] - uf[v]);
-    }
-    gas.rusanov(uf, ur, n, fi);
-  } else if (((-nb) & 3) == BC_FARFIELD) {
-    gas.farfield(uf, n, a.fsd + 5 * a.bdesign[blk], ur);
-#pragma unroll
-    for (int v = 0; v < S::NV; ++v) du[v] = ur[v] - uf[v];
-    gas.rusanov(uf, ur, n, fi);
-  } else {
-    T uc[S::NV];
-    gas.wall_common(uf, uc);
-#pragma unroll
-    for (int v = 0; v < S::NV; ++v) du[v] = uc[v] - uf[v];
-    ur[0] = uf[0];
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) ur[1 + i] = -uf[1 + i];
-    ur[DIM + 1] = uf[DIM + 1];
-    gas.rusanov(uf, ur, n, fi);
-  }
-#pragma unroll
-  for (int v = 0; v < S::NV; ++v) {
-    a.DU[at(blk, q, v, e, S::NFPAD, S::NV)] = du[v];
-    a.FI[at(blk, q, v, e, S::NFPAD, S::NV)] = fi[v];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// K_GRAD: corrected gradient -> physical gradient -> transformed flux
-// ---------------------------------------------------------------------------
 template <typename T, int DIM, int ORDER>
 __global__ __launch_bounds__(256) void k_grad(KArgs<T> a, const T *__restrict__ X) {
   using S = Shape<DIM, ORDER>;
@@ -372,47 +558,17 @@ __global__ __launch_bounds__(256) void k_grad(KArgs<T> a, const T *__restrict__ 
   for (int j = 0; j < 4; ++j) {
     const int i = rt * 16 + M::row(g, j);
     if (i >= S::NU) break;
-    T u[S::NV];
+    T u[S::NV], G[DIM][S::NV];
 #pragma unroll
     for (int v = 0; v < S::NV; ++v) u[v] = Xb[(i * S::NV + v) * EB + e];
-    double Sm[DIM][DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k)
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) Sm[k][c] = a.SM[at(blk, i, k * DIM + c, e, S::NUP, DIM * DIM)];
-    const double ij = a.IJ[(size_t(blk) * S::NUP + i) * EB + e];
-    T gu[DIM][S::NV];
-#pragma unroll
-    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-      for (int v = 0; v < S::NV; ++v) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) s += Sm[k][c] * double(acc[k][v][j]);
-        gu[c][v] = T(s * ij);
-      }
-    T Fi[DIM][S::NV], Fv[DIM][S::NV];
-    gas.flux_inv(u, Fi);
-    gas.flux_vis(u, gu, Fv, false);
-#pragma unroll
-    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-      for (int v = 0; v < S::NV; ++v) a.GU[at(blk, i, c * S::NV + v, e, S::NUP, S::NG)] = gu[c][v];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k)
-#pragma unroll
-      for (int v = 0; v < S::NV; ++v) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) s += Sm[k][c] * double(Fi[c][v] - Fv[c][v]);
-        a.FT[at(blk, i, k * S::NV + v, e, S::NUP, S::NG)] = T(s);
-      }
+      for (int v = 0; v < S::NV; ++v) G[k][v] = acc[k][v][j];
+    grad_epilogue<T, DIM, ORDER>(a, gas, blk, i, e, u, G);
   }
 }
 
-// ---------------------------------------------------------------------------
-// K_VISC: gradient trace and viscous common-flux parts at flux points
-// ---------------------------------------------------------------------------
 template <typename T, int DIM, int ORDER>
 __global__ __launch_bounds__(256) void k_visc(KArgs<T> a, int forces) {
   using S = Shape<DIM, ORDER>;
@@ -445,71 +601,15 @@ __global__ __launch_bounds__(256) void k_visc(KArgs<T> a, int forces) {
   for (int j = 0; j < 4; ++j) {
     const int q = rt * 16 + M::row(g, j);
     if (q >= S::NF) break;
-    T uf[S::NV], gf[DIM][S::NV], n[DIM], Fv[DIM][S::NV], pv[S::NV];
-#pragma unroll
-    for (int v = 0; v < S::NV; ++v) uf[v] = a.UF[at(blk, q, v, e, S::NFPAD, S::NV)];
-    double nd[DIM];
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-      nd[c] = a.FN[at(blk, q, c, e, S::NFPAD, DIM)];
-      n[c] = T(nd[c]);
-    }
+    T gf[DIM][S::NV];
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
 #pragma unroll
       for (int v = 0; v < S::NV; ++v) gf[c][v] = acc[c][v][j];
-    const int nb = a.NB[(size_t(blk) * S::NFPAD + q) * EB + e];
-    if (nb >= 0) {
-      gas.flux_vis(uf, gf, Fv, false);
-#pragma unroll
-      for (int v = 0; v < S::NV; ++v) {
-        T s = 0;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) s += Fv[c][v] * n[c];
-        pv[v] = T(0.5) * s;
-      }
-    } else {
-      const int code = -nb;
-      T ub[S::NV];
-      if ((code & 3) == BC_FARFIELD) {
-        gas.farfield(uf, n, a.fsd + 5 * a.bdesign[blk], ub);
-        gas.flux_vis(ub, gf, Fv, false);
-      } else {
-        gas.wall_common(uf, ub);
-        gas.flux_vis(ub, gf, Fv, true);
-      }
-#pragma unroll
-      for (int v = 0; v < S::NV; ++v) {
-        T s = 0;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) s += Fv[c][v] * n[c];
-        pv[v] = a.FI[at(blk, q, v, e, S::NFPAD, S::NV)] - s;
-      }
-      if (forces && (code & 3) == BC_WALL) {
-        // traction of the fluid on the body: W A (p n - tau . n), interior trace
-        T Fw[DIM][S::NV];
-        gas.flux_vis(uf, gf, Fw, false);
-        const double p = double(gas.pressure(uf));
-        const double wA = a.wface[q] * a.FA[(size_t(blk) * S::NFPAD + q) * EB + e];
-        const int64_t w = code >> 2;
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) {
-          double tn = 0.0;
-#pragma unroll
-          for (int c = 0; c < DIM; ++c) tn += double(Fw[c][1 + i]) * nd[c];
-          a.FC[w * 3 + i] = wA * (p * nd[i] - tn);
-        }
-        if (DIM == 2) a.FC[w * 3 + 2] = 0.0;
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < S::NV; ++v) a.PV[at(blk, q, v, e, S::NFPAD, S::NV)] = pv[v];
+    visc_epilogue<T, DIM, ORDER>(a, gas, blk, q, e, gf, forces);
   }
 }
 
-// ---------------------------------------------------------------------------
-// K_DIVRK: corrected divergence, residual, fused RK4 stage
-// ---------------------------------------------------------------------------
 template <typename T, int DIM, int ORDER>
 __global__ __launch_bounds__(256) void k_divrk(KArgs<T> a, int mode) {
   using S = Shape<DIM, ORDER>;
@@ -542,57 +642,669 @@ __global__ __launch_bounds__(256) void k_divrk(KArgs<T> a, int mode) {
     T b[S::NV];
 #pragma unroll
     for (int v = 0; v < S::NV; ++v) b[v] = 0;
-    if (q < S::NF && e < nvalid) {
-      const size_t fq = (size_t(blk) * S::NFPAD + q) * EB + e;
-      const int nb = a.NB[fq];
-      const double A = a.FA[fq];
-      if (nb >= 0) {
-        const size_t base = size_t(nb / EB) * S::NV * EB + (nb % EB);
-#pragma unroll
-        for (int v = 0; v < S::NV; ++v) {
-          const T f = a.FI[at(blk, q, v, e, S::NFPAD, S::NV)] - a.PV[at(blk, q, v, e, S::NFPAD, S::NV)] +
-                      a.PV[base + v * EB];
-          b[v] = T(A * double(f));
-        }
-      } else {
-#pragma unroll
-        for (int v = 0; v < S::NV; ++v) b[v] = T(A * double(a.PV[at(blk, q, v, e, S::NFPAD, S::NV)]));
-      }
-    }
+    if (q < S::NF && e < nvalid) common_flux<T, DIM, ORDER>(a, blk, q, e, b);
 #pragma unroll
     for (int v = 0; v < S::NV; ++v) acc[v] = M::mac(av, b[v], acc[v]);
   }
   if (e >= nvalid) return;
-  const T dt = T(a.bdt[blk]);
   int bad = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int i = rt * 16 + M::row(g, j);
     if (i >= S::NU) break;
-    const double ij = a.IJ[(size_t(blk) * S::NUP + i) * EB + e];
+    T div[S::NV];
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) div[v] = acc[v][j];
+    rk_epilogue<T, DIM, ORDER>(a, blk, i, e, div, mode, bad);
+  }
+  if (bad) atomicOr(a.flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// sum-factorised kernels: a workgroup stages the inputs of EW elements in LDS
+// ([point][channel][EW], element fastest) and applies the 1D operators along
+// the solution-point lines; outputs and epilogues are those of the dense kernels
+// ---------------------------------------------------------------------------
+template <typename T, int DIM, int ORDER> struct TS {
+  using S = Shape<DIM, ORDER>;
+  static constexpr int ew(int bytes) {
+    return bytes * 16 <= 65536 ? 16 : bytes * 8 <= 65536 ? 8 : bytes * 4 <= 65536 ? 4 : 2;
+  }
+  static constexpr int EW_INTERP = ew(S::NU * S::NV * int(sizeof(T)));
+  static constexpr int EW_GRAD = ew((S::NU + S::NF) * S::NV * int(sizeof(T)));
+  static constexpr int EW_VISC = ew(S::NU * S::NG * int(sizeof(T)));
+  static constexpr int EW_DIV = ew((S::NU * S::NG + S::NF * S::NV) * int(sizeof(T)));
+};
+
+// 1D basis in LDS: D[N][N], l(-1)[N], l(+1)[N], gL'[N], gR'[N]
+template <typename T, int N> struct Basis {
+  T D[N][N], lm[N], lp[N], gl[N], gr[N];
+  __device__ inline void load(const T *src) {
+    for (int t = threadIdx.x; t < N * N + 4 * N; t += blockDim.x) {
+      if (t < N * N) D[t / N][t % N] = src[t];
+      else if (t < N * N + N) lm[t - N * N] = src[t];
+      else if (t < N * N + 2 * N) lp[t - N * N - N] = src[t];
+      else if (t < N * N + 3 * N) gl[t - N * N - 2 * N] = src[t];
+      else gr[t - N * N - 3 * N] = src[t];
+    }
+  }
+};
+
+// copy channels [0, NCH) of points [0, NPT) of EW elements starting at slot e0 into LDS
+template <typename T, int NPT, int NPTG, int NCH, int EW>
+__device__ inline void stage_in(T *dst, const T *src_blk, int e0) {
+  for (int t = threadIdx.x; t < NPT * NCH * EW; t += blockDim.x) {
+    const int e = t % EW, pc = t / EW;
+    dst[t] = src_blk[size_t(pc) * EB + e0 + e];
+  }
+}
+
+template <typename T, int DIM, int ORDER>
+__global__ __launch_bounds__(256) void t_interp(KArgs<T> a, const T *__restrict__ X) {
+  using S = Shape<DIM, ORDER>;
+  constexpr int EW = TS<T, DIM, ORDER>::EW_INTERP, NS = EB / EW, N = S::N;
+  __shared__ T Us[S::NU * S::NV * EW];
+  __shared__ Basis<T, N> B;
+  const int64_t blk = blockIdx.x / NS;
+  const int e0 = int(blockIdx.x % NS) * EW;
+  const int nvalid = a.bcount[blk];
+  if (e0 >= nvalid) return;
+  B.load(a.basis);
+  stage_in<T, S::NU, S::NUP, S::NV, EW>(Us, X + size_t(blk) * S::NUP * S::NV * EB, e0);
+  __syncthreads();
+  for (int t = threadIdx.x; t < S::NF * EW; t += blockDim.x) {
+    const int e = t % EW, q = t / EW;
+    if (e0 + e >= nvalid) continue;
+    const int f = q / S::NFP, m = q % S::NFP, k = f / 2;
+    const T *l = (f & 1) ? B.lp : B.lm;
 #pragma unroll
     for (int v = 0; v < S::NV; ++v) {
-      const size_t x = at(blk, i, v, e, S::NUP, S::NV);
-      const T r = T(-double(acc[v][j]) * ij);
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += l[j] * Us[(Ref<DIM, N>::line(k, m, j) * S::NV + v) * EW + e];
+      a.UF[at(blk, q, v, e0 + e, S::NFPAD, S::NV)] = s;
+    }
+  }
+}
+
+template <typename T, int DIM, int ORDER>
+__global__ __launch_bounds__(256) void t_grad(KArgs<T> a, const T *__restrict__ X) {
+  using S = Shape<DIM, ORDER>;
+  constexpr int EW = TS<T, DIM, ORDER>::EW_GRAD, NS = EB / EW, N = S::N;
+  __shared__ T Us[S::NU * S::NV * EW];
+  __shared__ T Ds[S::NF * S::NV * EW];
+  __shared__ Basis<T, N> B;
+  const int64_t blk = blockIdx.x / NS;
+  const int e0 = int(blockIdx.x % NS) * EW;
+  const int nvalid = a.bcount[blk];
+  if (e0 >= nvalid) return;
+  B.load(a.basis);
+  stage_in<T, S::NU, S::NUP, S::NV, EW>(Us, X + size_t(blk) * S::NUP * S::NV * EB, e0);
+  stage_in<T, S::NF, S::NFPAD, S::NV, EW>(Ds, a.DU + size_t(blk) * S::NFPAD * S::NV * EB, e0);
+  __syncthreads();
+  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
+  for (int t = threadIdx.x; t < S::NU * EW; t += blockDim.x) {
+    const int e = t % EW, i = t / EW;
+    if (e0 + e >= nvalid) continue;
+    T G[DIM][S::NV], u[S::NV];
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) u[v] = Us[(i * S::NV + v) * EW + e];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      int ik, m;
+      Ref<DIM, N>::locate(i, k, ik, m);
+      const int qp = (2 * k + 1) * S::NFP + m, qm = 2 * k * S::NFP + m;
+#pragma unroll
+      for (int v = 0; v < S::NV; ++v) {
+        T s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += B.D[ik][j] * Us[(Ref<DIM, N>::line(k, m, j) * S::NV + v) * EW + e];
+        s += B.gr[ik] * Ds[(qp * S::NV + v) * EW + e] + B.gl[ik] * Ds[(qm * S::NV + v) * EW + e];
+        G[k][v] = s;
+      }
+    }
+    grad_epilogue<T, DIM, ORDER>(a, gas, blk, i, e0 + e, u, G);
+  }
+}
+
+template <typename T, int DIM, int ORDER>
+__global__ __launch_bounds__(256) void t_visc(KArgs<T> a, int forces) {
+  using S = Shape<DIM, ORDER>;
+  constexpr int EW = TS<T, DIM, ORDER>::EW_VISC, NS = EB / EW, N = S::N;
+  __shared__ T Gs[S::NU * S::NG * EW];
+  __shared__ Basis<T, N> B;
+  const int64_t blk = blockIdx.x / NS;
+  const int e0 = int(blockIdx.x % NS) * EW;
+  const int nvalid = a.bcount[blk];
+  if (e0 >= nvalid) return;
+  B.load(a.basis);
+  stage_in<T, S::NU, S::NUP, S::NG, EW>(Gs, a.GU + size_t(blk) * S::NUP * S::NG * EB, e0);
+  __syncthreads();
+  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
+  for (int t = threadIdx.x; t < S::NF * EW; t += blockDim.x) {
+    const int e = t % EW, q = t / EW;
+    if (e0 + e >= nvalid) continue;
+    const int f = q / S::NFP, m = q % S::NFP, k = f / 2;
+    const T *l = (f & 1) ? B.lp : B.lm;
+    T gf[DIM][S::NV];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+      for (int v = 0; v < S::NV; ++v) {
+        T s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += l[j] * Gs[(Ref<DIM, N>::line(k, m, j) * S::NG + c * S::NV + v) * EW + e];
+        gf[c][v] = s;
+      }
+    visc_epilogue<T, DIM, ORDER>(a, gas, blk, q, e0 + e, gf, forces);
+  }
+}
+
+template <typename T, int DIM, int ORDER>
+__global__ __launch_bounds__(256) void t_divrk(KArgs<T> a, int mode) {
+  using S = Shape<DIM, ORDER>;
+  constexpr int EW = TS<T, DIM, ORDER>::EW_DIV, NS = EB / EW, N = S::N;
+  __shared__ T Fs[S::NU * S::NG * EW];
+  __shared__ T Cs[S::NF * S::NV * EW];
+  __shared__ Basis<T, N> B;
+  const int64_t blk = blockIdx.x / NS;
+  const int e0 = int(blockIdx.x % NS) * EW;
+  const int nvalid = a.bcount[blk];
+  if (e0 >= nvalid) return;
+  B.load(a.basis);
+  stage_in<T, S::NU, S::NUP, S::NG, EW>(Fs, a.FT + size_t(blk) * S::NUP * S::NG * EB, e0);
+  for (int t = threadIdx.x; t < S::NF * EW; t += blockDim.x) {
+    const int e = t % EW, q = t / EW;
+    T b[S::NV];
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) b[v] = 0;
+    if (e0 + e < nvalid) common_flux<T, DIM, ORDER>(a, blk, q, e0 + e, b);
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) Cs[(q * S::NV + v) * EW + e] = b[v];
+  }
+  __syncthreads();
+  int bad = 0;
+  for (int t = threadIdx.x; t < S::NU * EW; t += blockDim.x) {
+    const int e = t % EW, i = t / EW;
+    if (e0 + e >= nvalid) continue;
+    T div[S::NV];
+#pragma unroll
+    for (int v = 0; v < S::NV; ++v) div[v] = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      int ik, m;
+      Ref<DIM, N>::locate(i, k, ik, m);
+      const int qp = (2 * k + 1) * S::NFP + m, qm = 2 * k * S::NFP + m;
+#pragma unroll
+      for (int v = 0; v < S::NV; ++v) {
+        T d = 0, fp = 0, fm = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          const T f = Fs[(Ref<DIM, N>::line(k, m, j) * S::NG + k * S::NV + v) * EW + e];
+          d += B.D[ik][j] * f;
+          fp += B.lp[j] * f;
+          fm += B.lm[j] * f;
+        }
+        // outward discontinuous normal flux: +F~_k at xi_k = +1, -F~_k at xi_k = -1
+        div[v] += d + B.gr[ik] * (Cs[(qp * S::NV + v) * EW + e] - fp) -
+                  B.gl[ik] * (Cs[(qm * S::NV + v) * EW + e] + fm);
+      }
+    }
+    rk_epilogue<T, DIM, ORDER>(a, blk, i, e0 + e, div, mode, bad);
+  }
+  if (bad) atomicOr(a.flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// fused stage: two launches per RK stage, sum-factorised, LDS-staged
+//
+//   k_stage_a: trace and common solution, Rusanov flux, corrected gradient,
+//              transformed flux, gradient trace and viscous half-flux, volume
+//              divergence (interpolated normal-flux correction included);
+//              writes Q = F_I* - P (or the whole boundary common flux), P, RV
+//   k_stage_b: transformed common flux A (Q + P_partner), flux correction,
+//              R = -(RV + corr)/|J|, RK4 stage, trace of the next stage state
+//
+// Workgroups are mapped so that the EB/EW sub-blocks of one element block,
+// and neighbouring blocks, run on the same XCD (dispatch is round-robin over
+// the 8 XCDs), keeping partner traces and shared segments in one L2.
+// ---------------------------------------------------------------------------
+__device__ inline int64_t xcd_remap(int64_t wg, int64_t nwg) {
+  const int64_t full = nwg / 8 * 8;
+  return wg < full ? (wg % 8) * (nwg / 8) + wg / 8 : wg;
+}
+
+template <typename T, int DIM, int ORDER> struct FS {
+  using S = Shape<DIM, ORDER>;
+  static constexpr int ew(int bytes, int budget) {
+    return bytes * 16 <= budget ? 16 : bytes * 8 <= budget ? 8 : bytes * 4 <= budget ? 4 : bytes * 2 <= budget ? 2 : 1;
+  }
+  // stage a: max(state + jumps, gradient + transformed flux) per element (aliased)
+  static constexpr int LDS_A_ELEM = (S::NU * S::NV + S::NF * S::NV) > 2 * S::NU * S::NG
+                                        ? (S::NU * S::NV + S::NF * S::NV) : 2 * S::NU * S::NG;
+  static constexpr int EW_A = ew(LDS_A_ELEM * int(sizeof(T)), 40960);
+  static constexpr int WG_A = S::NU * EW_A >= 256 ? 256 : (S::NU * EW_A + 63) / 64 * 64;
+  // stage b: common flux at faces and the new state
+  static constexpr int EW_B = ew((S::NF * S::NV + S::NU * S::NV) * int(sizeof(T)), 32768);
+  static constexpr int WG_B = S::NU * EW_B >= 256 ? 256 : (S::NU * EW_B + 63) / 64 * 64;
+};
+
+template <typename T, int DIM, int ORDER>
+__global__ __launch_bounds__(256) void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
+  using S = Shape<DIM, ORDER>;
+  using F = FS<T, DIM, ORDER>;
+  constexpr int EW = F::EW_A, WG = F::WG_A, NS = EB / EW, N = S::N, NV = S::NV, NG = S::NG;
+  constexpr int FI = (S::NF * EW + WG - 1) / WG, PI = (S::NU * EW + WG - 1) / WG;
+  // LDS: [state | jumps] while the gradient is formed, then [gradient | flux]
+  __shared__ T L[F::LDS_A_ELEM * EW];
+  T *Us = L, *Ds = L + S::NU * NV * EW;
+  T *Gs = L, *Fs = L + S::NU * NG * EW;
+  __shared__ Basis<T, N> B;
+  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t blk = wg / NS;
+  const int e0 = int(wg % NS) * EW;
+  const int nvalid = a.bcount[blk];
+  if (e0 >= nvalid) return;
+  const int tid = threadIdx.x;
+
+  // ---- prefetch everything that does not depend on LDS
+  int nbv[FI];
+  T nrm[FI][DIM], ur[FI][NV];
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
+    nbv[it] = -BC_FARFIELD;
+    if (t < S::NF * EW && eg < nvalid) {
+      nbv[it] = a.NB[(size_t(blk) * S::NFPAD + q) * EB + eg];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) nrm[it][c] = T(a.FN[at(blk, q, c, eg, S::NFPAD, DIM)]);
+    }
+  }
+  double Sm[PI][DIM][DIM], ijv[PI];
+#pragma unroll
+  for (int it = 0; it < PI; ++it) {
+    const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
+    if (t < S::NU * EW && eg < nvalid) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) Sm[it][k][c] = a.SM[at(blk, i, k * DIM + c, eg, S::NUP, DIM * DIM)];
+      ijv[it] = a.IJ[(size_t(blk) * S::NUP + i) * EB + eg];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    if (nbv[it] >= 0) {
+      const size_t base = size_t(nbv[it] / EB) * NV * EB + (nbv[it] % EB);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ur[it][v] = a.UF[base + v * EB];
+    }
+  }
+  B.load(a.basis);
+  stage_in<T, S::NU, S::NUP, NV, EW>(Us, X + size_t(blk) * S::NUP * NV * EB, e0);
+  __syncthreads();
+  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
+
+  // ---- faces: own trace, common solution jump (LDS), Rusanov flux (registers)
+  T ufv[FI][NV], fiv[FI][NV];
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
+    if (t >= S::NF * EW) break;
+    T du[NV];
+    if (eg < nvalid) {
+      const int f = q / S::NFP, m = q % S::NFP, k = f / 2;
+      const T *l = (f & 1) ? B.lp : B.lm;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T sv = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) sv += l[j] * Us[(Ref<DIM, N>::line(k, m, j) * NV + v) * EW + e];
+        ufv[it][v] = sv;
+      }
+      const int nb = nbv[it];
+      T ub[NV];
+      if (nb >= 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          ub[v] = ur[it][v];
+          du[v] = T(0.5) * (ub[v] - ufv[it][v]);
+        }
+      } else if (((-nb) & 3) == BC_FARFIELD) {
+        gas.farfield(ufv[it], nrm[it], a.fsd + 5 * a.bdesign[blk], ub);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) du[v] = ub[v] - ufv[it][v];
+      } else {
+        T uc[NV];
+        gas.wall_common(ufv[it], uc);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) du[v] = uc[v] - ufv[it][v];
+        ub[0] = ufv[it][0];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) ub[1 + c] = -ufv[it][1 + c];
+        ub[DIM + 1] = ufv[it][DIM + 1];
+      }
+      gas.rusanov(ufv[it], ub, nrm[it], fiv[it]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) du[v] = 0;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Ds[(q * NV + v) * EW + e] = du[v];
+  }
+  __syncthreads();
+
+  // ---- solution points: corrected reference gradient (registers), then LDS is reused
+  T Gr[PI][DIM][NV], ui[PI][NV];
+#pragma unroll
+  for (int it = 0; it < PI; ++it) {
+    const int t = tid + it * WG, e = t % EW, i = t / EW;
+    if (t >= S::NU * EW) break;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ui[it][v] = Us[(i * NV + v) * EW + e];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      int ik, m;
+      Ref<DIM, N>::locate(i, k, ik, m);
+      const int qp = (2 * k + 1) * S::NFP + m, qm = 2 * k * S::NFP + m;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T sv = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) sv += B.D[ik][j] * Us[(Ref<DIM, N>::line(k, m, j) * NV + v) * EW + e];
+        sv += B.gr[ik] * Ds[(qp * NV + v) * EW + e] + B.gl[ik] * Ds[(qm * NV + v) * EW + e];
+        Gr[it][k][v] = sv;
+      }
+    }
+  }
+  __syncthreads();
+  // physical gradient and transformed flux into the aliased LDS
+#pragma unroll
+  for (int it = 0; it < PI; ++it) {
+    const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
+    if (t >= S::NU * EW) break;
+    if (eg >= nvalid) {
+#pragma unroll
+      for (int c = 0; c < NG; ++c) Gs[(i * NG + c) * EW + e] = Fs[(i * NG + c) * EW + e] = 0;
+      continue;
+    }
+    T gu[DIM][NV];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double sg = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) sg += Sm[it][k][c] * double(Gr[it][k][v]);
+        gu[c][v] = T(sg * ijv[it]);
+        Gs[(i * NG + c * NV + v) * EW + e] = gu[c][v];
+      }
+    T Fi[DIM][NV], Fv[DIM][NV];
+    gas.flux_inv(ui[it], Fi);
+    gas.flux_vis(ui[it], gu, Fv, false);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double sf = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) sf += Sm[it][k][c] * double(Fi[c][v] - Fv[c][v]);
+        Fs[(i * NG + k * NV + v) * EW + e] = T(sf);
+      }
+  }
+  __syncthreads();
+
+  // ---- flux points: gradient trace, viscous half-flux P, Q = F_I* - P (boundary: full flux)
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
+    if (t >= S::NF * EW) break;
+    if (eg >= nvalid) continue;
+    const int f = q / S::NFP, m = q % S::NFP, k = f / 2;
+    const T *l = (f & 1) ? B.lp : B.lm;
+    T gf[DIM][NV], Fv[DIM][NV];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T sv = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) sv += l[j] * Gs[(Ref<DIM, N>::line(k, m, j) * NG + c * NV + v) * EW + e];
+        gf[c][v] = sv;
+      }
+    const int nb = nbv[it];
+    if (nb >= 0) {
+      gas.flux_vis(ufv[it], gf, Fv, false);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T sv = 0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) sv += Fv[c][v] * nrm[it][c];
+        const T pv = T(0.5) * sv;
+        a.PV[at(blk, q, v, eg, S::NFPAD, NV)] = pv;
+        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = fiv[it][v] - pv;
+      }
+    } else {
+      const int code = -nb;
+      T ub[NV];
+      if ((code & 3) == BC_FARFIELD) {
+        gas.farfield(ufv[it], nrm[it], a.fsd + 5 * a.bdesign[blk], ub);
+        gas.flux_vis(ub, gf, Fv, false);
+      } else {
+        gas.wall_common(ufv[it], ub);
+        gas.flux_vis(ub, gf, Fv, true);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T sv = 0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) sv += Fv[c][v] * nrm[it][c];
+        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = fiv[it][v] - sv;
+      }
+      if (forces && (code & 3) == BC_WALL) {
+        // traction of the fluid on the body: W A (p n - tau . n), interior trace
+        T Fw[DIM][NV];
+        gas.flux_vis(ufv[it], gf, Fw, false);
+        double nd[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) nd[c] = a.FN[at(blk, q, c, eg, S::NFPAD, DIM)];
+        const double p = double(gas.pressure(ufv[it]));
+        const double wA = a.wface[q] * a.FA[(size_t(blk) * S::NFPAD + q) * EB + eg];
+        const int64_t w = code >> 2;
+#pragma unroll
+        for (int ii = 0; ii < DIM; ++ii) {
+          double tn = 0.0;
+#pragma unroll
+          for (int c = 0; c < DIM; ++c) tn += double(Fw[c][1 + ii]) * nd[c];
+          a.FC[w * 3 + ii] = wA * (p * nd[ii] - tn);
+        }
+        if (DIM == 2) a.FC[w * 3 + 2] = 0.0;
+      }
+    }
+  }
+
+  // ---- solution points: volume divergence with the interpolated normal-flux correction
+#pragma unroll
+  for (int it = 0; it < PI; ++it) {
+    const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
+    if (t >= S::NU * EW) break;
+    if (eg >= nvalid) continue;
+    T div[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) div[v] = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      int ik, m;
+      Ref<DIM, N>::locate(i, k, ik, m);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T d = 0, fp = 0, fm = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          const T fv = Fs[(Ref<DIM, N>::line(k, m, j) * NG + k * NV + v) * EW + e];
+          d += B.D[ik][j] * fv;
+          fp += B.lp[j] * fv;
+          fm += B.lm[j] * fv;
+        }
+        div[v] += d - B.gr[ik] * fp - B.gl[ik] * fm;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a.FT[at(blk, i, v, eg, S::NUP, NV)] = div[v];
+  }
+}
+
+template <typename T, int DIM, int ORDER>
+__global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a, int mode) {
+  using S = Shape<DIM, ORDER>;
+  using F = FS<T, DIM, ORDER>;
+  constexpr int EW = F::EW_B, WG = F::WG_B, NS = EB / EW, N = S::N, NV = S::NV;
+  constexpr int FI = (S::NF * EW + WG - 1) / WG, PI = (S::NU * EW + WG - 1) / WG;
+  __shared__ T Cs[S::NF * NV * EW];
+  __shared__ T Un[S::NU * NV * EW];
+  __shared__ Basis<T, N> B;
+  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t blk = wg / NS;
+  const int e0 = int(wg % NS) * EW;
+  const int nvalid = a.bcount[blk];
+  if (e0 >= nvalid) return;
+  const int tid = threadIdx.x;
+  const T dt = T(a.bdt[blk]);
+
+  // ---- prefetch: face inputs, then point inputs
+  int nbv[FI];
+  double Av[FI];
+  T qv[FI][NV], pn[FI][NV];
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
+    nbv[it] = -BC_FARFIELD;
+    Av[it] = 0.0;
+    if (t < S::NF * EW && eg < nvalid) {
+      const size_t fq = (size_t(blk) * S::NFPAD + q) * EB + eg;
+      nbv[it] = a.NB[fq];
+      Av[it] = a.FA[fq];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qv[it][v] = a.FI[at(blk, q, v, eg, S::NFPAD, NV)];
+    }
+  }
+  T rv[PI][NV], un[PI][NV], ac[PI][NV];
+  double ijv[PI];
+#pragma unroll
+  for (int it = 0; it < PI; ++it) {
+    const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
+    if (t < S::NU * EW && eg < nvalid) {
+      ijv[it] = a.IJ[(size_t(blk) * S::NUP + i) * EB + eg];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const size_t x = at(blk, i, v, eg, S::NUP, NV);
+        rv[it][v] = a.FT[x];
+        un[it][v] = mode == MODE_RESID ? T(0) : a.U[x];
+        ac[it][v] = (mode == MODE_RK1 || mode == MODE_RK2 || mode == MODE_RK3) ? a.ACC[x] : T(0);
+      }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    if (nbv[it] >= 0) {
+      const size_t base = size_t(nbv[it] / EB) * NV * EB + (nbv[it] % EB);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[base + v * EB];
+    }
+  }
+  B.load(a.basis);
+
+  // ---- transformed outward common flux A (Q + P_partner), boundary: A Q
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
+    if (t >= S::NF * EW) break;
+    T b[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) b[v] = 0;
+    if (eg < nvalid) {
+      if (nbv[it] >= 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) b[v] = T(Av[it] * double(qv[it][v] + pn[it][v]));
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) b[v] = T(Av[it] * double(qv[it][v]));
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Cs[(q * NV + v) * EW + e] = b[v];
+  }
+  __syncthreads();
+
+  // ---- R = -(RV + corrections)/|J| and the RK4 stage
+  int bad = 0;
+#pragma unroll
+  for (int it = 0; it < PI; ++it) {
+    const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
+    if (t >= S::NU * EW) break;
+    if (eg >= nvalid) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Un[(i * NV + v) * EW + e] = 0;
+      continue;
+    }
+    T div[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) div[v] = rv[it][v];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      int ik, m;
+      Ref<DIM, N>::locate(i, k, ik, m);
+      const int qp = (2 * k + 1) * S::NFP + m, qm = 2 * k * S::NFP + m;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) div[v] += B.gr[ik] * Cs[(qp * NV + v) * EW + e] - B.gl[ik] * Cs[(qm * NV + v) * EW + e];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const size_t x = at(blk, i, v, eg, S::NUP, NV);
+      const T r = T(-double(div[v]) * ijv[it]);
+      T next = 0;
       if (mode == MODE_RESID) {
         a.RES[x] = r;
       } else if (mode == MODE_RK0) {
         a.ACC[x] = r;
-        a.US[x] = a.U[x] + T(0.5) * dt * r;
+        next = un[it][v] + T(0.5) * dt * r;
+        a.US[x] = next;
       } else if (mode == MODE_RK1) {
-        a.ACC[x] += T(2) * r;
-        a.US[x] = a.U[x] + T(0.5) * dt * r;
+        a.ACC[x] = ac[it][v] + T(2) * r;
+        next = un[it][v] + T(0.5) * dt * r;
+        a.US[x] = next;
       } else if (mode == MODE_RK2) {
-        a.ACC[x] += T(2) * r;
-        a.US[x] = a.U[x] + dt * r;
+        a.ACC[x] = ac[it][v] + T(2) * r;
+        next = un[it][v] + dt * r;
+        a.US[x] = next;
       } else {
-        const T un = a.U[x] + dt / T(6) * (a.ACC[x] + r);
-        a.U[x] = un;
-        bad |= !isfinite(un);
+        next = un[it][v] + dt / T(6) * (ac[it][v] + r);
+        a.U[x] = next;
+        bad |= !isfinite(next);
       }
+      Un[(i * NV + v) * EW + e] = next;
     }
   }
   if (bad) atomicOr(a.flag, 1);
+  if (mode == MODE_RESID) return;
+  __syncthreads();
+
+  // ---- trace of the next stage input at the flux points
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
+    if (t >= S::NF * EW) break;
+    if (eg >= nvalid) continue;
+    const int f = q / S::NFP, m = q % S::NFP, k = f / 2;
+    const T *l = (f & 1) ? B.lp : B.lm;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      T sv = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) sv += l[j] * Un[(Ref<DIM, N>::line(k, m, j) * NV + v) * EW + e];
+      a.UF[at(blk, q, v, eg, S::NFPAD, NV)] = sv;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -657,7 +1369,7 @@ template <typename T> static KArgs<T> make_args(const LaunchCfg &c, const DevArr
   a.U = (T *)d.U; a.US = (T *)d.US; a.ACC = (T *)d.ACC; a.UF = (T *)d.UF; a.DU = (T *)d.DU;
   a.FI = (T *)d.FI; a.GU = (T *)d.GU; a.FT = (T *)d.FT; a.PV = (T *)d.PV; a.RES = (T *)d.RES;
   a.opInt = (const T *)d.opInt; a.opGrad = (const T *)d.opGrad; a.opGcorr = (const T *)d.opGcorr;
-  a.opDivS = (const T *)d.opDivS; a.opCorr = (const T *)d.opCorr;
+  a.opDivS = (const T *)d.opDivS; a.opCorr = (const T *)d.opCorr; a.basis = (const T *)d.basis;
   a.SM = d.SM; a.IJ = d.IJ; a.FN = d.FN; a.FA = d.FA; a.bdt = d.bdt; a.fsd = d.fsd; a.wface = d.wface;
   a.FC = d.FC; a.fsum = d.fsum; a.stage64 = d.stage64;
   a.NB = d.NB; a.bcount = d.bcount; a.bdesign = d.bdesign; a.bcanon = d.bcanon; a.wall_first = d.wall_first;
@@ -671,35 +1383,51 @@ template <typename T, int DIM, int ORDER>
 static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, int stage, int mode,
                            bool forces) {
   using S = Shape<DIM, ORDER>;
+  using TT = TS<T, DIM, ORDER>;
   KArgs<T> a = make_args<T>(c, d);
   const T *X = stage == 0 ? a.U : a.US;
   const dim3 blk(256);
+  const bool tensor = (c.variant_mask >> kernel) & 1;
   switch (kernel) {
-    case K_INTERP: {
-      const int64_t waves = c.nblk * S::RTF;
-      hipLaunchKernelGGL((k_interp<T, DIM, ORDER>), dim3((waves + 3) / 4), blk, 0, c.stream, a, X);
+    case K_INTERP:
+      if (tensor)
+        hipLaunchKernelGGL((t_interp<T, DIM, ORDER>), dim3(c.nblk * (EB / TT::EW_INTERP)), blk, 0, c.stream, a, X);
+      else
+        hipLaunchKernelGGL((k_interp<T, DIM, ORDER>), dim3((c.nblk * S::RTF + 3) / 4), blk, 0, c.stream, a, X);
       break;
-    }
     case K_FACE: {
       const int64_t thr = c.nblk * S::NFPAD * EB;
       hipLaunchKernelGGL((k_face<T, DIM, ORDER>), dim3((thr + 255) / 256), blk, 0, c.stream, a);
       break;
     }
-    case K_GRAD: {
-      const int64_t waves = c.nblk * S::RTU;
-      hipLaunchKernelGGL((k_grad<T, DIM, ORDER>), dim3((waves + 3) / 4), blk, 0, c.stream, a, X);
+    case K_GRAD:
+      if (tensor)
+        hipLaunchKernelGGL((t_grad<T, DIM, ORDER>), dim3(c.nblk * (EB / TT::EW_GRAD)), blk, 0, c.stream, a, X);
+      else
+        hipLaunchKernelGGL((k_grad<T, DIM, ORDER>), dim3((c.nblk * S::RTU + 3) / 4), blk, 0, c.stream, a, X);
       break;
-    }
-    case K_VISC: {
-      const int64_t waves = c.nblk * S::RTF;
-      hipLaunchKernelGGL((k_visc<T, DIM, ORDER>), dim3((waves + 3) / 4), blk, 0, c.stream, a, int(forces));
+    case K_VISC:
+      if (tensor)
+        hipLaunchKernelGGL((t_visc<T, DIM, ORDER>), dim3(c.nblk * (EB / TT::EW_VISC)), blk, 0, c.stream, a,
+                           int(forces));
+      else
+        hipLaunchKernelGGL((k_visc<T, DIM, ORDER>), dim3((c.nblk * S::RTF + 3) / 4), blk, 0, c.stream, a,
+                           int(forces));
       break;
-    }
-    case K_DIVRK: {
-      const int64_t waves = c.nblk * S::RTU;
-      hipLaunchKernelGGL((k_divrk<T, DIM, ORDER>), dim3((waves + 3) / 4), blk, 0, c.stream, a, mode);
+    case K_STAGE_A:
+      hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER>), dim3(c.nblk * (EB / FS<T, DIM, ORDER>::EW_A)),
+                         dim3(FS<T, DIM, ORDER>::WG_A), 0, c.stream, a, X, int(forces));
       break;
-    }
+    case K_STAGE_B:
+      hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER>), dim3(c.nblk * (EB / FS<T, DIM, ORDER>::EW_B)),
+                         dim3(FS<T, DIM, ORDER>::WG_B), 0, c.stream, a, mode);
+      break;
+    case K_DIVRK:
+      if (tensor)
+        hipLaunchKernelGGL((t_divrk<T, DIM, ORDER>), dim3(c.nblk * (EB / TT::EW_DIV)), blk, 0, c.stream, a, mode);
+      else
+        hipLaunchKernelGGL((k_divrk<T, DIM, ORDER>), dim3((c.nblk * S::RTU + 3) / 4), blk, 0, c.stream, a, mode);
+      break;
     default:
       return hipErrorInvalidValue;
   }

@@ -55,7 +55,7 @@ fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
   // operators
   b += r256(size_t(RTF) * KTU * 64 * rs) + r256(size_t(dim) * RTU * KTU * 64 * rs) +
        r256(size_t(dim) * RTU * KTF * 64 * rs) + r256(size_t(RTU) * dim * KTU * 64 * rs) +
-       r256(size_t(RTU) * KTF * 64 * rs);
+       r256(size_t(RTU) * KTF * 64 * rs) + r256(size_t(D.n * D.n + 4 * D.n) * rs);
   // geometry and tables
   b += size_t(nblk) * D.nup * dim * dim * fr::EB * 8 + size_t(nblk) * D.nup * fr::EB * 8;
   b += size_t(nblk) * D.nfpad * dim * fr::EB * 8 + size_t(nblk) * D.nfpad * fr::EB * 8;

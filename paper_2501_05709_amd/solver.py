@@ -193,9 +193,24 @@ class FRMesh:
               "fr_residual")
         return r
 
+    def select_kernels(self, mask):
+        """Bit 0: fused two-launch stage.  Else bit k (2 grad, 3 visc, 4 divrk, 5 interp):
+        sum-factorised variant of that split kernel; clear: dense MFMA."""
+        check(_lib.load().fr_select_kernels(self.h, int(mask)), "fr_select_kernels")
+
+    def selected_kernels(self):
+        m = ctypes.c_int32()
+        check(_lib.load().fr_selected_kernels(self.h, ctypes.byref(m)), "fr_selected_kernels")
+        return m.value
+
+    def autotune(self, steps=3):
+        m = ctypes.c_int32()
+        check(_lib.load().fr_autotune(self.h, int(steps), ctypes.byref(m)), "fr_autotune")
+        return m.value
+
     def profile_kernels(self, steps):
-        ms = np.zeros(6)
-        n = np.zeros(6, dtype=np.int64)
+        ms = np.zeros(8)
+        n = np.zeros(8, dtype=np.int64)
         check(_lib.load().fr_profile_kernels(self.h, int(steps), ms.ctypes.data_as(_lib._dp),
                                              n.ctypes.data_as(_lib._i64p)), "fr_profile_kernels")
         return ms, n

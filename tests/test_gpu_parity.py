@@ -66,20 +66,42 @@ def case(name):
 
 
 CASES = ["vortex2d_p3", "box2d_curved_p2", "tgv_p1", "tgv_p2", "tgv_p3", "tgv_p4", "airfoil_p3", "airfoil_p2"]
+# kernel structures / operator back-ends: five launches per stage with dense
+# element-batched MFMA contractions or sum factorisation, or the fused
+# two-launch stage (sum factorised)
+VARIANTS = {"dense": 0, "tensor": (1 << 2) | (1 << 3) | (1 << 4) | (1 << 5), "fused": 1 | (1 << 5)}
 
 
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
 @pytest.mark.parametrize("name", CASES)
-def test_residual_fp64_matches_oracle(name):
+def test_residual_fp64_matches_oracle(name, variant):
     m = case(name)
     o = OracleMesh(m)
     u = perturbed(o, m)
     ref = o.residual(u)
     g = FRMesh(m, "fp64")
+    g.select_kernels(VARIANTS[variant])
+    assert g.selected_kernels() == VARIANTS[variant]
     assert np.array_equal(g.neighbours(), o.neighbours())
     r = g.residual(u)
     err = rel_err(r, ref)
-    print(f"{name}: fp64 residual rel L2 {err:.3e}")
+    print(f"{name} {variant}: fp64 residual rel L2 {err:.3e}")
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-4)])
+def test_variants_agree_and_mix(prec, tol):
+    """Every per-kernel mix of the two back-ends gives the same residual to round-off
+    (FP32: the residual amplifies the flux rounding, as in the FP32-vs-oracle test)."""
+    m = case("airfoil_p3")
+    o = OracleMesh(m)
+    u = perturbed(o, m)
+    g = FRMesh(m, prec)
+    g.select_kernels(0)
+    ref = g.residual(u)
+    for mask in (VARIANTS["tensor"], VARIANTS["fused"], 1, 1 << 2, (1 << 3) | (1 << 5), 1 << 4):
+        g.select_kernels(mask)
+        assert rel_err(g.residual(u), ref) <= tol, mask
 
 
 @pytest.mark.parametrize("name", ["vortex2d_p3", "tgv_p3", "airfoil_p3"])
@@ -97,7 +119,8 @@ def test_residual_fp32_close_to_oracle(name):
     assert err <= 1e-3
 
 
-def test_vortex_state_after_100_steps():
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_vortex_state_after_100_steps(variant):
     """Isentropic vortex, 16x16 periodic quads, p = 3, 100 RK4 steps of 1e-3."""
     m = W.config_vortex(0)
     o = OracleMesh(m)
@@ -105,20 +128,23 @@ def test_vortex_state_after_100_steps():
     ref = o.rk4(u0, m["dt"], 100)
     for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
         g = FRMesh(m, prec)
+        g.select_kernels(VARIANTS[variant])
         g.set_state(u0)
         g.step(100)
         err = rel_err(g.get_state(), ref)
-        print(f"vortex 100 steps {prec}: rel L2 {err:.3e}")
+        print(f"vortex 100 steps {prec} {variant}: rel L2 {err:.3e}")
         assert err <= tol
 
 
-def test_tgv_state_after_steps():
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_tgv_state_after_steps(variant):
     m = W.config_tgv(nel=6, order=3)
     o = OracleMesh(m)
     u0 = o.initial_state()
     ref = o.rk4(u0, m["dt"], 100)
     for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
         g = FRMesh(m, prec)
+        g.select_kernels(VARIANTS[variant])
         g.set_state(u0)
         g.step(100)
         err = rel_err(g.get_state(), ref)
@@ -126,13 +152,15 @@ def test_tgv_state_after_steps():
         assert err <= tol
 
 
-def test_airfoil_state_and_forces():
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_airfoil_state_and_forces(variant):
     m = W.config_airfoil(3, ni=24, nj=5, nk=2)
     o = OracleMesh(m)
     u0 = o.initial_state()
     n = 20
     ref, hist = o.rk4(u0, m["dt"], n, forces=True)
     g = FRMesh(m, "fp64")
+    g.select_kernels(VARIANTS[variant])
     g.set_state(u0)
     g.step(n)
     err = rel_err(g.get_state(), ref)
@@ -188,10 +216,12 @@ def test_batch_members_bit_identical_to_solo():
         o = OracleMesh(m)
         us.append(perturbed(o, m, seed=len(us)))
     b.set_state(np.concatenate(us, axis=0))
+    mask = b.autotune(2)
     b.step(8)
     ub = b.get_state()
     for i, m in enumerate(meshes):
         g = FRMesh(m, "fp32")
+        g.select_kernels(mask)
         g.set_state(us[i])
         g.step(8)
         e0, ne = b.design_range(i)
