@@ -7,7 +7,13 @@ Mach 0.1, RK4 with dt = 1e-3.  A "step" is one full RK4 step (four FR
 residual evaluations and the fused stage updates) of the whole mesh; the
 state is resident in HBM before the timed region starts.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--workload tgv|airfoil]
+    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--workload tgv|airfoil|batch|serve]
+
+``--workload batch``: sixteen NACA 4-digit O-grids of uneven size advanced by
+one graph of launches per step (aggregate DOF-updates/s, latency of the
+batched solve).  ``--workload serve``: a Poisson stream of airfoil solve
+requests (mean 4/s, order 2..4, 500 steps each) through the request pool
+(p50/p99 latency from arrival to result, aggregate DOF-updates/s).
 
 Prints one JSON line.  ``value`` is FP32-form DOF-updates/s (DOF = elements x
 solution points x conserved variables, one update = one RK4 step); the plain
@@ -18,6 +24,7 @@ the FP64 oracle timed on this host's cores on a bounded sample of steps.
 """
 import argparse
 import hashlib
+import threading
 import json
 import os
 import sys
@@ -123,12 +130,167 @@ def timed_run(mesh, u0, steps, warmup):
     return time.perf_counter() - t0
 
 
+def bench_batch(args):
+    """Sixteen uneven airfoil designs in one solver: every launch covers all designs."""
+    from paper_2501_05709_amd import workloads as W
+    from paper_2501_05709_amd.solver import FRMesh
+    meshes = W.config_batch(0)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        b = FRMesh(meshes, prec)
+        u0 = np.concatenate([W.uniform_state(ne * b.nu, m["freestream"][0], m["freestream"][1:4],
+                                             m["freestream"][4]).reshape(ne, b.nu, b.nv)
+                             for m, ne in zip(meshes, [b.design_range(i)[1] for i in range(len(meshes))])])
+        b.set_state(u0)
+        mask = b.autotune(2)
+        t = timed_run(b, u0, args.steps, args.warmup)
+        dof = b.E * b.nu * b.nv
+        out[prec] = {"value": dof * args.steps / t, "ms_per_step": t / args.steps * 1e3, "mask": mask,
+                     "batched_solve_latency_s": t, "dof": dof, "elements": b.E}
+        if prec == "fp32":
+            cl = [b.forces(i)[5] for i in range(len(meshes))]
+            out[prec]["mean_CL_per_design"] = [round(float(v), 5) for v in cl]
+        b.close()
+        del b
+        torch_empty()
+    res = {
+        "metric": "FR DOF-updates/s, batch of 16 airfoil designs (FP32 form); batched-solve latency",
+        "value": round(out["fp32"]["value"], 1), "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(out["fp32"]["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "16 NACA 4-digit O-grids (96-192)x(32-64)x(4-12) quadratic hexes, p=3, "
+                               "Re 23000, Mach 0.2, AoA 5 deg, seed 0",
+                   "elements": out["fp32"]["elements"], "dof": out["fp32"]["dof"]},
+        "fp64": out["fp64"], "fp32": out["fp32"],
+        "speedup_fp32_over_fp64": round(out["fp32"]["value"] / out["fp64"]["value"], 3),
+    }
+    print(json.dumps(res))
+
+
+def torch_empty():
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def bench_serve(args):
+    """Poisson stream of solve requests through the continuous-batching pool."""
+    from paper_2501_05709_amd import workloads as W
+    from paper_2501_05709_amd.solver import FRMesh, FRPool, footprint
+    trace = W.request_trace(0, n_requests=args.requests)
+    meshes = [W.config_airfoil(ni=r["ni"], nj=r["nj"], nk=r["nk"], order=r["order"], design=r["design"])
+              for r in trace]
+    # autotune each order once so the pool's solvers start from the tuned choice
+    for order in sorted({r["order"] for r in trace}):
+        small = W.config_airfoil(ni=48, nj=16, nk=2, order=order)
+        g = FRMesh(small, "fp32")
+        fs = small["freestream"]
+        g.set_state(W.uniform_state(g.E * g.nu, fs[0], fs[1:4], fs[4]).reshape(g.shape))
+        g.autotune(2)
+        g.close()
+    steps = 500
+    pool = FRPool(int(args.budget_gb * 2 ** 30))
+    elems = [len(m["elem_nodes"]) for m in meshes]
+    dof = [e * (m["order"] + 1) ** 3 * 5 for e, m in zip(elems, meshes)]
+    arrival = {i: trace[i]["arrival"] for i in range(len(trace))}
+    done_at, admitted_at = {}, {}
+    slot_of = {}
+    running_elems = [0]
+    lock = threading.Lock()
+    t0 = time.perf_counter()
+    tick = 25
+
+    def admitter():
+        # FIFO admission in arrival order, at most `cap` active elements (enough to
+        # fill the device) and within the pool's HBM budget
+        for i in range(len(trace)):
+            while time.perf_counter() - t0 < arrival[i]:
+                time.sleep(0.001)
+            while True:
+                with lock:
+                    ok = running_elems[0] == 0 or running_elems[0] + elems[i] <= args.active_elements
+                if ok:
+                    s = pool.admit(meshes[i], steps, precision="fp32")
+                    if s is not None:
+                        break
+                time.sleep(0.002)
+            with lock:
+                slot_of[s] = i
+                running_elems[0] += elems[i]
+                admitted_at[i] = time.perf_counter() - t0
+
+    th = threading.Thread(target=admitter, daemon=True)
+    th.start()
+    while len(done_at) < len(trace):
+        with lock:
+            active = bool(slot_of)
+        if not active:
+            time.sleep(0.001)
+            continue
+        pool.launch(tick)
+        for s in pool.collect():
+            pool.result(s)
+            with lock:
+                i = slot_of.pop(s)
+                running_elems[0] -= elems[i]
+            done_at[i] = time.perf_counter() - t0
+    th.join()
+    makespan = time.perf_counter() - t0
+    lat = np.array([done_at[i] - arrival[i] for i in range(len(trace))])
+    total = sum(d * steps for d in dof)
+    pool.close()
+    # serial plain-FP64 reference: measured FP64 rate per order on a mid-size
+    # request, then the same trace served one at a time (FIFO) at those rates
+    rate64 = {}
+    for order in sorted({r["order"] for r in trace}):
+        mm = W.config_airfoil(ni=144, nj=48, nk=8, order=order)
+        g = FRMesh(mm, "fp64")
+        fs = mm["freestream"]
+        u0 = W.uniform_state(g.E * g.nu, fs[0], fs[1:4], fs[4]).reshape(g.shape)
+        g.set_state(u0)
+        g.select_kernels(0)  # plain path: dense MFMA operators, five launches per stage
+        t = timed_run(g, u0, 20, 2)
+        rate64[order] = g.E * g.nu * g.nv * 20 / t
+        g.close()
+    clock, lat64 = 0.0, []
+    for i in range(len(trace)):
+        clock = max(clock, arrival[i]) + dof[i] * steps / rate64[trace[i]["order"]]
+        lat64.append(clock - arrival[i])
+    lat64 = np.array(lat64)
+    res = {
+        "metric": "served airfoil solves: p50/p99 latency (arrival to result) and aggregate DOF-updates/s",
+        "value": round(total / makespan, 1), "unit": "DOF-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Poisson trace of {len(trace)} NACA O-grid solves, mean 4/s, orders 2-4, "
+                               f"{steps} RK4 steps each, seed 0", "budget_gb": args.budget_gb, "tick_steps": tick,
+                   "active_element_cap": args.active_elements},
+        "queue_wait_p50_s": round(float(np.percentile([admitted_at[i] - arrival[i] for i in range(len(trace))], 50)), 3),
+        "latency_p50_s": round(float(np.percentile(lat, 50)), 3),
+        "latency_p99_s": round(float(np.percentile(lat, 99)), 3),
+        "latency_max_s": round(float(lat.max()), 3),
+        "makespan_s": round(makespan, 3), "last_arrival_s": round(max(arrival.values()), 3),
+        "offered_dof_updates": total,
+        "serial_fp64_plain": {"dof_updates_per_s_by_order": {str(k): round(v, 1) for k, v in rate64.items()},
+                              "modelled_makespan_s": round(clock, 3),
+                              "modelled_latency_p50_s": round(float(np.percentile(lat64, 50)), 3),
+                              "modelled_latency_p99_s": round(float(np.percentile(lat64, 99)), 3),
+                              "note": "FIFO one-at-a-time service at measured plain-FP64 rates"},
+        "speedup_vs_serial_fp64": round(clock / makespan, 3),
+    }
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="tgv", choices=["tgv", "airfoil"])
+    ap.add_argument("--workload", default="tgv", choices=["tgv", "airfoil", "batch", "serve"])
+    ap.add_argument("--requests", type=int, default=64, help="serve: requests in the trace")
+    ap.add_argument("--budget-gb", type=float, default=96.0, help="serve: HBM budget of the pool")
+    ap.add_argument("--active-elements", type=int, default=150000,
+                    help="serve: admit while the running requests hold fewer elements than this")
     ap.add_argument("--cpu-steps", type=int, default=None, help="oracle sample (steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -140,6 +302,10 @@ def main():
     import torch
     from paper_2501_05709_amd.solver import FRMesh
 
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     m, desc = build_workload(args.workload)
     g32 = FRMesh(m, "fp32")
     xyz = g32.solution_points().reshape(-1, 3)

@@ -193,7 +193,9 @@ fr_status fr_autotune(fr_mesh *m, int64_t steps, int32_t *mask_out);
 /* ---- served requests: continuous batching under an HBM budget ---------- */
 
 /* A pool admits solve requests while their device footprint fits in
- * hbm_budget bytes; admitted requests run concurrently on the device. */
+ * hbm_budget bytes; admitted requests run concurrently on the device.  Pool
+ * calls are thread-safe: one host thread may admit requests (building their
+ * meshes) while another launches and collects steps. */
 fr_status fr_pool_create(size_t hbm_budget, int32_t device, fr_pool **out);
 void fr_pool_destroy(fr_pool *p);
 
@@ -210,6 +212,13 @@ fr_status fr_pool_admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, 
  * them.  Slots that have finished are written to done[0..*n_done-1]
  * (capacity max_done). */
 fr_status fr_pool_tick(fr_pool *p, int64_t k, int64_t *done, int32_t max_done, int32_t *n_done);
+
+/* The two halves of fr_pool_tick: enqueue up to k steps for every running
+ * request without waiting (the host is then free, e.g. to admit requests),
+ * and wait for the enqueued steps and report the requests that finished
+ * (or failed: their fr_pool_result returns the error). */
+fr_status fr_pool_launch(fr_pool *p, int64_t k);
+fr_status fr_pool_collect(fr_pool *p, int64_t *done, int32_t max_done, int32_t *n_done);
 
 /* Result of a finished request (fr_forces layout) and its state if u is
  * not NULL; frees the slot and its device memory. */

@@ -68,6 +68,8 @@ SIGNATURES = {
     "fr_pool_admit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MeshDesc), _dp, ctypes.c_int64, _i64p]),
     "fr_pool_tick": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _i64p, ctypes.c_int32,
                                     ctypes.POINTER(ctypes.c_int32)]),
+    "fr_pool_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "fr_pool_collect": (ctypes.c_int, [ctypes.c_void_p, _i64p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "fr_pool_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp, _dp]),
     "fr_pool_usage": (ctypes.c_int, [ctypes.c_void_p, _i64p]),
     "fr_last_error": (ctypes.c_char_p, []),

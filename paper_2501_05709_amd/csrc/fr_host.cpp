@@ -12,6 +12,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -33,6 +34,22 @@ struct FrError {
 
 void hip_check(hipError_t e, const char *what) {
   if (e != hipSuccess) fail(FR_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// static-partition parallel loop over [0, n) on the host's hardware threads
+template <class F> void parallel_for(int64_t n, F &&f) {
+  const int64_t nt = std::max<int64_t>(1, std::min<int64_t>(std::thread::hardware_concurrency(), (n + 1023) / 1024));
+  if (nt == 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int64_t t = 0; t < nt; ++t)
+    pool.emplace_back([&, t] {
+      const int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+      for (int64_t i = lo; i < hi; ++i) f(i);
+    });
+  for (auto &th : pool) th.join();
 }
 
 template <class F> fr_status guarded(F &&f) {
@@ -335,8 +352,9 @@ HostMesh build_host_mesh(const fr_mesh_desc &d) {
   H.fn.resize(size_t(E) * nf * dim);
   H.fA.resize(size_t(E) * nf);
   H.fx.assign(size_t(E) * nf * 3, 0.0);
-  bool bad = false;
-  for (int64_t e = 0; e < E; ++e) {
+  std::vector<char> bad_e(size_t(E), 0);
+  parallel_for(E, [&](int64_t e) {
+    bool &bad = reinterpret_cast<bool &>(bad_e[size_t(e)]);
     for (int i = 0; i < nu; ++i) {
       auto c = R.upt_idx(i);
       std::array<double, 3> r{b.x[c[0]], b.x[c[1]], dim == 3 ? b.x[c[2]] : 0.0};
@@ -367,8 +385,9 @@ HostMesh build_host_mesh(const fr_mesh_desc &d) {
           H.fx[(size_t(e) * nf + qq) * 3 + j] = x[j];
         }
       }
-  }
-  if (bad) fail(FR_E_MESH, "non-positive Jacobian");
+  });
+  for (char b : bad_e)
+    if (b) fail(FR_E_MESH, "non-positive Jacobian");
 
   // ---- connectivity: faces by corner node ids, then by periodic translation
   const int nfe = 2 * dim, nc = dim == 2 ? 2 : 4;
@@ -688,8 +707,15 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
       bcanon[blk] = ds.e0 + b * EB;
       bdt[blk] = ds.dt;
     }
-    int64_t widx = ds.wall0;
+    // wall flux points are numbered in canonical (element, flux point) order
+    std::vector<int64_t> wall_base(size_t(ds.E) + 1, 0);
     for (int64_t e = 0; e < ds.E; ++e) {
+      int64_t c = 0;
+      for (int qq = 0; qq < nf; ++qq) c += H.nbr[size_t(e) * nf + qq] == -FR_BC_WALL;
+      wall_base[e + 1] = wall_base[e] + c;
+    }
+    parallel_for(ds.E, [&](int64_t e) {
+      int64_t widx = ds.wall0 + wall_base[e];
       const int64_t g = ds.e0 + e;
       const int64_t blk = ds.blk0 + e / EB;
       const int s = int(e % EB);
@@ -718,7 +744,7 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
         }
         NBt[(size_t(blk) * NFPAD + qq) * EB + s] = code;
       }
-    }
+    });
   }
   wall_first[nd] = M->nwall;
   // operators
@@ -760,6 +786,9 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
     bv.insert(bv.end(), b.lp.begin(), b.lp.end());
     bv.insert(bv.end(), b.gLd.begin(), b.gLd.end());
     bv.insert(bv.end(), b.gRd.begin(), b.gRd.end());
+    // strong-form 1D divergence: Dv = D - gR' l(+1)^T - gL' l(-1)^T
+    for (int i = 0; i < b.n; ++i)
+      for (int j = 0; j < b.n; ++j) bv.push_back(b.D[i * b.n + j] - b.gRd[i] * b.lp[j] - b.gLd[i] * b.lm[j]);
     a.basis = upload_real(bv);
   }
   a.SM = M->upload(SM);

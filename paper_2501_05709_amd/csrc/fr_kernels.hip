@@ -86,23 +86,29 @@ template <typename T> struct KArgs {
 // gas physics (paper Eqs. (1)-(7))
 // ---------------------------------------------------------------------------
 
+// reciprocal: hardware rcp (1 ulp) in the FP32 form, exact division in FP64
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double recip(double x) { return 1.0 / x; }
+
 template <typename T, int D> struct Gas {
   static constexpr int NV = D + 2;
   T gam, mu, kappa;
 
-  __device__ inline T pressure(const T *u) const {
+  // pressure from the conserved state and 1/rho
+  __device__ inline T pressure(const T *u, T ir) const {
     T ke = 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) ke += u[1 + i] * u[1 + i];
-    return (gam - T(1)) * (u[D + 1] - T(0.5) * ke / u[0]);
+    return (gam - T(1)) * (u[D + 1] - T(0.5) * ke * ir);
   }
+  __device__ inline T pressure(const T *u) const { return pressure(u, recip(u[0])); }
 
   __device__ inline void flux_inv(const T *u, T F[D][NV]) const {
-    const T ir = T(1) / u[0];
+    const T ir = recip(u[0]);
     T v[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) v[i] = u[1 + i] * ir;
-    const T p = pressure(u);
+    const T p = pressure(u, ir);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       F[j][0] = u[1 + j];
@@ -115,7 +121,7 @@ template <typename T, int D> struct Gas {
   // F_vis,j = (0, tau_ij, v_i tau_ij - q_j), q_j = -(mu gamma/Pr) de/dx_j;
   // g[j][var] = d(var)/dx_j.  adiabatic drops q.
   __device__ inline void flux_vis(const T *u, const T g[D][NV], T F[D][NV], bool adiabatic) const {
-    const T ir = T(1) / u[0];
+    const T ir = recip(u[0]);
     T v[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) v[i] = u[1 + i] * ir;
@@ -149,50 +155,48 @@ template <typename T, int D> struct Gas {
     }
   }
 
+  // Rusanov common flux for the outward unit normal n of the own side:
+  // normal fluxes of both sides, wave speed max(|v.n| + c) of the two sides
   __device__ inline void rusanov(const T *uL, const T *uR, const T *n, T *Fn) const {
-    T FL[D][NV], FR[D][NV];
-    flux_inv(uL, FL);
-    flux_inv(uR, FR);
+    const T irL = recip(uL[0]), irR = recip(uR[0]);
     T vnL = 0, vnR = 0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       vnL += uL[1 + j] * n[j];
       vnR += uR[1 + j] * n[j];
     }
-    vnL /= uL[0];
-    vnR /= uR[0];
-    const T lamL = fabs(vnL) + sqrt(gam * pressure(uL) / uL[0]);
-    const T lamR = fabs(vnR) + sqrt(gam * pressure(uR) / uR[0]);
+    vnL *= irL;
+    vnR *= irR;
+    const T pL = pressure(uL, irL), pR = pressure(uR, irR);
+    const T lamL = fabs(vnL) + sqrt(gam * pL * irL);
+    const T lamR = fabs(vnR) + sqrt(gam * pR * irR);
     const T lam = lamL > lamR ? lamL : lamR;
+    // F(u).n = (rho vn, rho v vn + p n, vn (rho E + p))
+    Fn[0] = T(0.5) * (uL[0] * vnL + uR[0] * vnR) - T(0.5) * lam * (uR[0] - uL[0]);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      T fl = 0, fr = 0;
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        fl += FL[j][v] * n[j];
-        fr += FR[j][v] * n[j];
-      }
-      Fn[v] = T(0.5) * (fl + fr) - T(0.5) * lam * (uR[v] - uL[v]);
-    }
+    for (int i = 0; i < D; ++i)
+      Fn[1 + i] = T(0.5) * (uL[1 + i] * vnL + pL * n[i] + uR[1 + i] * vnR + pR * n[i]) -
+                  T(0.5) * lam * (uR[1 + i] - uL[1 + i]);
+    Fn[D + 1] = T(0.5) * (vnL * (uL[D + 1] + pL) + vnR * (uR[D + 1] + pR)) - T(0.5) * lam * (uR[D + 1] - uL[D + 1]);
   }
 
   // Riemann-invariant far field: outgoing invariant from the interior,
   // incoming from the free stream; entropy and tangential velocity from the
   // upwind side.
   __device__ inline void farfield(const T *uL, const T *n, const double *fs, T *ub) const {
-    const T rhoL = uL[0];
+    const T rhoL = uL[0], irL = recip(rhoL);
     T vL[D], vI[D];
     T vnL = 0, vnI = 0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      vL[j] = uL[1 + j] / rhoL;
+      vL[j] = uL[1 + j] * irL;
       vI[j] = T(fs[1 + j]);
       vnL += vL[j] * n[j];
       vnI += vI[j] * n[j];
     }
-    const T pL = pressure(uL);
+    const T pL = pressure(uL, irL);
     const T rhoI = T(fs[0]), pI = T(fs[4]);
-    const T cL = sqrt(gam * pL / rhoL), cI = sqrt(gam * pI / rhoI);
+    const T cL = sqrt(gam * pL * irL), cI = sqrt(gam * pI / rhoI);
     const T Rp = vnL + T(2) * cL / (gam - T(1));
     const T Rm = vnI - T(2) * cI / (gam - T(1));
     const T vnb = T(0.5) * (Rp + Rm);
@@ -228,7 +232,7 @@ template <typename T, int D> struct Gas {
     uc[0] = uL[0];
 #pragma unroll
     for (int i = 0; i < D; ++i) uc[1 + i] = 0;
-    uc[D + 1] = uL[D + 1] - T(0.5) * ke / uL[0];
+    uc[D + 1] = uL[D + 1] - T(0.5) * ke * recip(uL[0]);
   }
 };
 
@@ -676,16 +680,19 @@ template <typename T, int DIM, int ORDER> struct TS {
   static constexpr int EW_DIV = ew((S::NU * S::NG + S::NF * S::NV) * int(sizeof(T)));
 };
 
-// 1D basis in LDS: D[N][N], l(-1)[N], l(+1)[N], gL'[N], gR'[N]
+// 1D basis in LDS: D[N][N], l(-1)[N], l(+1)[N], gL'[N], gR'[N], and the
+// strong-form divergence operator Dv = D - gR' l(+1)^T - gL' l(-1)^T (the
+// derivative of the flux polynomial minus its interpolated face corrections)
 template <typename T, int N> struct Basis {
-  T D[N][N], lm[N], lp[N], gl[N], gr[N];
+  T D[N][N], lm[N], lp[N], gl[N], gr[N], Dv[N][N];
   __device__ inline void load(const T *src) {
-    for (int t = threadIdx.x; t < N * N + 4 * N; t += blockDim.x) {
+    for (int t = threadIdx.x; t < 2 * N * N + 4 * N; t += blockDim.x) {
       if (t < N * N) D[t / N][t % N] = src[t];
       else if (t < N * N + N) lm[t - N * N] = src[t];
       else if (t < N * N + 2 * N) lp[t - N * N - N] = src[t];
       else if (t < N * N + 3 * N) gl[t - N * N - 2 * N] = src[t];
-      else gr[t - N * N - 3 * N] = src[t];
+      else if (t < N * N + 4 * N) gr[t - N * N - 3 * N] = src[t];
+      else Dv[(t - N * N - 4 * N) / N][(t - N * N - 4 * N) % N] = src[t];
     }
   }
 };
@@ -890,7 +897,8 @@ template <typename T, int DIM, int ORDER> struct FS {
 };
 
 template <typename T, int DIM, int ORDER>
-__global__ __launch_bounds__(256) void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2, 8)))
+void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   using S = Shape<DIM, ORDER>;
   using F = FS<T, DIM, ORDER>;
   constexpr int EW = F::EW_A, WG = F::WG_A, NS = EB / EW, N = S::N, NV = S::NV, NG = S::NG;
@@ -1138,15 +1146,10 @@ __global__ __launch_bounds__(256) void k_stage_a(KArgs<T> a, const T *__restrict
       Ref<DIM, N>::locate(i, k, ik, m);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        T d = 0, fp = 0, fm = 0;
+        T d = 0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-          const T fv = Fs[(Ref<DIM, N>::line(k, m, j) * NG + k * NV + v) * EW + e];
-          d += B.D[ik][j] * fv;
-          fp += B.lp[j] * fv;
-          fm += B.lm[j] * fv;
-        }
-        div[v] += d - B.gr[ik] * fp - B.gl[ik] * fm;
+        for (int j = 0; j < N; ++j) d += B.Dv[ik][j] * Fs[(Ref<DIM, N>::line(k, m, j) * NG + k * NV + v) * EW + e];
+        div[v] += d;
       }
     }
 #pragma unroll

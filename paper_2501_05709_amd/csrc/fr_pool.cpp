@@ -5,12 +5,15 @@
 // others run are admitted as soon as their device footprint fits in the
 // budget, and their kernels overlap on the device.  A tick enqueues up to k
 // steps for every running request, then waits; finished requests keep their
-// results until collected.
+// results until collected.  All pool calls are thread-safe: a host thread
+// may admit (and build the mesh of) a new request while another launches and
+// collects steps; the mesh build runs outside the pool lock.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +27,7 @@ thread_local std::string g_pool_err;
 extern "C" const char *fr_last_error(void);
 
 struct fr_pool {
+  std::mutex mu;
   size_t budget = 0, used = 0;
   int device = 0;
   std::vector<hipStream_t> streams;
@@ -31,7 +35,7 @@ struct fr_pool {
     fr_mesh *m = nullptr;
     int64_t left = 0, total = 0;
     size_t bytes = 0;
-    bool done = false;
+    bool done = false, in_flight = false;
     fr_status status = FR_OK;
   };
   std::map<int64_t, Req> reqs;
@@ -55,7 +59,7 @@ fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
   // operators
   b += r256(size_t(RTF) * KTU * 64 * rs) + r256(size_t(dim) * RTU * KTU * 64 * rs) +
        r256(size_t(dim) * RTU * KTF * 64 * rs) + r256(size_t(RTU) * dim * KTU * 64 * rs) +
-       r256(size_t(RTU) * KTF * 64 * rs) + r256(size_t(D.n * D.n + 4 * D.n) * rs);
+       r256(size_t(RTU) * KTF * 64 * rs) + r256(size_t(2 * D.n * D.n + 4 * D.n) * rs);
   // geometry and tables
   b += size_t(nblk) * D.nup * dim * dim * fr::EB * 8 + size_t(nblk) * D.nup * fr::EB * 8;
   b += size_t(nblk) * D.nfpad * dim * fr::EB * 8 + size_t(nblk) * D.nfpad * fr::EB * 8;
@@ -106,13 +110,27 @@ fr_status fr_pool_admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, 
   size_t need = 0;
   fr_status st = fr_footprint(desc, &need);
   if (st != FR_OK) return st;
-  if (need > p->budget - std::min(p->budget, p->used)) return FR_E_NOMEM;
+  hipStream_t stream;
+  {
+    // reserve the footprint first so that concurrent admissions respect the budget
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (need > p->budget - std::min(p->budget, p->used)) return FR_E_NOMEM;
+    p->used += need;
+    stream = p->streams[p->rr++ % p->streams.size()];
+  }
+  auto release = [&] {
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->used -= std::min(p->used, need);
+  };
   fr_mesh_desc d = *desc;
   d.device = p->device;
-  d.stream = p->streams[p->rr++ % p->streams.size()];
+  d.stream = stream;
   fr_mesh *m = nullptr;
   st = fr_mesh_create(&d, &m);
-  if (st != FR_OK) return st;
+  if (st != FR_OK) {
+    release();
+    return st;
+  }
   int64_t info[10];
   fr_mesh_info(m, info);
   const int64_t n = info[3] * info[4] * info[6];
@@ -134,25 +152,25 @@ fr_status fr_pool_admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, 
   st = fr_set_state(m, u0);
   if (st != FR_OK) {
     fr_mesh_destroy(m);
+    release();
     return st;
   }
   fr_pool::Req r;
   r.m = m;
   r.left = r.total = steps;
-  r.bytes = size_t(info[9]);
-  p->used += r.bytes;
+  r.bytes = need;
+  std::lock_guard<std::mutex> lk(p->mu);
   *slot = p->next_slot++;
   p->reqs[*slot] = r;
   return FR_OK;
 }
 
-fr_status fr_pool_tick(fr_pool *p, int64_t k, int64_t *done, int32_t max_done, int32_t *n_done) {
-  if (!p || k <= 0 || !n_done) return FR_E_ARG;
-  *n_done = 0;
-  std::vector<int64_t> ran;
+fr_status fr_pool_launch(fr_pool *p, int64_t k) {
+  if (!p || k <= 0) return FR_E_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
   for (auto &kv : p->reqs) {
     auto &r = kv.second;
-    if (r.done) continue;
+    if (r.done || r.in_flight) continue;
     const int64_t n = std::min(k, r.left);
     const fr_status st = fr_step_async(r.m, n);
     if (st != FR_OK) {
@@ -161,10 +179,22 @@ fr_status fr_pool_tick(fr_pool *p, int64_t k, int64_t *done, int32_t max_done, i
       continue;
     }
     r.left -= n;
-    ran.push_back(kv.first);
+    r.in_flight = true;
   }
-  for (auto slot : ran) {
-    auto &r = p->reqs[slot];
+  return FR_OK;
+}
+
+fr_status fr_pool_collect(fr_pool *p, int64_t *done, int32_t max_done, int32_t *n_done) {
+  if (!p || !n_done) return FR_E_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  *n_done = 0;
+  for (auto &kv : p->reqs) {
+    auto &r = kv.second;
+    if (!r.in_flight) {
+      if (r.done && r.status != FR_OK && done && *n_done < max_done) done[(*n_done)++] = kv.first;
+      continue;
+    }
+    r.in_flight = false;
     const fr_status st = fr_sync(r.m);
     if (st != FR_OK) {
       r.done = true;
@@ -172,17 +202,24 @@ fr_status fr_pool_tick(fr_pool *p, int64_t k, int64_t *done, int32_t max_done, i
     } else if (r.left == 0) {
       r.done = true;
     }
-    if (r.done && done && *n_done < max_done) done[(*n_done)++] = slot;
+    if (r.done && done && *n_done < max_done) done[(*n_done)++] = kv.first;
   }
   return FR_OK;
 }
 
+fr_status fr_pool_tick(fr_pool *p, int64_t k, int64_t *done, int32_t max_done, int32_t *n_done) {
+  const fr_status st = fr_pool_launch(p, k);
+  if (st != FR_OK) return st;
+  return fr_pool_collect(p, done, max_done, n_done);
+}
+
 fr_status fr_pool_result(fr_pool *p, int64_t slot, double *out, double *u) {
   if (!p) return FR_E_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
   auto it = p->reqs.find(slot);
   if (it == p->reqs.end()) return FR_E_ARG;
   auto &r = it->second;
-  if (!r.done) return FR_E_STATE;
+  if (!r.done || r.in_flight) return FR_E_STATE;
   fr_status st = r.status;
   if (st == FR_OK && out) st = fr_forces(r.m, 0, out);
   if (st == FR_OK && u) st = fr_get_state(r.m, u);
@@ -194,6 +231,7 @@ fr_status fr_pool_result(fr_pool *p, int64_t slot, double *out, double *u) {
 
 fr_status fr_pool_usage(const fr_pool *p, int64_t *used) {
   if (!p || !used) return FR_E_ARG;
+  std::lock_guard<std::mutex> lk(const_cast<fr_pool *>(p)->mu);
   used[0] = int64_t(p->used);
   int64_t running = 0;
   for (auto &kv : p->reqs)

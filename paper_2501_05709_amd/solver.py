@@ -276,6 +276,18 @@ class FRPool:
               "fr_pool_tick")
         return [int(v) for v in done[:n.value]]
 
+    def launch(self, k):
+        """Enqueue up to k steps for every running request; returns at once."""
+        check(_lib.load().fr_pool_launch(self.h, int(k)), "fr_pool_launch")
+
+    def collect(self, max_done=256):
+        """Wait for the enqueued steps; slots of requests that finished."""
+        done = np.zeros(max_done, dtype=np.int64)
+        n = ctypes.c_int32()
+        check(_lib.load().fr_pool_collect(self.h, done.ctypes.data_as(_lib._i64p), max_done, ctypes.byref(n)),
+              "fr_pool_collect")
+        return [int(v) for v in done[:n.value]]
+
     def result(self, slot, shape=None):
         out = np.zeros(8)
         u = np.zeros(shape) if shape is not None else None

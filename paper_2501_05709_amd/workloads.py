@@ -93,13 +93,15 @@ def box_mesh(dim, nel, lo, hi, q=1, warp=0.0, order=3):
 def naca4(m, pc, t, theta):
     """NACA 4-digit surface point for parameter theta in [0, 2 pi).
 
-    x = (1 + cos theta)/2; theta in [0, pi] is the lower surface (trailing
-    edge to leading edge), theta in (pi, 2 pi) the upper one, so increasing
-    theta runs clockwise.  Closed trailing edge (last thickness coefficient
-    -0.1036).
+    theta in [0, pi] is the lower surface (trailing edge to leading edge),
+    theta in (pi, 2 pi) the upper one, so increasing theta runs clockwise.
+    With u = theta/pi (lower) or 2 - theta/pi (upper), x = 1 - sin(pi u / 2):
+    about uniform spacing at the trailing edge, clustering at the leading
+    edge.  Closed trailing edge (last thickness coefficient -0.1036).
     """
     theta = np.asarray(theta, dtype=np.float64)
-    x = 0.5 * (1.0 + np.cos(theta))
+    u = np.where(theta <= np.pi, theta / np.pi, 2.0 - theta / np.pi)
+    x = np.clip(1.0 - np.sin(0.5 * np.pi * u), 0.0, 1.0)
     yt = 5.0 * t * (0.2969 * np.sqrt(np.maximum(x, 0.0)) - 0.1260 * x - 0.3516 * x ** 2
                     + 0.2843 * x ** 3 - 0.1036 * x ** 4)
     if m > 0.0:
@@ -164,6 +166,64 @@ def naca_ogrid(m, pc, t, ni, nj, nk, span=0.2, radius=20.0, ratio=1.1, q=2, orde
         np.stack([outer, np.full_like(outer, 3), np.full_like(outer, outer_bc)], 1)]).astype(np.int64)
     return dict(dim=3, order=order, q=q, nodes=nodes, elem_nodes=elem.astype(np.int64),
                 periodic=np.array([[0.0, 0.0, span]]), bfaces=bfaces)
+
+
+def min_width(mesh, order=None):
+    """Smallest element width across a pair of opposite faces, 2|J| / |grad_x xi_k|^-1,
+    over the Gauss-Legendre points of the mesh's order (captures sliver elements)."""
+    q, d = mesh["q"], mesh["dim"]
+    order = mesh["order"] if order is None else order
+    xg, _ = np.polynomial.legendre.leggauss(order + 1)
+    nodes1 = np.linspace(-1.0, 1.0, q + 1)
+
+    def shape(t):
+        N = np.ones((len(t), q + 1))
+        dN = np.zeros((len(t), q + 1))
+        for a in range(q + 1):
+            for b in range(q + 1):
+                if b != a:
+                    N[:, a] *= (t - nodes1[b]) / (nodes1[a] - nodes1[b])
+            for c in range(q + 1):
+                if c == a:
+                    continue
+                term = np.full(len(t), 1.0 / (nodes1[a] - nodes1[c]))
+                for b in range(q + 1):
+                    if b != a and b != c:
+                        term *= (t - nodes1[b]) / (nodes1[a] - nodes1[b])
+                dN[:, a] += term
+        return N, dN
+
+    N, dN = shape(xg)
+    na = q + 1
+    n = len(xg)
+    X = mesh["nodes"][mesh["elem_nodes"]]  # [E, na^d, d], node a = a0 + na a1 (+ na^2 a2)
+    if d == 2:
+        # W_k[point (i0 + n i1), node (a0 + na a1)]: derivative along axis k of the map
+        W0 = np.einsum("ia,jb->jiba", dN, N).reshape(n * n, na * na)
+        W1 = np.einsum("ia,jb->jiba", N, dN).reshape(n * n, na * na)
+        c0 = np.matmul(W0, X)  # [E, points, 2]
+        c1 = np.matmul(W1, X)
+        det = c0[..., 0] * c1[..., 1] - c0[..., 1] * c1[..., 0]
+        # width across the faces of axis k: 2 |J| / |column of the other axis|
+        w0 = 2.0 * det / np.linalg.norm(c1, axis=-1)
+        w1 = 2.0 * det / np.linalg.norm(c0, axis=-1)
+        return float(min(w0.min(), w1.min()))
+    shp = (n * n * n, na * na * na)
+    W = [np.einsum("ia,jb,kc->kjicba", *fs).reshape(shp)
+         for fs in ((dN, N, N), (N, dN, N), (N, N, dN))]
+    cols = [np.matmul(Wk, X) for Wk in W]  # [E, points, 3]
+    c = [[cols[k][..., i] for i in range(3)] for k in range(3)]
+
+    def cross(u, v):
+        return (u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0])
+
+    s = [cross(c[(k + 1) % 3], c[(k + 2) % 3]) for k in range(3)]  # |J| grad xi_k
+    det = c[0][0] * s[0][0] + c[0][1] * s[0][1] + c[0][2] * s[0][2]
+    best = np.inf
+    for k in range(3):
+        norm = np.sqrt(s[k][0] ** 2 + s[k][1] ** 2 + s[k][2] ** 2)
+        best = min(best, float((2.0 * det / norm).min()))
+    return best
 
 
 def min_edge(mesh):
@@ -254,12 +314,12 @@ def airfoil_flow(aoa_deg=5.0, mach=0.2, re=23000.0, pr=0.71, gamma=GAMMA, span=0
                 drag_dir=np.array([math.cos(a), math.sin(a), 0.0]))
 
 
-def airfoil_dt(mesh, order):
-    """Fixed RK4 step: 0.5 h_min / ((|U| + c)(2p + 1))."""
+def airfoil_dt(mesh, order, cfl=0.5):
+    """Fixed RK4 step: cfl h_min / ((|U| + c)(2p + 1)), h_min = smallest element width."""
     fs = mesh["freestream"]
     c = math.sqrt(mesh["gamma"] * fs[4] / fs[0])
     speed = float(np.linalg.norm(fs[1:4])) + c
-    return 0.5 * min_edge(mesh) / (speed * (2 * order + 1))
+    return cfl * min_width(mesh, order) / (speed * (2 * order + 1))
 
 
 def config_vortex(seed=0, nel=16, order=3):
