@@ -293,6 +293,8 @@ def main():
                     help="serve: admit while the running requests hold fewer elements than this")
     ap.add_argument("--cpu-steps", type=int, default=None, help="oracle sample (steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device to device (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -302,6 +304,14 @@ def main():
     import torch
     from paper_2501_05709_amd.solver import FRMesh
 
+    if args.calibrate_copy:
+        src = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "serve":

@@ -9,6 +9,9 @@ markdown table.  Only the standard library is used.
 from __future__ import annotations
 
 import argparse
+import hashlib
+import json
+import os
 import sqlite3
 from collections import defaultdict
 
@@ -37,11 +40,49 @@ def kernels(db):
     return agg
 
 
+def traffic_entry(fetch_db, write_db, kernel, copy_bytes):
+    """HBM bytes per launch of `kernel` from FETCH_SIZE and WRITE_SIZE runs, each scaled by
+    what the same counter reads for the largest device copy (copy_bytes read and written)."""
+    def per_kernel(db, counter):
+        agg = counters(db)
+        k = [v for (name, c), v in agg.items() if c == counter and kernel in name]
+        con = sqlite3.connect(db)
+        # the calibration copy is the device copy dispatch with the largest count
+        big = max(float(r[0]) for r in con.execute(
+            "select value from counters_collection where counter_name = ? and kernel_name like '%copyBuffer%'",
+            (counter,)))
+        return k[0][1] / k[0][0], big
+    f_k, f_copy = per_kernel(fetch_db, "FETCH_SIZE")
+    w_k, w_copy = per_kernel(write_db, "WRITE_SIZE")
+    f_scale = copy_bytes / (f_copy * 1024.0)
+    w_scale = copy_bytes / (w_copy * 1024.0)
+    return {"fetch_kib": round(f_k, 1), "write_kib": round(w_k, 1),
+            "copy_fetch_kib": round(f_copy, 1), "copy_write_kib": round(w_copy, 1),
+            "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+            "hbm_bytes_per_launch": round(f_k * 1024.0 * f_scale + w_k * 1024.0 * w_scale)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db", nargs="+")
     ap.add_argument("--match", default="")
+    ap.add_argument("--traffic", nargs=4, metavar=("WORKLOAD", "KERNEL", "FETCH_DB", "WRITE_DB"),
+                    help="write the counter traffic of KERNEL into profiles/counters.json")
+    ap.add_argument("--copy-bytes", type=float, default=2.0 ** 30)
     args = ap.parse_args()
+    if args.traffic:
+        workload, kernel, fdb, wdb = args.traffic
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        src = open(os.path.join(root, "paper_2501_05709_amd", "csrc", "fr_kernels.hip"), "rb").read()
+        entry = traffic_entry(fdb, wdb, kernel, args.copy_bytes)
+        entry["source_sha256"] = hashlib.sha256(src).hexdigest()
+        entry["kernel_match"] = kernel
+        path = os.path.join(root, "profiles", "counters.json")
+        data = json.load(open(path)) if os.path.exists(path) else {}
+        data.setdefault(workload, {})[kernel.split("<")[0]] = entry
+        json.dump(data, open(path, "w"), indent=1, sort_keys=True)
+        print(json.dumps(entry))
+        return
     print("| kernel | counter | dispatches | mean per dispatch | grid |")
     print("|---|---|---|---|---|")
     for db in args.db:
