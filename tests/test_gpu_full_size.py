@@ -1,0 +1,262 @@
+"""GPU parity at the full workload sizes, in the launch configuration the benchmark
+times (kernel structure chosen by the autotuner on the mesh itself), plus edge cases.
+
+Same measure and bars as test_gpu_parity: relative L2 per physical field, max over
+density, momentum vector and total energy; FP64 residual and state 1e-12; FP32 form
+1e-5; batch members bit for bit against their solo runs.
+
+  * Taylor-Green 24^3 hexes, p = 3 (4.4 M DOF): FP64 residual; 200 RK4 steps of the
+    FP32 form and the FP64 path against the oracle, and the kinetic-energy decay
+    E_k(t) = <rho |v|^2 / 2> sampled every 20 steps.
+  * NACA O-grid 160x48x8 quadratic hexes, p = 3 (19.7 M DOF): FP64 residual; 3 steps
+    of both forms from a perturbed state, with the wall force of every step.
+  * Sixteen uneven O-grids in one batch (917,407 hexes): the smallest design and one
+    drawn at random, bit for bit against solo runs; the smallest against the oracle.
+  * Edge cases: a single periodic element that is its own neighbour on every face
+    (2D and 3D), zero steps, a ragged last block.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleMesh
+from paper_2501_05709_amd import workloads as W
+from paper_2501_05709_amd.solver import FRMesh
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_err(x, ref):
+    nv = ref.shape[-1]
+    x = x.reshape(-1, nv)
+    ref = ref.reshape(-1, nv)
+    return max(np.linalg.norm(x[:, c] - ref[:, c]) / np.linalg.norm(ref[:, c])
+               for c in ([0], list(range(1, nv - 1)), [nv - 1]))
+
+
+def perturbed(o, mesh, amp=0.1, seed=0):
+    """Free stream (or the mesh's initial state) times a smooth density/energy perturbation."""
+    x = o.solution_points()
+    if "init" in mesh:
+        u = o.initial_state()
+    else:
+        fs = mesh["freestream"]
+        u = W.uniform_state(o.E * o.nu, fs[0], fs[1:1 + o.dim], fs[4]).reshape(o.shape)
+    rng = np.random.default_rng(seed)
+    k = rng.uniform(0.5, 2.0, size=3)
+    s = np.sin(k[0] * x[..., 0] + 0.3) * np.cos(k[1] * x[..., 1] - 0.2) * np.cos(k[2] * x[..., 2] + 0.1)
+    u = u.copy()
+    u[..., 0] *= 1.0 + amp * s
+    u[..., -1] *= 1.0 + amp * s
+    return u
+
+
+def kinetic_energy(u, order):
+    """Volume mean of rho |v|^2 / 2 on an affine mesh of equal elements (GL weights)."""
+    w = np.polynomial.legendre.leggauss(order + 1)[1]
+    wt = np.multiply.outer(np.multiply.outer(w, w), w).ravel() / 8.0
+    rho = u[..., 0]
+    m2 = (u[..., 1:4] ** 2).sum(axis=-1)
+    return float((0.5 * m2 / rho * wt).sum(axis=-1).mean())
+
+
+def tuned(mesh, prec, u):
+    g = FRMesh(mesh, prec)
+    g.set_state(u)
+    g.autotune(2)
+    return g
+
+
+@pytest.fixture(scope="module")
+def tgv():
+    m = W.config_tgv(nel=24, order=3)
+    o = OracleMesh(m)
+    return m, o, o.initial_state()
+
+
+def test_tgv_full_fp64_residual(tgv):
+    m, o, u0 = tgv
+    u = perturbed(o, m)
+    g = tuned(m, "fp64", u0)
+    err = rel_err(g.residual(u), o.residual(u))
+    print(f"tgv 24^3 fp64 residual (mask {g.selected_kernels()}): rel L2 {err:.3e}", flush=True)
+    assert err <= 1e-12
+
+
+@pytest.mark.timeout(300)
+def test_tgv_full_200_steps_and_kinetic_energy(tgv):
+    m, o, u0 = tgv
+    dt, chunk, nchunk = m["dt"], 20, 10
+    ref, ek_ref = [u0], [kinetic_energy(u0, 3)]
+    for _ in range(nchunk):
+        ref.append(o.rk4(ref[-1], dt, chunk))
+        ek_ref.append(kinetic_energy(ref[-1], 3))
+    ek_ref = np.array(ek_ref)
+    for prec, tol, ek_tol in (("fp64", 1e-12, 1e-12), ("fp32", 1e-5, 2e-2)):
+        g = tuned(m, prec, u0)
+        g.set_state(u0)
+        ek = [kinetic_energy(u0, 3)]
+        for c in range(nchunk):
+            g.step(chunk)
+            u = g.get_state()
+            ek.append(kinetic_energy(u, 3))
+            if c == 4:
+                err100 = rel_err(u, ref[5])
+        ek = np.array(ek)
+        err = rel_err(u, ref[-1])
+        # decay between samples, relative to the oracle's
+        rate_err = np.abs(np.diff(ek) - np.diff(ek_ref)).max() / np.abs(np.diff(ek_ref)).max()
+        print(f"tgv 24^3 {prec}: rel L2 after 100 steps {err100:.3e}, after 200 {err:.3e}; "
+              f"E_k {ek[0]:.9f} -> {ek[-1]:.9f} (oracle {ek_ref[-1]:.9f}), decay rel err {rate_err:.2e}",
+              flush=True)
+        assert err100 <= tol and err <= tol
+        assert np.abs(ek - ek_ref).max() <= tol * ek_ref[0]
+        assert rate_err <= ek_tol
+        g.close()
+
+
+@pytest.fixture(scope="module")
+def airfoil():
+    m = W.config_airfoil(0, ni=160, nj=48, nk=8, order=3)
+    o = OracleMesh(m)
+    return m, o, perturbed(o, m, amp=0.05)
+
+
+def test_airfoil_full_fp64_residual(airfoil):
+    m, o, u = airfoil
+    g = tuned(m, "fp64", u)
+    err = rel_err(g.residual(u), o.residual(u))
+    print(f"airfoil 160x48x8 fp64 residual (mask {g.selected_kernels()}): rel L2 {err:.3e}", flush=True)
+    assert err <= 1e-12
+
+
+@pytest.mark.timeout(300)
+def test_airfoil_full_steps_and_forces(airfoil):
+    m, o, u = airfoil
+    n = 3
+    ref, hist = o.rk4(u, m["dt"], n, forces=True)
+    qref = 0.5 * m["ref_area"]
+    scale = np.abs(hist).max()
+    for prec, tol, ftol in (("fp64", 1e-12, 1e-10), ("fp32", 1e-5, 1e-4)):
+        g = tuned(m, prec, u)
+        g.set_state(u)
+        g.step(n)
+        err = rel_err(g.get_state(), ref)
+        f = g.forces()
+        ferr = np.abs(f[2:5] - hist[-1]).max() / scale
+        mean_err = abs(f[5] - hist.mean(axis=0) @ m["lift_dir"] / qref) / (scale / qref)
+        print(f"airfoil 160x48x8 {prec} {n} steps: rel L2 {err:.3e}, force rel err {ferr:.2e}, "
+              f"mean C_L err {mean_err:.2e}", flush=True)
+        assert err <= tol
+        assert f[7] == n and ferr <= ftol and mean_err <= ftol
+        g.close()
+
+
+@pytest.mark.timeout(400)
+def test_full_batch_members_match_solo_and_oracle():
+    meshes = W.config_batch(0)
+    sizes = [len(m["elem_nodes"]) for m in meshes]
+    small = int(np.argmin(sizes))
+    other = int(np.random.default_rng(7).choice([i for i in range(len(meshes)) if i != small]))
+    states = []
+    o_small = OracleMesh(meshes[small])
+    for i, m in enumerate(meshes):
+        if i == small:
+            states.append(perturbed(o_small, m, amp=0.05, seed=i))
+        else:
+            fs = m["freestream"]
+            states.append(W.uniform_state(sizes[i] * 64, fs[0], fs[1:4], fs[4]).reshape(sizes[i], 64, 5))
+    u0 = np.concatenate(states)
+    b = FRMesh(meshes, "fp32")
+    b.set_state(u0)
+    mask = b.autotune(2)
+    b.set_state(u0)
+    n = 2
+    b.step(n)
+    ub = b.get_state()
+    print(f"batch of {len(meshes)} designs, {b.E} elements, mask {mask}", flush=True)
+    for i in (small, other):
+        g = FRMesh(meshes[i], "fp32")
+        g.select_kernels(mask)
+        g.set_state(states[i])
+        g.step(n)
+        e0, ne = b.design_range(i)
+        assert np.array_equal(ub[e0:e0 + ne], g.get_state()), i
+        assert np.array_equal(b.forces(i), g.forces()), i
+        g.close()
+    e0, ne = b.design_range(small)
+    ref = o_small.rk4(states[small], meshes[small]["dt"], n)
+    err = rel_err(ub[e0:e0 + ne], ref)
+    print(f"smallest design ({sizes[small]} elements) fp32 batched vs oracle, {n} steps: {err:.3e}", flush=True)
+    assert err <= 1e-5
+    b.close()
+
+
+VARIANTS = {"dense": 0, "tensor": (1 << 2) | (1 << 3) | (1 << 4) | (1 << 5), "fused": 1 | (1 << 5)}
+
+
+def single_element(dim):
+    if dim == 2:
+        m = W.box_mesh(2, (1, 1), (0, 0), (1.0, 1.3), q=1, order=3)
+    else:
+        m = W.box_mesh(3, (1, 1, 1), (0, 0, 0), (1.0, 1.3, 0.8), q=1, order=3)
+    fs = np.array([1.0, 0.3, -0.2, 0.1 if dim == 3 else 0.0, 1.0])
+    m.update(gamma=1.4, prandtl=0.72, mu=0.01, freestream=fs, dt=1e-3)
+    return m
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+@pytest.mark.parametrize("dim", [2, 3])
+def test_single_self_periodic_element(dim, variant):
+    """One element whose every face is periodic with its opposite face."""
+    m = single_element(dim)
+    o = OracleMesh(m)
+    nb = o.neighbours()
+    assert (nb >= 0).all()
+    u = perturbed(o, m, amp=0.2)
+    ref_r = o.residual(u)
+    ref_u = o.rk4(u, m["dt"], 5)
+    for prec, tol_r, tol_u in (("fp64", 1e-12, 1e-12), ("fp32", 1e-3, 1e-5)):
+        g = FRMesh(m, prec)
+        g.select_kernels(VARIANTS[variant])
+        assert np.array_equal(g.neighbours(), nb)
+        er = rel_err(g.residual(u), ref_r)
+        g.set_state(u)
+        g.step(5)
+        eu = rel_err(g.get_state(), ref_u)
+        print(f"single element {dim}D {variant} {prec}: residual {er:.2e}, 5 steps {eu:.2e}", flush=True)
+        assert er <= tol_r and eu <= tol_u
+        g.close()
+
+
+def test_zero_steps_is_a_no_op():
+    m = W.config_airfoil(5, ni=16, nj=4, nk=3)
+    o = OracleMesh(m)
+    u = perturbed(o, m)
+    g = FRMesh(m, "fp32")
+    g.set_state(u)
+    g.step(2)
+    a, fa = g.get_state(), g.forces()
+    g.step(0)
+    assert np.array_equal(g.get_state(), a)
+    assert np.array_equal(g.forces(), fa)
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_ragged_last_block(variant):
+    """105 elements: the last block of 16 holds 9, and the fused kernels' last
+    workgroup of the block is partly empty."""
+    m = W.box_mesh(3, (5, 3, 7), (0, 0, 0), (1.0, 0.6, 1.4), q=2, warp=0.04, order=3)
+    fs = np.array([1.0, 0.2, 0.1, -0.1, 1.0])
+    m.update(gamma=1.4, prandtl=0.71, mu=0.005, freestream=fs, dt=5e-4)
+    o = OracleMesh(m)
+    u = perturbed(o, m)
+    ref = o.rk4(u, m["dt"], 10)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        g = FRMesh(m, prec)
+        g.select_kernels(VARIANTS[variant])
+        g.set_state(u)
+        g.step(10)
+        err = rel_err(g.get_state(), ref)
+        print(f"ragged 105 elements {variant} {prec}: {err:.2e}", flush=True)
+        assert err <= tol
+        g.close()

@@ -64,6 +64,9 @@ MESHES = {
     "box2d_curved": lambda: W.box_mesh(2, (4, 4), (0, 0), (1, 1), q=2, warp=0.05, order=2),
     "box3d": lambda: W.box_mesh(3, (3, 2, 4), (0, 0, 0), (1, 1, 2), order=3),
     "box3d_self_periodic": lambda: W.box_mesh(3, (1, 2, 1), (0, 0, 0), (1, 1, 1), order=2),
+    "single_element_2d": lambda: W.box_mesh(2, (1, 1), (0, 0), (1.0, 1.3), order=3),
+    "single_element_3d": lambda: W.box_mesh(3, (1, 1, 1), (0, 0, 0), (1.0, 1.3, 0.8), order=3),
+    "ragged_box3d_curved": lambda: W.box_mesh(3, (5, 3, 7), (0, 0, 0), (1.0, 0.6, 1.4), q=2, warp=0.04, order=3),
     "ogrid": lambda: dict(W.naca_ogrid(0.04, 0.4, 0.12, 16, 4, 2), **W.airfoil_flow()),
     "ogrid_p4": lambda: dict(W.naca_ogrid(0.0, 0.4, 0.1, 8, 3, 1, order=4), **W.airfoil_flow()),
     "ogrid_rotated": _rotated_ogrid,
