@@ -84,6 +84,14 @@ def rel_l2(x, ref):
     return max(out)
 
 
+def kinetic_energy(u, order):
+    """Volume mean of rho |v|^2 / 2 over a mesh of equal affine hexes (tensor GL weights)."""
+    w = np.polynomial.legendre.leggauss(order + 1)[1]
+    wt = np.multiply.outer(np.multiply.outer(w, w), w).ravel() / 8.0
+    m2 = (u[..., 1:4] ** 2).sum(axis=-1)
+    return float((0.5 * m2 / u[..., 0] * wt).sum(axis=-1).mean())
+
+
 def counters_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
     or None if it is missing or the kernel source changed since it was taken."""
@@ -347,13 +355,22 @@ def main():
 
     # --- plain FP64 GPU path
     err64_oracle = err32_oracle = None
+    ek = None
     if ref_sample is not None:
         g64.set_state(u0)
         g64.step(n_sample)
-        err64_oracle = rel_l2(g64.get_state(), ref_sample)
+        s64 = g64.get_state()
+        err64_oracle = rel_l2(s64, ref_sample)
         g32.set_state(u0)
         g32.step(n_sample)
-        err32_oracle = rel_l2(g32.get_state(), ref_sample)
+        s32 = g32.get_state()
+        err32_oracle = rel_l2(s32, ref_sample)
+        if args.workload == "tgv":
+            k0, ko = kinetic_energy(u0, 3), kinetic_energy(ref_sample, 3)
+            ek = {"E_k_0": k0, "steps": n_sample, "E_k_oracle": ko,
+                  "E_k_fp64": kinetic_energy(s64, 3), "E_k_fp32": kinetic_energy(s32, 3),
+                  "decay_rel_err_fp64": abs((k0 - kinetic_energy(s64, 3)) - (k0 - ko)) / (k0 - ko),
+                  "decay_rel_err_fp32": abs((k0 - kinetic_energy(s32, 3)) - (k0 - ko)) / (k0 - ko)}
     t64 = timed_run(g64, u0, args.steps, args.warmup)
     u64 = g64.get_state()
 
@@ -361,6 +378,9 @@ def main():
     t32 = timed_run(g32, u0, args.steps, args.warmup)
     u32 = g32.get_state()
     err32_vs64 = rel_l2(u32, u64)
+    if ek is not None:
+        ek["after_timed_run"] = {"steps": args.warmup + args.steps, "E_k_fp64": kinetic_energy(u64, 3),
+                                 "E_k_fp32": kinetic_energy(u32, 3)}
 
     # --- the all-dense-MFMA operator back-end, for comparison
     g32.select_kernels(0)
@@ -435,6 +455,7 @@ def main():
         "fp32_rel_l2_vs_oracle": err32_oracle,
         "fp32_rel_l2_vs_fp64_gpu": err32_vs64,
         "oracle_sample_steps": n_sample if ref_sample is not None else None,
+        "kinetic_energy": ek,
         "speedup_fp32_over_fp64": round(t64 / t32, 3),
         "kernel_variants": {"fp32_mask": mask32, "fp64_mask": mask64,
                             "note": "bit 0: fused two-launch stage (sum-factorised); else bit k set: "

@@ -86,9 +86,12 @@ template <typename T> struct KArgs {
 // gas physics (paper Eqs. (1)-(7))
 // ---------------------------------------------------------------------------
 
-// reciprocal: hardware rcp (1 ulp) in the FP32 form, exact division in FP64
+// reciprocal and square root: hardware rcp and sqrt (1 ulp) in the FP32 form,
+// correctly rounded in FP64
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double recip(double x) { return 1.0 / x; }
+__device__ inline float sqrtv(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double sqrtv(double x) { return sqrt(x); }
 
 template <typename T, int D> struct Gas {
   static constexpr int NV = D + 2;
@@ -155,6 +158,41 @@ template <typename T, int D> struct Gas {
     }
   }
 
+  // F_vis . n for a unit normal n, formed directly: (0, tau n, v . tau n - q . n)
+  __device__ inline void flux_vis_n(const T *u, const T g[D][NV], const T *n, T *Fn, bool adiabatic) const {
+    const T ir = recip(u[0]);
+    T v[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[i] = u[1 + i] * ir;
+    const T E = u[D + 1] * ir;
+    T dv[D][D], qn = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T vdv = 0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        dv[i][j] = (g[j][1 + i] - v[i] * g[j][0]) * ir;
+        vdv += v[i] * dv[i][j];
+      }
+      qn += ((g[j][D + 1] - E * g[j][0]) * ir - vdv) * n[j];
+    }
+    T div = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) div += dv[i][i];
+    const T d23 = T(2.0 / 3.0) * div;
+    T work = 0;
+    Fn[0] = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      T s = -d23 * n[i];
+#pragma unroll
+      for (int j = 0; j < D; ++j) s += (dv[i][j] + dv[j][i]) * n[j];
+      Fn[1 + i] = mu * s;
+      work += v[i] * Fn[1 + i];
+    }
+    Fn[D + 1] = adiabatic ? work : work + kappa * qn;
+  }
+
   // Rusanov common flux for the outward unit normal n of the own side:
   // normal fluxes of both sides, wave speed max(|v.n| + c) of the two sides
   __device__ inline void rusanov(const T *uL, const T *uR, const T *n, T *Fn) const {
@@ -168,8 +206,8 @@ template <typename T, int D> struct Gas {
     vnL *= irL;
     vnR *= irR;
     const T pL = pressure(uL, irL), pR = pressure(uR, irR);
-    const T lamL = fabs(vnL) + sqrt(gam * pL * irL);
-    const T lamR = fabs(vnR) + sqrt(gam * pR * irR);
+    const T lamL = fabs(vnL) + sqrtv(gam * pL * irL);
+    const T lamR = fabs(vnR) + sqrtv(gam * pR * irR);
     const T lam = lamL > lamR ? lamL : lamR;
     // F(u).n = (rho vn, rho v vn + p n, vn (rho E + p))
     Fn[0] = T(0.5) * (uL[0] * vnL + uR[0] * vnR) - T(0.5) * lam * (uR[0] - uL[0]);
@@ -196,7 +234,7 @@ template <typename T, int D> struct Gas {
     }
     const T pL = pressure(uL, irL);
     const T rhoI = T(fs[0]), pI = T(fs[4]);
-    const T cL = sqrt(gam * pL * irL), cI = sqrt(gam * pI / rhoI);
+    const T cL = sqrtv(gam * pL * irL), cI = sqrtv(gam * pI / rhoI);
     const T Rp = vnL + T(2) * cL / (gam - T(1));
     const T Rm = vnI - T(2) * cI / (gam - T(1));
     const T vnb = T(0.5) * (Rp + Rm);
@@ -244,11 +282,24 @@ __device__ inline size_t at(int64_t blk, int pt, int ch, int e, int NPT, int NCH
 // reference-element index maps (conventions of include/fr.h)
 // ---------------------------------------------------------------------------
 template <int DIM, int N> struct Ref {
-  // solution point on the line through face point m of a face on axis k, at position j
-  __device__ static inline int line(int k, int m, int j) {
-    if (DIM == 2) return k == 0 ? j + N * m : m + N * j;
+  // the line through face point m of a face on axis k: solution point base + j * stride
+  // at position j.  Written with selects, not branches, because k is a run-time value
+  // in the flux-point passes.
+  __device__ static inline void line_of(int k, int m, int &base, int &stride) {
+    if (DIM == 2) {
+      base = k == 0 ? N * m : m;
+      stride = k == 0 ? 1 : N;
+      return;
+    }
     const int a = m % N, b = m / N;
-    return k == 0 ? j + N * (a + N * b) : (k == 1 ? a + N * (j + N * b) : a + N * (b + N * j));
+    const int sa = k == 0 ? N : 1, sb = k == 2 ? N : N * N;
+    base = a * sa + b * sb;
+    stride = k == 0 ? 1 : (k == 1 ? N : N * N);
+  }
+  __device__ static inline int line(int k, int m, int j) {
+    int base, stride;
+    line_of(k, m, base, stride);
+    return base + j * stride;
   }
   // position along axis k and face-point index of solution point i
   __device__ static inline void locate(int i, int k, int &ik, int &m) {
@@ -314,7 +365,7 @@ template <typename T, int DIM, int ORDER>
 __device__ inline void visc_epilogue(const KArgs<T> &a, const Gas<T, DIM> &gas, int64_t blk, int q, int e,
                                      const T gf[DIM][DIM + 2], int forces) {
   using S = Shape<DIM, ORDER>;
-  T uf[S::NV], n[DIM], Fv[DIM][S::NV], pv[S::NV];
+  T uf[S::NV], n[DIM], pv[S::NV];
 #pragma unroll
   for (int v = 0; v < S::NV; ++v) uf[v] = a.UF[at(blk, q, v, e, S::NFPAD, S::NV)];
   double nd[DIM];
@@ -324,32 +375,23 @@ __device__ inline void visc_epilogue(const KArgs<T> &a, const Gas<T, DIM> &gas, 
     n[c] = T(nd[c]);
   }
   const int nb = a.NB[(size_t(blk) * S::NFPAD + q) * EB + e];
+  T fn[S::NV];
   if (nb >= 0) {
-    gas.flux_vis(uf, gf, Fv, false);
+    gas.flux_vis_n(uf, gf, n, fn, false);
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v) {
-      T s = 0;
-#pragma unroll
-      for (int c = 0; c < DIM; ++c) s += Fv[c][v] * n[c];
-      pv[v] = T(0.5) * s;
-    }
+    for (int v = 0; v < S::NV; ++v) pv[v] = T(0.5) * fn[v];
   } else {
     const int code = -nb;
     T ub[S::NV];
     if ((code & 3) == BC_FARFIELD) {
       gas.farfield(uf, n, a.fsd + 5 * a.bdesign[blk], ub);
-      gas.flux_vis(ub, gf, Fv, false);
+      gas.flux_vis_n(ub, gf, n, fn, false);
     } else {
       gas.wall_common(uf, ub);
-      gas.flux_vis(ub, gf, Fv, true);
+      gas.flux_vis_n(ub, gf, n, fn, true);
     }
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v) {
-      T s = 0;
-#pragma unroll
-      for (int c = 0; c < DIM; ++c) s += Fv[c][v] * n[c];
-      pv[v] = a.FI[at(blk, q, v, e, S::NFPAD, S::NV)] - s;
-    }
+    for (int v = 0; v < S::NV; ++v) pv[v] = a.FI[at(blk, q, v, e, S::NFPAD, S::NV)] - fn[v];
     if (forces && (code & 3) == BC_WALL) {
       // traction of the fluid on the body: W A (p n - tau . n), interior trace
       T Fw[DIM][S::NV];
@@ -915,17 +957,39 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   if (e0 >= nvalid) return;
   const int tid = threadIdx.x;
 
-  // ---- prefetch everything that does not depend on LDS
+  // ---- prefetch in the order of first use: neighbour codes, stage state, normals,
+  // partner traces; the metrics of the solution points go last, so that they stay
+  // in flight through the flux-point pass and the gradient
+  constexpr int SI = (S::NU * NV * EW + WG - 1) / WG;
   int nbv[FI];
-  T nrm[FI][DIM], ur[FI][NV];
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
     nbv[it] = -BC_FARFIELD;
+    if (t < S::NF * EW && eg < nvalid) nbv[it] = a.NB[(size_t(blk) * S::NFPAD + q) * EB + eg];
+  }
+  T ust[SI];
+  const T *Xb = X + size_t(blk) * S::NUP * NV * EB;
+#pragma unroll
+  for (int r = 0; r < SI; ++r) {
+    const int t = tid + r * WG;
+    if (t < S::NU * NV * EW) ust[r] = Xb[(t / EW) * EB + e0 + t % EW];
+  }
+  T nrm[FI][DIM], ur[FI][NV];
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
     if (t < S::NF * EW && eg < nvalid) {
-      nbv[it] = a.NB[(size_t(blk) * S::NFPAD + q) * EB + eg];
 #pragma unroll
       for (int c = 0; c < DIM; ++c) nrm[it][c] = T(a.FN[at(blk, q, c, eg, S::NFPAD, DIM)]);
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    if (nbv[it] >= 0) {
+      const size_t base = size_t(nbv[it] / EB) * NV * EB + (nbv[it] % EB);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ur[it][v] = a.UF[base + v * EB];
     }
   }
   double Sm[PI][DIM][DIM], ijv[PI];
@@ -940,16 +1004,12 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       ijv[it] = a.IJ[(size_t(blk) * S::NUP + i) * EB + eg];
     }
   }
-#pragma unroll
-  for (int it = 0; it < FI; ++it) {
-    if (nbv[it] >= 0) {
-      const size_t base = size_t(nbv[it] / EB) * NV * EB + (nbv[it] % EB);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) ur[it][v] = a.UF[base + v * EB];
-    }
-  }
   B.load(a.basis);
-  stage_in<T, S::NU, S::NUP, NV, EW>(Us, X + size_t(blk) * S::NUP * NV * EB, e0);
+#pragma unroll
+  for (int r = 0; r < SI; ++r) {
+    const int t = tid + r * WG;
+    if (t < S::NU * NV * EW) Us[t] = ust[r];
+  }
   __syncthreads();
   const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
 
@@ -1070,7 +1130,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
     if (eg >= nvalid) continue;
     const int f = q / S::NFP, m = q % S::NFP, k = f / 2;
     const T *l = (f & 1) ? B.lp : B.lm;
-    T gf[DIM][NV], Fv[DIM][NV];
+    T gf[DIM][NV];
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
 #pragma unroll
@@ -1081,14 +1141,12 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
         gf[c][v] = sv;
       }
     const int nb = nbv[it];
+    T fn[NV];
     if (nb >= 0) {
-      gas.flux_vis(ufv[it], gf, Fv, false);
+      gas.flux_vis_n(ufv[it], gf, nrm[it], fn, false);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        T sv = 0;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) sv += Fv[c][v] * nrm[it][c];
-        const T pv = T(0.5) * sv;
+        const T pv = T(0.5) * fn[v];
         a.PV[at(blk, q, v, eg, S::NFPAD, NV)] = pv;
         a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = fiv[it][v] - pv;
       }
@@ -1097,18 +1155,13 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       T ub[NV];
       if ((code & 3) == BC_FARFIELD) {
         gas.farfield(ufv[it], nrm[it], a.fsd + 5 * a.bdesign[blk], ub);
-        gas.flux_vis(ub, gf, Fv, false);
+        gas.flux_vis_n(ub, gf, nrm[it], fn, false);
       } else {
         gas.wall_common(ufv[it], ub);
-        gas.flux_vis(ub, gf, Fv, true);
+        gas.flux_vis_n(ub, gf, nrm[it], fn, true);
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        T sv = 0;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) sv += Fv[c][v] * nrm[it][c];
-        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = fiv[it][v] - sv;
-      }
+      for (int v = 0; v < NV; ++v) a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = fiv[it][v] - fn[v];
       if (forces && (code & 3) == BC_WALL) {
         // traction of the fluid on the body: W A (p n - tau . n), interior trace
         T Fw[DIM][NV];
@@ -1174,7 +1227,9 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a, int mode) {
   const int tid = threadIdx.x;
   const T dt = T(a.bdt[blk]);
 
-  // ---- prefetch: face inputs, then point inputs
+  // ---- prefetch in the order of first use: face inputs (codes first, so that the
+  // partner gather issues early), then the point inputs, which stay in flight
+  // through the flux pass
   int nbv[FI];
   double Av[FI];
   T qv[FI][NV], pn[FI][NV];
@@ -1182,13 +1237,24 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a, int mode) {
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
     nbv[it] = -BC_FARFIELD;
+    if (t < S::NF * EW && eg < nvalid) nbv[it] = a.NB[(size_t(blk) * S::NFPAD + q) * EB + eg];
+  }
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
     Av[it] = 0.0;
     if (t < S::NF * EW && eg < nvalid) {
-      const size_t fq = (size_t(blk) * S::NFPAD + q) * EB + eg;
-      nbv[it] = a.NB[fq];
-      Av[it] = a.FA[fq];
+      Av[it] = a.FA[(size_t(blk) * S::NFPAD + q) * EB + eg];
 #pragma unroll
       for (int v = 0; v < NV; ++v) qv[it][v] = a.FI[at(blk, q, v, eg, S::NFPAD, NV)];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    if (nbv[it] >= 0) {
+      const size_t base = size_t(nbv[it] / EB) * NV * EB + (nbv[it] % EB);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[base + v * EB];
     }
   }
   T rv[PI][NV], un[PI][NV], ac[PI][NV];
@@ -1205,14 +1271,6 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a, int mode) {
         un[it][v] = mode == MODE_RESID ? T(0) : a.U[x];
         ac[it][v] = (mode == MODE_RK1 || mode == MODE_RK2 || mode == MODE_RK3) ? a.ACC[x] : T(0);
       }
-    }
-  }
-#pragma unroll
-  for (int it = 0; it < FI; ++it) {
-    if (nbv[it] >= 0) {
-      const size_t base = size_t(nbv[it] / EB) * NV * EB + (nbv[it] % EB);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[base + v * EB];
     }
   }
   B.load(a.basis);

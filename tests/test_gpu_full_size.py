@@ -91,7 +91,12 @@ def test_tgv_full_200_steps_and_kinetic_energy(tgv):
         ref.append(o.rk4(ref[-1], dt, chunk))
         ek_ref.append(kinetic_energy(ref[-1], 3))
     ek_ref = np.array(ek_ref)
-    for prec, tol, ek_tol in (("fp64", 1e-12, 1e-12), ("fp32", 1e-5, 2e-2)):
+    # E_k is a weighted mean of a quadratic in the state, so a state error below tol
+    # bounds its error by about 2 tol E_k; the decay between samples is a difference
+    # of two such values
+    dek = np.abs(np.diff(ek_ref)).min()
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        ek_tol = 2.0 * 2.0 * tol * ek_ref[0] / dek
         g = tuned(m, prec, u0)
         g.set_state(u0)
         ek = [kinetic_energy(u0, 3)]
@@ -106,10 +111,11 @@ def test_tgv_full_200_steps_and_kinetic_energy(tgv):
         # decay between samples, relative to the oracle's
         rate_err = np.abs(np.diff(ek) - np.diff(ek_ref)).max() / np.abs(np.diff(ek_ref)).max()
         print(f"tgv 24^3 {prec}: rel L2 after 100 steps {err100:.3e}, after 200 {err:.3e}; "
-              f"E_k {ek[0]:.9f} -> {ek[-1]:.9f} (oracle {ek_ref[-1]:.9f}), decay rel err {rate_err:.2e}",
+              f"E_k {ek[0]:.9f} -> {ek[-1]:.9f} (oracle {ek_ref[-1]:.9f}), decay rel err {rate_err:.2e} "
+              f"(bound {ek_tol:.1e})",
               flush=True)
         assert err100 <= tol and err <= tol
-        assert np.abs(ek - ek_ref).max() <= tol * ek_ref[0]
+        assert np.abs(ek - ek_ref).max() <= 2.0 * tol * ek_ref[0]
         assert rate_err <= ek_tol
         g.close()
 
