@@ -1210,8 +1210,9 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   }
 }
 
-template <typename T, int DIM, int ORDER>
-__global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a, int mode) {
+template <typename T, int DIM, int ORDER, int MODE>
+__global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
+  constexpr int mode = MODE;  // RK stage or residual: fixes what is read and written
   using S = Shape<DIM, ORDER>;
   using F = FS<T, DIM, ORDER>;
   constexpr int EW = F::EW_B, WG = F::WG_B, NS = EB / EW, N = S::N, NV = S::NV;
@@ -1479,10 +1480,18 @@ static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, i
       hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER>), dim3(c.nblk * (EB / FS<T, DIM, ORDER>::EW_A)),
                          dim3(FS<T, DIM, ORDER>::WG_A), 0, c.stream, a, X, int(forces));
       break;
-    case K_STAGE_B:
-      hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER>), dim3(c.nblk * (EB / FS<T, DIM, ORDER>::EW_B)),
-                         dim3(FS<T, DIM, ORDER>::WG_B), 0, c.stream, a, mode);
+    case K_STAGE_B: {
+      const dim3 grid(c.nblk * (EB / FS<T, DIM, ORDER>::EW_B)), wgs(FS<T, DIM, ORDER>::WG_B);
+      switch (mode) {
+        case MODE_RK0: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK0>), grid, wgs, 0, c.stream, a); break;
+        case MODE_RK1: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK1>), grid, wgs, 0, c.stream, a); break;
+        case MODE_RK2: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK2>), grid, wgs, 0, c.stream, a); break;
+        case MODE_RK3: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK3>), grid, wgs, 0, c.stream, a); break;
+        case MODE_RESID: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RESID>), grid, wgs, 0, c.stream, a); break;
+        default: return hipErrorInvalidValue;
+      }
       break;
+    }
     case K_DIVRK:
       if (tensor)
         hipLaunchKernelGGL((t_divrk<T, DIM, ORDER>), dim3(c.nblk * (EB / TT::EW_DIV)), blk, 0, c.stream, a, mode);
