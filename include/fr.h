@@ -159,7 +159,8 @@ fr_status fr_forces(const fr_mesh *m, int32_t design, double *out);
 fr_status fr_residual(fr_mesh *m, const double *u, double *r);
 
 /* Device pointer and layout of the state, for callers that keep data on
- * the device: layout [block][n_u padded to 16][variables][16 elements]. */
+ * the device: blocks of 16 elements, each split into 4 sub-blocks of 4;
+ * layout [block][sub-block][n_u padded to 16][variables][4 elements]. */
 fr_status fr_state_device(const fr_mesh *m, void **ptr, int64_t *bytes);
 
 /* Kernel-timing hook for benchmarks: runs `steps` RK4 steps with HIP events

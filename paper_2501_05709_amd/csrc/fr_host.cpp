@@ -721,28 +721,28 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
       const int s = int(e % EB);
       for (int i = 0; i < nu; ++i) {
         for (int c = 0; c < dim * dim; ++c)
-          SM[((size_t(blk) * NUP + i) * dim * dim + c) * EB + s] = H.S[(size_t(e) * nu + i) * dim * dim + c];
-        IJ[(size_t(blk) * NUP + i) * EB + s] = 1.0 / H.detJ[size_t(e) * nu + i];
+          SM[lay(blk, i, c, s, NUP, dim * dim)] = H.S[(size_t(e) * nu + i) * dim * dim + c];
+        IJ[lay(blk, i, 0, s, NUP, 1)] = 1.0 / H.detJ[size_t(e) * nu + i];
         for (int c = 0; c < 3; ++c) M->xu[(size_t(g) * nu + i) * 3 + c] = H.xu[(size_t(e) * nu + i) * 3 + c];
       }
       for (int qq = 0; qq < nf; ++qq) {
         const size_t hq = size_t(e) * nf + qq;
-        for (int c = 0; c < dim; ++c) FN[((size_t(blk) * NFPAD + qq) * dim + c) * EB + s] = H.fn[hq * dim + c];
-        FA[(size_t(blk) * NFPAD + qq) * EB + s] = H.fA[hq];
+        for (int c = 0; c < dim; ++c) FN[lay(blk, qq, c, s, NFPAD, dim)] = H.fn[hq * dim + c];
+        FA[lay(blk, qq, 0, s, NFPAD, 1)] = H.fA[hq];
         const int64_t p = H.nbr[hq];
         int code;
         if (p >= 0) {
           const int64_t gp = ds.e0 + p / nf;
           const int qp = int(p % nf);
           auto bs = dev_slot(gp);
-          code = int((bs.first * NFPAD + qp) * EB + bs.second);
+          code = int(lay(bs.first, qp, 0, bs.second, NFPAD, 1));
           M->nbr_canon[size_t(g) * nf + qq] = gp * nf + qp;
         } else {
           const int kind = int(-p);
           code = kind == FR_BC_WALL ? -int(kind | (widx++ << 2)) : -kind;
           M->nbr_canon[size_t(g) * nf + qq] = p;
         }
-        NBt[(size_t(blk) * NFPAD + qq) * EB + s] = code;
+        NBt[lay(blk, qq, 0, s, NFPAD, 1)] = code;
       }
     });
   }

@@ -9,6 +9,17 @@
 namespace fr {
 
 constexpr int EB = 16;  // elements per block: the N extent of one MFMA tile
+constexpr int SB = 4;   // elements per sub-block: contiguous run of one point and channel
+constexpr int NSB = EB / SB;
+
+// Index of (point pt, channel ch) of element slot e in block blk of a per-element
+// array with NPT points and NCH channels.  Layout [block][sub-block][point][channel][SB]:
+// the SB elements of a sub-block are contiguous for each point and channel, and the
+// whole sub-block is one contiguous run, so a workgroup that owns a sub-block reads
+// and writes it in full segments.
+__host__ __device__ inline size_t lay(int64_t blk, int pt, int ch, int e, int NPT, int NCH) {
+  return ((size_t(blk * NSB + e / SB) * NPT + pt) * NCH + ch) * SB + size_t(e % SB);
+}
 
 // Packed boundary code stored in the neighbour table: -(kind | index << 2),
 // index = position of a wall flux point in the compact wall list.
@@ -36,12 +47,12 @@ struct DevArrays {
   void *opInt = nullptr, *opGrad = nullptr, *opGcorr = nullptr, *opDivS = nullptr, *opCorr = nullptr;
   // 1D basis (real): D[n][n], l(-1)[n], l(+1)[n], g_L'[n], g_R'[n]
   void *basis = nullptr;
-  // FP64 geometry
-  double *SM = nullptr;  // [blk][NUP][dim*dim][EB]  S = |J| J^-1
-  double *IJ = nullptr;  // [blk][NUP][EB]          1/|J|
-  double *FN = nullptr;  // [blk][NFPAD][dim][EB]   outward unit normal
-  double *FA = nullptr;  // [blk][NFPAD][EB]        |S^T n_hat|
-  int *NB = nullptr;     // [blk][NFPAD][EB]        partner (blk*NFPAD+q)*EB+slot, or boundary code
+  // FP64 geometry, all in the sub-blocked layout of lay()
+  double *SM = nullptr;  // NUP points, dim*dim channels: S = |J| J^-1
+  double *IJ = nullptr;  // NUP points, 1 channel: 1/|J|
+  double *FN = nullptr;  // NFPAD points, dim channels: outward unit normal
+  double *FA = nullptr;  // NFPAD points, 1 channel: |S^T n_hat|
+  int *NB = nullptr;     // NFPAD points, 1 channel: partner lay(blk, q, 0, slot, NFPAD, 1), or boundary code
   int *bcount = nullptr;   // [blk] valid elements in the block
   int *bdesign = nullptr;  // [blk]
   int64_t *bcanon = nullptr;  // [blk] canonical element index of slot 0

@@ -275,7 +275,7 @@ template <typename T, int D> struct Gas {
 };
 
 __device__ inline size_t at(int64_t blk, int pt, int ch, int e, int NPT, int NCH) {
-  return ((size_t(blk) * NPT + pt) * NCH + ch) * EB + e;
+  return lay(blk, pt, ch, e, NPT, NCH);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,7 +330,7 @@ __device__ inline void grad_epilogue(const KArgs<T> &a, const Gas<T, DIM> &gas, 
   for (int k = 0; k < DIM; ++k)
 #pragma unroll
     for (int c = 0; c < DIM; ++c) Sm[k][c] = a.SM[at(blk, i, k * DIM + c, e, S::NUP, DIM * DIM)];
-  const double ij = a.IJ[(size_t(blk) * S::NUP + i) * EB + e];
+  const double ij = a.IJ[lay(blk, i, 0, e, S::NUP, 1)];
   T gu[DIM][S::NV];
 #pragma unroll
   for (int c = 0; c < DIM; ++c)
@@ -374,7 +374,7 @@ __device__ inline void visc_epilogue(const KArgs<T> &a, const Gas<T, DIM> &gas, 
     nd[c] = a.FN[at(blk, q, c, e, S::NFPAD, DIM)];
     n[c] = T(nd[c]);
   }
-  const int nb = a.NB[(size_t(blk) * S::NFPAD + q) * EB + e];
+  const int nb = a.NB[lay(blk, q, 0, e, S::NFPAD, 1)];
   T fn[S::NV];
   if (nb >= 0) {
     gas.flux_vis_n(uf, gf, n, fn, false);
@@ -397,7 +397,7 @@ __device__ inline void visc_epilogue(const KArgs<T> &a, const Gas<T, DIM> &gas, 
       T Fw[DIM][S::NV];
       gas.flux_vis(uf, gf, Fw, false);
       const double p = double(gas.pressure(uf));
-      const double wA = a.wface[q] * a.FA[(size_t(blk) * S::NFPAD + q) * EB + e];
+      const double wA = a.wface[q] * a.FA[lay(blk, q, 0, e, S::NFPAD, 1)];
       const int64_t w = code >> 2;
 #pragma unroll
       for (int i = 0; i < DIM; ++i) {
@@ -417,15 +417,15 @@ __device__ inline void visc_epilogue(const KArgs<T> &a, const Gas<T, DIM> &gas, 
 template <typename T, int DIM, int ORDER>
 __device__ inline void common_flux(const KArgs<T> &a, int64_t blk, int q, int e, T *b) {
   using S = Shape<DIM, ORDER>;
-  const size_t fq = (size_t(blk) * S::NFPAD + q) * EB + e;
+  const size_t fq = lay(blk, q, 0, e, S::NFPAD, 1);
   const int nb = a.NB[fq];
   const double A = a.FA[fq];
   if (nb >= 0) {
-    const size_t base = size_t(nb / EB) * S::NV * EB + (nb % EB);
+    const size_t base = size_t(nb / SB) * S::NV * SB + (nb % SB);
 #pragma unroll
     for (int v = 0; v < S::NV; ++v) {
       const T f = a.FI[at(blk, q, v, e, S::NFPAD, S::NV)] - a.PV[at(blk, q, v, e, S::NFPAD, S::NV)] +
-                  a.PV[base + v * EB];
+                  a.PV[base + v * SB];
       b[v] = T(A * double(f));
     }
   } else {
@@ -438,7 +438,7 @@ __device__ inline void common_flux(const KArgs<T> &a, int64_t blk, int q, int e,
 template <typename T, int DIM, int ORDER>
 __device__ inline void rk_epilogue(const KArgs<T> &a, int64_t blk, int i, int e, const T *div, int mode, int &bad) {
   using S = Shape<DIM, ORDER>;
-  const double ij = a.IJ[(size_t(blk) * S::NUP + i) * EB + e];
+  const double ij = a.IJ[lay(blk, i, 0, e, S::NUP, 1)];
   const T dt = T(a.bdt[blk]);
 #pragma unroll
   for (int v = 0; v < S::NV; ++v) {
@@ -475,12 +475,12 @@ __device__ inline void face_common(const KArgs<T> &a, const Gas<T, DIM> &gas, in
   T ur[S::NV], n[DIM];
 #pragma unroll
   for (int j = 0; j < DIM; ++j) n[j] = T(a.FN[at(blk, q, j, e, S::NFPAD, DIM)]);
-  const int nb = a.NB[(size_t(blk) * S::NFPAD + q) * EB + e];
+  const int nb = a.NB[lay(blk, q, 0, e, S::NFPAD, 1)];
   if (nb >= 0) {
-    const size_t base = size_t(nb / EB) * S::NV * EB + (nb % EB);
+    const size_t base = size_t(nb / SB) * S::NV * SB + (nb % SB);
 #pragma unroll
     for (int v = 0; v < S::NV; ++v) {
-      ur[v] = a.UF[base + v * EB];
+      ur[v] = a.UF[base + v * SB];
       du[v] = T(0.5) * (ur[v] - uf[v]);
     }
   } else if (((-nb) & 3) == BC_FARFIELD) {
@@ -536,13 +536,13 @@ __global__ __launch_bounds__(256) void k_interp(KArgs<T> a, const T *__restrict_
   typename M::C acc[S::NV];
 #pragma unroll
   for (int v = 0; v < S::NV; ++v) acc[v] = typename M::C{0, 0, 0, 0};
-  const T *Xb = X + size_t(blk) * S::NUP * S::NV * EB;
+  const T *Xb = X + lay(blk, 0, 0, e, S::NUP, S::NV);
 #pragma unroll 4
   for (int kt = 0; kt < S::KTU; ++kt) {
     const T av = a.opInt[(size_t(rt) * S::KTU + kt) * 64 + lane];
     const int pt = kt * 4 + g;
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v) acc[v] = M::mac(av, Xb[(pt * S::NV + v) * EB + e], acc[v]);
+    for (int v = 0; v < S::NV; ++v) acc[v] = M::mac(av, Xb[(pt * S::NV + v) * SB], acc[v]);
   }
   if (e >= a.bcount[blk]) return;
 #pragma unroll
@@ -570,13 +570,13 @@ __global__ __launch_bounds__(256) void k_grad(KArgs<T> a, const T *__restrict__ 
   for (int k = 0; k < DIM; ++k)
 #pragma unroll
     for (int v = 0; v < S::NV; ++v) acc[k][v] = typename M::C{0, 0, 0, 0};
-  const T *Xb = X + size_t(blk) * S::NUP * S::NV * EB;
+  const T *Xb = X + lay(blk, 0, 0, e, S::NUP, S::NV);
 #pragma unroll 2
   for (int kt = 0; kt < S::KTU; ++kt) {
     const int pt = kt * 4 + g;
     T b[S::NV];
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v) b[v] = Xb[(pt * S::NV + v) * EB + e];
+    for (int v = 0; v < S::NV; ++v) b[v] = Xb[(pt * S::NV + v) * SB];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       const T av = a.opGrad[((size_t(k) * S::RTU + rt) * S::KTU + kt) * 64 + lane];
@@ -584,13 +584,13 @@ __global__ __launch_bounds__(256) void k_grad(KArgs<T> a, const T *__restrict__ 
       for (int v = 0; v < S::NV; ++v) acc[k][v] = M::mac(av, b[v], acc[k][v]);
     }
   }
-  const T *Db = a.DU + size_t(blk) * S::NFPAD * S::NV * EB;
+  const T *Db = a.DU + lay(blk, 0, 0, e, S::NFPAD, S::NV);
 #pragma unroll 2
   for (int kt = 0; kt < S::KTF; ++kt) {
     const int pt = kt * 4 + g;
     T b[S::NV];
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v) b[v] = Db[(pt * S::NV + v) * EB + e];
+    for (int v = 0; v < S::NV; ++v) b[v] = Db[(pt * S::NV + v) * SB];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       const T av = a.opGcorr[((size_t(k) * S::RTU + rt) * S::KTF + kt) * 64 + lane];
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(256) void k_grad(KArgs<T> a, const T *__restrict__ 
     if (i >= S::NU) break;
     T u[S::NV], G[DIM][S::NV];
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v) u[v] = Xb[(i * S::NV + v) * EB + e];
+    for (int v = 0; v < S::NV; ++v) u[v] = Xb[(i * S::NV + v) * SB];
 #pragma unroll
     for (int k = 0; k < DIM; ++k)
 #pragma unroll
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(256) void k_visc(KArgs<T> a, int forces) {
   for (int k = 0; k < DIM; ++k)
 #pragma unroll
     for (int v = 0; v < S::NV; ++v) acc[k][v] = typename M::C{0, 0, 0, 0};
-  const T *Gb = a.GU + size_t(blk) * S::NUP * S::NG * EB;
+  const T *Gb = a.GU + lay(blk, 0, 0, e, S::NUP, S::NG);
 #pragma unroll 2
   for (int kt = 0; kt < S::KTU; ++kt) {
     const T av = a.opInt[(size_t(rt) * S::KTU + kt) * 64 + lane];
@@ -639,7 +639,7 @@ __global__ __launch_bounds__(256) void k_visc(KArgs<T> a, int forces) {
     for (int k = 0; k < DIM; ++k)
 #pragma unroll
       for (int v = 0; v < S::NV; ++v)
-        acc[k][v] = M::mac(av, Gb[(pt * S::NG + k * S::NV + v) * EB + e], acc[k][v]);
+        acc[k][v] = M::mac(av, Gb[(pt * S::NG + k * S::NV + v) * SB], acc[k][v]);
   }
   if (e >= a.bcount[blk]) return;
   const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
@@ -670,7 +670,7 @@ __global__ __launch_bounds__(256) void k_divrk(KArgs<T> a, int mode) {
   typename M::C acc[S::NV];
 #pragma unroll
   for (int v = 0; v < S::NV; ++v) acc[v] = typename M::C{0, 0, 0, 0};
-  const T *Fb = a.FT + size_t(blk) * S::NUP * S::NG * EB;
+  const T *Fb = a.FT + lay(blk, 0, 0, e, S::NUP, S::NG);
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
 #pragma unroll 2
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(256) void k_divrk(KArgs<T> a, int mode) {
       const T av = a.opDivS[((size_t(rt) * DIM + k) * S::KTU + kt) * 64 + lane];
       const int pt = kt * 4 + g;
 #pragma unroll
-      for (int v = 0; v < S::NV; ++v) acc[v] = M::mac(av, Fb[(pt * S::NG + k * S::NV + v) * EB + e], acc[v]);
+      for (int v = 0; v < S::NV; ++v) acc[v] = M::mac(av, Fb[(pt * S::NG + k * S::NV + v) * SB], acc[v]);
     }
   }
 #pragma unroll 2
@@ -743,8 +743,8 @@ template <typename T, int N> struct Basis {
 template <typename T, int NPT, int NPTG, int NCH, int EW>
 __device__ inline void stage_in(T *dst, const T *src_blk, int e0) {
   for (int t = threadIdx.x; t < NPT * NCH * EW; t += blockDim.x) {
-    const int e = t % EW, pc = t / EW;
-    dst[t] = src_blk[size_t(pc) * EB + e0 + e];
+    const int e = e0 + t % EW, pc = t / EW;
+    dst[t] = src_blk[(size_t(e / SB) * NPTG * NCH + pc) * SB + e % SB];
   }
 }
 
@@ -966,14 +966,15 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
     nbv[it] = -BC_FARFIELD;
-    if (t < S::NF * EW && eg < nvalid) nbv[it] = a.NB[(size_t(blk) * S::NFPAD + q) * EB + eg];
+    if (t < S::NF * EW && eg < nvalid) nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
   }
   T ust[SI];
   const T *Xb = X + size_t(blk) * S::NUP * NV * EB;
 #pragma unroll
   for (int r = 0; r < SI; ++r) {
     const int t = tid + r * WG;
-    if (t < S::NU * NV * EW) ust[r] = Xb[(t / EW) * EB + e0 + t % EW];
+    const int e = e0 + t % EW;
+    if (t < S::NU * NV * EW) ust[r] = Xb[(size_t(e / SB) * S::NUP * NV + t / EW) * SB + e % SB];
   }
   T nrm[FI][DIM], ur[FI][NV];
 #pragma unroll
@@ -987,9 +988,9 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     if (nbv[it] >= 0) {
-      const size_t base = size_t(nbv[it] / EB) * NV * EB + (nbv[it] % EB);
+      const size_t base = size_t(nbv[it] / SB) * NV * SB + (nbv[it] % SB);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) ur[it][v] = a.UF[base + v * EB];
+      for (int v = 0; v < NV; ++v) ur[it][v] = a.UF[base + v * SB];
     }
   }
   double Sm[PI][DIM][DIM], ijv[PI];
@@ -1001,7 +1002,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       for (int k = 0; k < DIM; ++k)
 #pragma unroll
         for (int c = 0; c < DIM; ++c) Sm[it][k][c] = a.SM[at(blk, i, k * DIM + c, eg, S::NUP, DIM * DIM)];
-      ijv[it] = a.IJ[(size_t(blk) * S::NUP + i) * EB + eg];
+      ijv[it] = a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
     }
   }
   B.load(a.basis);
@@ -1170,7 +1171,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) nd[c] = a.FN[at(blk, q, c, eg, S::NFPAD, DIM)];
         const double p = double(gas.pressure(ufv[it]));
-        const double wA = a.wface[q] * a.FA[(size_t(blk) * S::NFPAD + q) * EB + eg];
+        const double wA = a.wface[q] * a.FA[lay(blk, q, 0, eg, S::NFPAD, 1)];
         const int64_t w = code >> 2;
 #pragma unroll
         for (int ii = 0; ii < DIM; ++ii) {
@@ -1238,14 +1239,14 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
     nbv[it] = -BC_FARFIELD;
-    if (t < S::NF * EW && eg < nvalid) nbv[it] = a.NB[(size_t(blk) * S::NFPAD + q) * EB + eg];
+    if (t < S::NF * EW && eg < nvalid) nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
   }
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
     Av[it] = 0.0;
     if (t < S::NF * EW && eg < nvalid) {
-      Av[it] = a.FA[(size_t(blk) * S::NFPAD + q) * EB + eg];
+      Av[it] = a.FA[lay(blk, q, 0, eg, S::NFPAD, 1)];
 #pragma unroll
       for (int v = 0; v < NV; ++v) qv[it][v] = a.FI[at(blk, q, v, eg, S::NFPAD, NV)];
     }
@@ -1253,9 +1254,9 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     if (nbv[it] >= 0) {
-      const size_t base = size_t(nbv[it] / EB) * NV * EB + (nbv[it] % EB);
+      const size_t base = size_t(nbv[it] / SB) * NV * SB + (nbv[it] % SB);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[base + v * EB];
+      for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[base + v * SB];
     }
   }
   T rv[PI][NV], un[PI][NV], ac[PI][NV];
@@ -1264,7 +1265,7 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
   for (int it = 0; it < PI; ++it) {
     const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
     if (t < S::NU * EW && eg < nvalid) {
-      ijv[it] = a.IJ[(size_t(blk) * S::NUP + i) * EB + eg];
+      ijv[it] = a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const size_t x = at(blk, i, v, eg, S::NUP, NV);
