@@ -422,3 +422,77 @@ def request_trace(seed=0, n_requests=64, rate=4.0, size_scale=1.0, orders=(2, 3,
 
 def points_per_element(dim, order):
     return (order + 1) ** dim
+
+
+# ---------------------------------------------------------------------------
+# acoustic inputs: data surfaces and the exact fields of stationary sources in a
+# uniform stream (the paper's verification cases, Appendix C)
+# ---------------------------------------------------------------------------
+
+def sphere_surface(radius=1.0, n_polar=30, n_azimuth=45):
+    """Equal-area panels on a sphere: n_polar bands equal in cos(theta), n_azimuth panels
+    per band.  Returns panel centres [n, 3], outward unit normals [n, 3], areas [n]."""
+    c = np.linspace(1.0, -1.0, n_polar + 1)
+    th = np.arccos(0.5 * (c[:-1] + c[1:]))
+    ph = (np.arange(n_azimuth) + 0.5) * 2.0 * np.pi / n_azimuth
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    n = np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], axis=-1).reshape(-1, 3)
+    area = 4.0 * np.pi * radius ** 2 / (n_polar * n_azimuth)
+    return radius * n, n, np.full(n.shape[0], area)
+
+
+def stationary_source(kind, x, t, mach, c0=340.75, rho0=1.234, amplitude=1.0, omega=10.0 * np.pi, axis=1):
+    """Exact disturbance field of a stationary monopole or dipole at the origin of a
+    stream of Mach vector `mach`.
+
+    The potential is phi = A / (4 pi R*) exp(i omega (t - R / c0)) (monopole) or its
+    derivative along `axis` (dipole), with the amplitude and phase radii R*, R of the
+    stream; u = grad phi, p' = -rho0 (d/dt + c0 M . grad) phi and rho' = p' / c0^2.
+    x [n, 3], t [nt] -> rho' [nt, n], u [nt, n, 3], p' [nt, n] (real parts).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    M = np.asarray(mach, dtype=np.float64)
+    g2 = 1.0 / (1.0 - M @ M)
+    k = omega / c0
+    Mr = x @ M
+    Rs = np.sqrt((x * x).sum(-1) + g2 * Mr ** 2) / np.sqrt(g2)
+    R = g2 * (Rs - Mr)
+    dRs = (x + g2 * Mr[:, None] * M) / (g2 * Rs[:, None])          # d R* / d x_i
+    dR = g2 * (dRs - M)
+    eye = np.eye(3)
+    ddRs = ((eye + g2 * M[:, None] * M[None, :])[None] / (g2 * Rs[:, None, None])
+            - dRs[:, :, None] * dRs[:, None, :] / Rs[:, None, None])
+    ddR = g2 * ddRs
+    f = np.exp(-1j * k * R) / Rs                                      # spatial factor
+    g = -1j * k * dR - dRs / Rs[:, None]                              # grad f / f
+    dg = -1j * k * ddR - ddRs / Rs[:, None, None] + dRs[:, :, None] * dRs[:, None, :] / Rs[:, None, None] ** 2
+    df = f[:, None] * g                                               # d f / d x_i
+    ddf = f[:, None, None] * (g[:, :, None] * g[:, None, :] + dg)     # d2 f / dx_i dx_j
+    if kind == "monopole":
+        s, ds = f, df
+    elif kind == "dipole":
+        s, ds = df[:, axis], ddf[:, :, axis]
+    else:
+        raise ValueError(kind)
+    C = amplitude / (4.0 * np.pi)
+    e = np.exp(1j * omega * np.asarray(t, dtype=np.float64))[:, None]
+    u = np.real(C * e[:, :, None] * ds[None, :, :])
+    p = np.real(-rho0 * C * e * (1j * omega * s + c0 * (ds @ M))[None, :])
+    return p / c0 ** 2, u, p
+
+
+def acoustic_case(kind="monopole", mach=(0.0, 0.0, 0.5), periods=12, dt_over_T=0.02, radius=1.0,
+                  n_polar=30, n_azimuth=45, c0=340.75, rho0=1.234, gamma=GAMMA, omega=10.0 * np.pi,
+                  amplitude=1.0):
+    """Data-surface samples of a stationary source in a stream (the paper's verification
+    set-up): sphere of `radius`, samples every dt = dt_over_T * period for `periods`."""
+    pts, nrm, area = sphere_surface(radius, n_polar, n_azimuth)
+    T = 2.0 * np.pi / omega
+    dt = dt_over_T * T
+    nt = int(round(periods / dt_over_T)) + 1
+    t = dt * np.arange(nt)
+    rho_p, u, p_p = stationary_source(kind, pts, t, mach, c0, rho0, amplitude=amplitude, omega=omega)
+    p0 = rho0 * c0 ** 2 / gamma
+    return dict(points=pts, normals=nrm, areas=area, rho=rho0 + rho_p, u=u, p=p0 + p_p, dt=dt,
+                mach=np.asarray(mach, dtype=np.float64), c0=c0, rho0=rho0, p0=p0, kind=kind, omega=omega,
+                amplitude=amplitude)
