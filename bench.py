@@ -35,7 +35,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm": 8000.0, "mfma_f32": 157.3, "mfma_f64": 78.6}  # GB/s, TFLOP/s
+PEAK = {"hbm": 8000.0, "mfma_f32": 157.3, "mfma_f64": 78.6, "fp64": 78.6}  # GB/s, TFLOP/s (fp64: vector FMA)
 KERNEL_NAMES = {1: "k_face", 2: "k_grad", 3: "k_visc", 4: "k_divrk", 5: "k_interp", 6: "k_stage_a",
                 7: "k_stage_b"}
 
@@ -291,12 +291,81 @@ def bench_serve(args):
     print(json.dumps(res))
 
 
+def bench_fwh(args):
+    """Far-field pressure at the paper's observer from its airfoil data surface (24,000
+    panels, 4,332 samples, 125 spanwise copies filling 25 chords)."""
+    from paper_2501_05709_amd import workloads as W
+    from paper_2501_05709_amd.solver import FWH
+    case = W.fwh_airfoil_case(seed=0)
+    n = case["n_copies"]
+    g = FWH(case["points"], case["normals"], case["areas"], case["mach"], case["c0"], case["rho0"], case["p0"],
+            case["dt"], case["n_samples"], n_copies=n, copy_shift=case["copy_shift"])
+    t_app = 0.0
+    for rho, u, p in W.fwh_airfoil_samples(case):
+        t0 = time.perf_counter()
+        g.append(rho, u, p)
+        t_app += time.perf_counter() - t0
+    x = case["observer"]
+    for _ in range(max(args.warmup, 1)):
+        t, p = g.pressure(x)
+    ms = []
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        t, p = g.pressure(x)
+        ms.append(g.time_ms())
+    wall = (time.perf_counter() - wall0) / args.steps
+    npan = case["points"].shape[0]
+    work = float(n) * npan * t.size                      # (copy, panel, observer time) triples
+    k_ms = float(np.mean(ms))
+    flops = 64.0 * work                                  # 8 taps x 4 source series, one FMA each
+    # oracle on a bounded sample: one copy of one spanwise row of panels, all samples
+    row = slice(0, 1200)
+    sub = FWH(case["points"][row], case["normals"][row], case["areas"][row], case["mach"], case["c0"],
+              case["rho0"], case["p0"], case["dt"], case["n_samples"])
+    rows = []
+    for rho, u, pp in W.fwh_airfoil_samples(case):
+        sub.append(rho[:, row], u[:, row], pp[:, row])
+        rows.append((rho[:, row], u[:, row], pp[:, row]))
+    rho = np.concatenate([r[0] for r in rows])
+    u = np.concatenate([r[1] for r in rows])
+    pp = np.concatenate([r[2] for r in rows])
+    ts, ps = sub.pressure(x)
+    cpu = err = None
+    if not args.no_cpu_baseline:
+        from oracle import fwh as ofwh
+        t0 = time.perf_counter()
+        to, po, _, _ = ofwh.observer_pressure(case["points"][row], case["normals"][row], case["areas"][row], rho, u,
+                                              pp, case["dt"], x, case["mach"], case["c0"], case["rho0"], case["p0"])
+        tc = time.perf_counter() - t0
+        err = float(np.abs(ps - po).max() / np.abs(po).max())
+        cpu = {"value": 1200.0 * to.size / tc, "unit": "panel-samples/s", "cores": 1, "kind": "oracle",
+               "sample": f"one copy of one spanwise row (1,200 panels), all {case['n_samples']} samples, "
+                         f"numpy FP64, {tc:.1f} s"}
+    res = {
+        "metric": "FW-H far-field pressure: (copy, panel, observer-time) triples per second",
+        "value": round(work / (k_ms * 1e-3), 1), "unit": "panel-samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(k_ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"airfoil data surface {npan} panels x {n} spanwise copies (25 chords), "
+                               f"{case['n_samples']} samples, one observer 10 chords below the trailing edge",
+                   "observer_times": int(t.size)},
+        "wall_ms_per_step": round(wall * 1e3, 3), "append_s": round(t_app, 3),
+        "roofline": {"bound": "alu", "achieved": round(flops / (k_ms * 1e-3) / 1e12, 2), "peak": PEAK["fp64"],
+                     "unit": "TFLOP/s", "frac": round(flops / (k_ms * 1e-3) / 1e12 / PEAK["fp64"], 4),
+                     "kernel": "k_fwh_sum", "traffic": None},
+        "rel_err_vs_oracle_row": err,
+        "p_rms": float(np.sqrt(np.mean((p - p.mean()) ** 2))),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="tgv", choices=["tgv", "airfoil", "batch", "serve"])
+    ap.add_argument("--workload", default="tgv", choices=["tgv", "airfoil", "batch", "serve", "fwh"])
     ap.add_argument("--requests", type=int, default=64, help="serve: requests in the trace")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: mean arrivals per second")
     ap.add_argument("--budget-gb", type=float, default=96.0, help="serve: HBM budget of the pool")
@@ -327,6 +396,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "fwh":
+        return bench_fwh(args)
     m, desc = build_workload(args.workload)
     g32 = FRMesh(m, "fp32")
     xyz = g32.solution_points().reshape(-1, 3)

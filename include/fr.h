@@ -228,6 +228,83 @@ fr_status fr_pool_result(fr_pool *p, int64_t slot, double *out, double *u);
 /* used[0] = bytes held, used[1] = running requests. */
 fr_status fr_pool_usage(const fr_pool *p, int64_t *used);
 
+/* ---- Far-field acoustics: FW-H from a permeable data surface ----------
+ *
+ * The acoustic pressure at an observer from flow samples on a stationary
+ * permeable data surface in a uniform stream (the paper's Appendix A source
+ * terms and Appendix B solution of the FW-H equation with a moving medium,
+ * quadrupole term dropped), summed by the advanced-time approach of
+ * Appendix B, with spanwise copies of the surface (Section 3.3: the data
+ * surface of a spanwise-periodic flow is repeated along the span).
+ *
+ *   Q   = rho (u_n + U_n) - rho0 U_n,  L_i = (p - p0) n_i + rho u_i (u_n + U_n)
+ *   4 pi p'_T = sum_S [(1 - M_R) Qdot / R* - c0 Q M_R* / R*^2] dS
+ *   4 pi p'_L = sum_S [Ldot_R / (c0 R*) + L_R* / R*^2] dS
+ *
+ * with u the flow velocity relative to the stream (disturbance velocity),
+ * R*, R the amplitude and phase radii of the stream, and every panel's
+ * samples arriving at t = tau + R / c0.  Time derivatives are fourth-order
+ * central differences (the two samples at each end of the record have
+ * none); panel series are interpolated to the observer times by cubic
+ * Lagrange interpolation.  The observer times are spaced by the sampling
+ * interval dt and run from the latest first arrival plus dt to the earliest
+ * last arrival less 2 dt, so that every stencil lies inside every panel's
+ * record.  FP64 throughout; results do not depend on launch shapes (fixed
+ * summation order).
+ */
+typedef struct fr_fwh fr_fwh;
+
+typedef struct {
+  int64_t n_points;        /* panels of one copy of the data surface */
+  const double *points;    /* [n_points][3] panel centres (copied) */
+  const double *normals;   /* [n_points][3] outward unit normals (copied) */
+  const double *areas;     /* [n_points] panel areas (copied) */
+  int32_t n_copies;        /* >= 1; copy k sits at (k - (n_copies - 1) / 2) copy_shift */
+  double copy_shift[3];
+  double mach[3];          /* free-stream Mach vector, |M| < 1 */
+  double c0, rho0, p0;     /* free-stream sound speed, density, pressure */
+  double dt, tau0;         /* sampling interval, time of the first sample */
+  int64_t capacity;        /* samples per panel the record holds, >= 8 */
+  int32_t device;
+  void *stream;            /* hipStream_t, or NULL */
+  fr_alloc_fn alloc;       /* optional device allocator, as in fr_mesh_desc */
+  fr_free_fn free;
+  void *alloc_ctx;
+} fr_fwh_desc;
+
+/* Create a record of capacity * n_points samples on the device
+ * (4 * 8 bytes per sample).  FR_E_ARG for an invalid descriptor. */
+fr_status fr_fwh_create(const fr_fwh_desc *desc, fr_fwh **out);
+void fr_fwh_destroy(fr_fwh *h);
+
+/* Append n snapshots: host [n][n_points][5] = rho, u1, u2, u3, p with u the
+ * disturbance velocity; their source strengths are formed on the device.
+ * FR_E_ARG when the record would exceed its capacity. */
+fr_status fr_fwh_append(fr_fwh *h, int64_t n, const double *samples);
+
+/* Snapshots recorded so far. */
+fr_status fr_fwh_samples(const fr_fwh *h, int64_t *n);
+
+/* Observer-time window for observer[3]: first time and number of times.
+ * FR_E_STATE if the record is shorter than the spread of arrival times. */
+fr_status fr_fwh_window(fr_fwh *h, const double *observer, double *t_start, int64_t *n_out);
+
+/* p'(t) at observer[3] on the window's times, into host p[capacity]; its
+ * thickness and loading parts into p_thickness and p_loading when those are
+ * not NULL.  FR_E_ARG if capacity is below the window length. */
+fr_status fr_fwh_pressure(fr_fwh *h, const double *observer, int64_t capacity, double *t_start,
+                          int64_t *n_out, double *p, double *p_thickness, double *p_loading);
+
+/* p'(t) at observer[3] on the caller's grid t_start + m dt, m < n, which must
+ * lie inside the window of fr_fwh_window (FR_E_ARG otherwise): to align
+ * several observers or runs on one time grid. */
+fr_status fr_fwh_pressure_at(fr_fwh *h, const double *observer, double t_start, int64_t n, double *p,
+                             double *p_thickness, double *p_loading);
+
+/* Device time (ms) of the last fr_fwh_pressure or fr_fwh_pressure_at (HIP
+ * events on its stream around the summation kernels). */
+fr_status fr_fwh_time_ms(const fr_fwh *h, double *ms);
+
 const char *fr_last_error(void);
 
 #ifdef __cplusplus

@@ -40,6 +40,17 @@ class MeshDesc(ctypes.Structure):
     ]
 
 
+class FwhDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_points", ctypes.c_int64), ("points", _dp), ("normals", _dp), ("areas", _dp),
+        ("n_copies", ctypes.c_int32), ("copy_shift", ctypes.c_double * 3), ("mach", ctypes.c_double * 3),
+        ("c0", ctypes.c_double), ("rho0", ctypes.c_double), ("p0", ctypes.c_double),
+        ("dt", ctypes.c_double), ("tau0", ctypes.c_double), ("capacity", ctypes.c_int64),
+        ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
+        ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
+    ]
+
+
 # every function declared in include/fr.h: name -> (restype, argtypes)
 SIGNATURES = {
     "fr_mesh_create": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(ctypes.c_void_p)]),
@@ -72,6 +83,14 @@ SIGNATURES = {
     "fr_pool_collect": (ctypes.c_int, [ctypes.c_void_p, _i64p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "fr_pool_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp, _dp]),
     "fr_pool_usage": (ctypes.c_int, [ctypes.c_void_p, _i64p]),
+    "fr_fwh_create": (ctypes.c_int, [ctypes.POINTER(FwhDesc), ctypes.POINTER(ctypes.c_void_p)]),
+    "fr_fwh_destroy": (None, [ctypes.c_void_p]),
+    "fr_fwh_append": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp]),
+    "fr_fwh_samples": (ctypes.c_int, [ctypes.c_void_p, _i64p]),
+    "fr_fwh_window": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _i64p]),
+    "fr_fwh_pressure": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int64, _dp, _i64p, _dp, _dp, _dp]),
+    "fr_fwh_pressure_at": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp]),
+    "fr_fwh_time_ms": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "fr_last_error": (ctypes.c_char_p, []),
 }
 

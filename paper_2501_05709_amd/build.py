@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfr.so")
-SOURCES = ["fr_kernels.hip", "fr_host.cpp", "fr_pool.cpp"]
+SOURCES = ["fr_kernels.hip", "fr_host.cpp", "fr_pool.cpp", "fr_fwh.hip"]
 ARCH = "gfx950"
 
 

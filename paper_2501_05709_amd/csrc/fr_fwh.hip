@@ -1,0 +1,540 @@
+// Far-field acoustic pressure from samples on a stationary permeable data surface in a
+// uniform stream: the moving-medium time-domain solution of the FW-H equation without
+// the quadrupole term (the paper's Appendices A and B), summed by the advanced-time
+// approach, with spanwise copies of the surface.  FP64 throughout.
+//
+// Device layout: the source strengths of every sample are formed when the sample is
+// appended and kept as four time series per panel, [Q, L1, L2, L3][panel][time], time
+// contiguous.  For one observer:
+//   k_fwh_delay   per (copy, panel): arrival delay R / c0; per-block min and max
+//   (host)        the common observer-time window from the extreme delays
+//   k_fwh_sum     per (panel chunk, time chunk): for every copy and panel of the chunk,
+//                 the panel's integrands at the window's observer times, as one 8-tap
+//                 stencil over its series (cubic interpolation in source time composed
+//                 with the fourth-order time derivative), weighted by the panel's
+//                 geometric factors; partial sums per panel chunk
+//   k_fwh_reduce  per observer time: the partial sums in fixed chunk order
+// Because the surface and the observer are stationary and the observer times are spaced
+// by the sampling interval, each panel's fractional delay and hence its stencil weights
+// are the same for every observer time: the sum is a delay-and-sum over the series.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fr.h"
+#include "fr_internal.hpp"
+
+namespace {
+
+constexpr int NQ = 4;          // Q, L1, L2, L3
+constexpr int SUM_WG = 256;    // threads of k_fwh_sum
+constexpr int SUM_OUT = 8;     // consecutive observer times per thread
+constexpr int SUM_PANELS = 32; // panels per chunk
+constexpr int SUM_PAIRS = 64;  // (copy, panel) pairs whose weights share the LDS
+
+struct Err {
+  fr_status code;
+  std::string msg;
+};
+[[noreturn]] void fail(fr_status c, const std::string &m) { throw Err{c, m}; }
+void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) fail(FR_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+template <class F> fr_status guarded(F &&f) {
+  try {
+    f();
+    return FR_OK;
+  } catch (const Err &e) {
+    fr::set_last_error(e.msg.c_str());
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    fr::set_last_error("host allocation failed");
+    return FR_E_NOMEM;
+  }
+}
+
+struct Stream {
+  double mach[3], U[3], c0, rho0, p0, g2;
+};
+
+// amplitude radius R*, phase radius R and their gradients for r = x - y (Appendix B)
+struct Radii {
+  double Rs, R, gRs[3], gR[3];
+};
+__device__ inline Radii radii(const double *x, const double *y, const Stream &s) {
+  Radii o;
+  double r[3], rr = 0.0, Mr = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    r[i] = x[i] - y[i];
+    rr += r[i] * r[i];
+    Mr += s.mach[i] * r[i];
+  }
+  o.Rs = sqrt(rr + s.g2 * Mr * Mr) / sqrt(s.g2);
+  o.R = s.g2 * (o.Rs - Mr);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    o.gRs[i] = (r[i] + s.g2 * Mr * s.mach[i]) / (s.g2 * o.Rs);
+    o.gR[i] = s.g2 * (o.gRs[i] - s.mach[i]);
+  }
+  return o;
+}
+
+__device__ inline void panel_position(const double *geo, int64_t j, int c, int ncopy, const double *shift,
+                                      double *y) {
+  const double k = double(c) - 0.5 * double(ncopy - 1);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) y[i] = geo[j * 7 + i] + k * shift[i];
+}
+
+// source strengths of appended snapshots (Appendix A, stationary surface):
+// Q = rho (u_n + U_n) - rho0 U_n, L_i = (p - p0) n_i + rho u_i (u_n + U_n)
+__global__ __launch_bounds__(256) void k_fwh_append(const double *__restrict__ samples, const double *__restrict__ geo,
+                                                    int64_t np, int64_t nsnap, int64_t k0, int64_t cap, Stream s,
+                                                    double *__restrict__ src) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= np * nsnap) return;
+  const int64_t j = t % np, k = t / np;
+  const double *x = samples + (k * np + j) * 5;
+  const double *n = geo + j * 7 + 3;
+  const double rho = x[0], p = x[4];
+  const double un = x[1] * n[0] + x[2] * n[1] + x[3] * n[2];
+  const double Un = s.U[0] * n[0] + s.U[1] * n[1] + s.U[2] * n[2];
+  const double flux = rho * (un + Un);
+  const int64_t col = j * cap + k0 + k;
+  src[0 * np * cap + col] = flux - s.rho0 * Un;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) src[(1 + i) * np * cap + col] = (p - s.p0) * n[i] + flux * x[1 + i];
+}
+
+__device__ inline double arrival_delay(const double *geo, int64_t cj, int64_t np, int ncopy, const double *shift,
+                                       const double *xo, const Stream &s) {
+  double y[3];
+  panel_position(geo, cj % np, int(cj / np), ncopy, shift, y);
+  return radii(xo, y, s).R / s.c0;
+}
+
+struct Geo3 {
+  double shift[3], xo[3];
+};
+
+// arrival delay of every (copy, panel); per-block minimum and maximum
+__global__ __launch_bounds__(256) void k_fwh_delay(const double *__restrict__ geo, int64_t np, int ncopy, Geo3 g,
+                                                   Stream s, double *__restrict__ mm) {
+  __shared__ double lo[256], hi[256];
+  const int64_t n = np * ncopy;
+  double a = INFINITY, b = -INFINITY;
+  for (int64_t cj = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; cj < n; cj += int64_t(gridDim.x) * blockDim.x) {
+    const double d = arrival_delay(geo, cj, np, ncopy, g.shift, g.xo, s);
+    a = fmin(a, d);
+    b = fmax(b, d);
+  }
+  lo[threadIdx.x] = a;
+  hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+      lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + w]);
+      hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    mm[2 * blockIdx.x] = lo[0];
+    mm[2 * blockIdx.x + 1] = hi[0];
+  }
+}
+
+struct Window {
+  double t_start, dt, tau0;
+  int64_t n_out, nt;
+  double t_end;  // end of the common window (the grid's last time is at most this)
+};
+
+// Thickness and loading integrands of every copy and panel of one chunk at the observer
+// times of one time chunk, summed; partial sums per chunk: part[chunk][2][n_out].
+// The (copy, panel) pairs of the chunk go in batches of SUM_PAIRS: one thread per pair
+// forms the pair's stencil weights into LDS, then every thread applies them to its
+// SUM_OUT consecutive observer times.
+__global__ __launch_bounds__(SUM_WG) void k_fwh_sum(const double *__restrict__ src, const double *__restrict__ geo,
+                                                    int64_t np, int64_t cap, int ncopy, Geo3 g, Stream s, Window w,
+                                                    double *__restrict__ part) {
+  __shared__ double Wt[SUM_PAIRS][NQ * 8];
+  __shared__ int64_t Wb[SUM_PAIRS];
+  __shared__ int Wj[SUM_PAIRS];
+  const int64_t chunk = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int64_t m0 = (int64_t(blockIdx.x) * SUM_WG + tid) * SUM_OUT;
+  const int64_t nv = w.nt - 4;  // samples with a time derivative
+  double accT[SUM_OUT], accL[SUM_OUT];
+#pragma unroll
+  for (int o = 0; o < SUM_OUT; ++o) accT[o] = accL[o] = 0.0;
+  const int64_t j0 = chunk * SUM_PANELS, j1 = j0 + SUM_PANELS < np ? j0 + SUM_PANELS : np;
+  const int64_t npair = (j1 - j0) * ncopy;  // pair q: panel j0 + q / ncopy, copy q % ncopy
+  for (int64_t q0 = 0; q0 < npair; q0 += SUM_PAIRS) {
+    const int nb = int(npair - q0 < SUM_PAIRS ? npair - q0 : SUM_PAIRS);
+    if (tid < nb) {
+      const int64_t j = j0 + (q0 + tid) / ncopy;
+      const int c = int((q0 + tid) % ncopy);
+      double y[3];
+      panel_position(geo, j, c, ncopy, g.shift, y);
+      const Radii r = radii(g.xo, y, s);
+      const double area = geo[j * 7 + 6];
+      // geometric factors of the integrands (Appendix B), times the panel area
+      const double MR = s.mach[0] * r.gR[0] + s.mach[1] * r.gR[1] + s.mach[2] * r.gR[2];
+      const double MRs = s.mach[0] * r.gRs[0] + s.mach[1] * r.gRs[1] + s.mach[2] * r.gRs[2];
+      double a[NQ], b[NQ];
+      a[0] = area * (1.0 - MR) / r.Rs;            // x Qdot
+      b[0] = -area * s.c0 * MRs / (r.Rs * r.Rs);  // x Q
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        a[1 + i] = area * r.gR[i] / (s.c0 * r.Rs);   // x Ldot_i
+        b[1 + i] = area * r.gRs[i] / (r.Rs * r.Rs);  // x L_i
+      }
+      // position of observer time 0 among the panel's derivative-bearing samples; the
+      // clamp keeps every stencil inside the record (it only absorbs rounding)
+      const double pos0 = (w.t_start - w.tau0 - r.R / s.c0) / w.dt - 2.0;
+      int64_t i0 = int64_t(floor(pos0));
+      const int64_t i0max = nv - 3 - (w.n_out - 1);
+      i0 = i0 > i0max ? i0max : i0;
+      i0 = i0 < 1 ? 1 : i0;
+      const double sf = pos0 - double(i0);
+      // cubic Lagrange weights (nodes -1..2) and their composition with the
+      // fourth-order derivative (1, -8, 0, 8, -1) / 12 dt: 8 taps from sample i0 - 1
+      const double l[4] = {-sf * (sf - 1.0) * (sf - 2.0) / 6.0, (sf + 1.0) * (sf - 1.0) * (sf - 2.0) / 2.0,
+                           -(sf + 1.0) * sf * (sf - 2.0) / 2.0, (sf + 1.0) * sf * (sf - 1.0) / 6.0};
+      double wv[8], wd[8];
+#pragma unroll
+      for (int d = 0; d < 8; ++d) wv[d] = wd[d] = 0.0;
+      const double fd[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
+      const double idt = 1.0 / (12.0 * w.dt);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        wv[u + 2] += l[u];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) wd[u + v] += l[u] * fd[v] * idt;
+      }
+#pragma unroll
+      for (int x = 0; x < NQ; ++x)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) Wt[tid][x * 8 + d] = a[x] * wd[d] + b[x] * wv[d];
+      Wb[tid] = i0 - 1;
+      Wj[tid] = int(j - j0);
+    }
+    __syncthreads();
+    if (m0 < w.n_out) {
+      const bool full = m0 + SUM_OUT <= w.n_out;
+      for (int p = 0; p < nb; ++p) {
+        const int64_t base = Wb[p] + m0;  // sample of tap 0 for observer time m0
+        const int64_t j = j0 + Wj[p];
+#pragma unroll
+        for (int x = 0; x < NQ; ++x) {
+          const double *X = src + (x * np + j) * cap + base;
+          double xs[SUM_OUT + 7];
+          if (full) {
+#pragma unroll
+            for (int d = 0; d < SUM_OUT + 7; ++d) xs[d] = X[d];
+          } else {
+            // last chunk: only the samples of observer times inside the window
+            const int nvalid = int(w.n_out - m0) + 7;
+#pragma unroll
+            for (int d = 0; d < SUM_OUT + 7; ++d) xs[d] = d < nvalid ? X[d] : 0.0;
+          }
+#pragma unroll
+          for (int o = 0; o < SUM_OUT; ++o) {
+            double sv = 0.0;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) sv += Wt[p][x * 8 + d] * xs[o + d];
+            if (x == 0) accT[o] += sv;
+            else accL[o] += sv;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int o = 0; o < SUM_OUT; ++o) {
+    const int64_t m = m0 + o;
+    if (m >= w.n_out) break;
+    part[(chunk * 2 + 0) * w.n_out + m] = accT[o];
+    part[(chunk * 2 + 1) * w.n_out + m] = accL[o];
+  }
+}
+
+// p'_T, p'_L and p' at each observer time: partial sums in chunk order, over 4 pi
+__global__ __launch_bounds__(256) void k_fwh_reduce(const double *__restrict__ part, int64_t nchunk, int64_t n_out,
+                                                    double *__restrict__ out) {
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= n_out) return;
+  double t = 0.0, l = 0.0;
+  for (int64_t c = 0; c < nchunk; ++c) {
+    t += part[(c * 2 + 0) * n_out + m];
+    l += part[(c * 2 + 1) * n_out + m];
+  }
+  const double f = 1.0 / (4.0 * M_PI);
+  out[m] = (t + l) * f;
+  out[n_out + m] = t * f;
+  out[2 * n_out + m] = l * f;
+}
+
+}  // namespace
+
+struct fr_fwh {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  fr_alloc_fn alloc = nullptr;
+  fr_free_fn free = nullptr;
+  void *ctx = nullptr;
+  int64_t np = 0, cap = 0, nt = 0;
+  int ncopy = 1;
+  double shift[3] = {0, 0, 0}, dt = 0, tau0 = 0;
+  Stream s{};
+  double *geo = nullptr, *src = nullptr, *stage = nullptr, *mm = nullptr, *part = nullptr, *out = nullptr;
+  size_t stage_bytes = 0, part_bytes = 0, out_bytes = 0;
+  std::vector<void *> owned;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = 0.0;
+
+  void *dalloc(size_t n) {
+    void *p = nullptr;
+    if (alloc) {
+      p = alloc(n, ctx, stream);
+      if (!p) fail(FR_E_NOMEM, "device allocation callback failed");
+    } else if (hipMalloc(&p, n) != hipSuccess) {
+      fail(FR_E_NOMEM, "hipMalloc failed");
+    }
+    owned.push_back(p);
+    return p;
+  }
+  void dfree(void *p) {
+    if (!p) return;
+    owned.erase(std::remove(owned.begin(), owned.end(), p), owned.end());
+    if (free) free(p, ctx, stream);
+    else (void)hipFree(p);
+  }
+  ~fr_fwh() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void *p : owned) {
+      if (free) free(p, ctx, stream);
+      else (void)hipFree(p);
+    }
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+  }
+  // device scratch that grows on demand: partial sums and outputs
+  double *grow(double *&p, size_t &have, size_t need) {
+    if (need > have) {
+      dfree(p);
+      p = (double *)dalloc(need);
+      have = need;
+    }
+    return p;
+  }
+  // observer-time window of the common record (the oracle's rule, same arithmetic)
+  Window window(const double *xo) {
+    if (nt < 8) fail(FR_E_STATE, "fewer than 8 samples recorded");
+    Geo3 g;
+    for (int i = 0; i < 3; ++i) {
+      g.shift[i] = shift[i];
+      g.xo[i] = xo[i];
+    }
+    const int blocks = 64;
+    hipLaunchKernelGGL(k_fwh_delay, dim3(blocks), dim3(256), 0, stream, geo, np, ncopy, g, s, mm);
+    hip_check(hipGetLastError(), "delay kernel");
+    std::vector<double> h(2 * blocks);
+    hip_check(hipMemcpyAsync(h.data(), mm, h.size() * sizeof(double), hipMemcpyDeviceToHost, stream), "delay copy");
+    hip_check(hipStreamSynchronize(stream), "delay sync");
+    double dmin = INFINITY, dmax = -INFINITY;
+    for (int b = 0; b < blocks; ++b) {
+      dmin = std::min(dmin, h[2 * b]);
+      dmax = std::max(dmax, h[2 * b + 1]);
+    }
+    Window w;
+    w.dt = dt;
+    w.tau0 = tau0;
+    w.nt = nt;
+    w.t_start = (tau0 + 2 * dt + dmax) + dt;
+    const double t_end = (tau0 + double(nt - 3) * dt + dmin) - 2.0 * dt;
+    w.t_end = t_end;
+    w.n_out = int64_t(std::floor((t_end - w.t_start) / dt + 1e-9)) + 1;
+    if (w.n_out <= 0) fail(FR_E_STATE, "record too short for the spread of arrival times");
+    if (w.n_out > nt - 7) fail(FR_E_STATE, "observer window longer than the record");
+    return w;
+  }
+};
+
+extern "C" {
+
+fr_status fr_fwh_create(const fr_fwh_desc *d, fr_fwh **out) {
+  return guarded([&] {
+    if (!out) fail(FR_E_ARG, "null output");
+    *out = nullptr;
+    if (!d || d->n_points <= 0 || !d->points || !d->normals || !d->areas || d->n_copies < 1 || d->capacity < 8 ||
+        !(d->dt > 0.0) || !(d->c0 > 0.0))
+      fail(FR_E_ARG, "invalid FW-H descriptor");
+    const double m2 = d->mach[0] * d->mach[0] + d->mach[1] * d->mach[1] + d->mach[2] * d->mach[2];
+    if (!(m2 < 1.0)) fail(FR_E_ARG, "free-stream Mach number must be below 1");
+    hip_check(hipSetDevice(d->device), "hipSetDevice");
+    auto *h = new fr_fwh();
+    try {
+      h->device = d->device;
+      h->stream = (hipStream_t)d->stream;
+      h->alloc = d->alloc;
+      h->free = d->free;
+      h->ctx = d->alloc_ctx;
+      h->np = d->n_points;
+      h->cap = d->capacity;
+      h->ncopy = d->n_copies;
+      h->dt = d->dt;
+      h->tau0 = d->tau0;
+      for (int i = 0; i < 3; ++i) {
+        h->shift[i] = d->copy_shift[i];
+        h->s.mach[i] = d->mach[i];
+        h->s.U[i] = d->c0 * d->mach[i];
+      }
+      h->s.c0 = d->c0;
+      h->s.rho0 = d->rho0;
+      h->s.p0 = d->p0;
+      h->s.g2 = 1.0 / (1.0 - m2);
+      std::vector<double> g(size_t(h->np) * 7);
+      for (int64_t j = 0; j < h->np; ++j) {
+        for (int i = 0; i < 3; ++i) {
+          g[j * 7 + i] = d->points[j * 3 + i];
+          g[j * 7 + 3 + i] = d->normals[j * 3 + i];
+        }
+        g[j * 7 + 6] = d->areas[j];
+      }
+      h->geo = (double *)h->dalloc(g.size() * sizeof(double));
+      hip_check(hipMemcpyAsync(h->geo, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice, h->stream),
+                "geometry upload");
+      h->src = (double *)h->dalloc(size_t(NQ) * h->np * h->cap * sizeof(double));
+      h->mm = (double *)h->dalloc(2 * 64 * sizeof(double));
+      hip_check(hipEventCreate(&h->ev0), "event");
+      hip_check(hipEventCreate(&h->ev1), "event");
+      hip_check(hipStreamSynchronize(h->stream), "create sync");
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+  });
+}
+
+void fr_fwh_destroy(fr_fwh *h) { delete h; }
+
+fr_status fr_fwh_append(fr_fwh *h, int64_t n, const double *samples) {
+  return guarded([&] {
+    if (!h || n < 0 || (n > 0 && !samples)) fail(FR_E_ARG, "bad argument");
+    if (h->nt + n > h->cap) fail(FR_E_ARG, "record capacity exceeded");
+    if (n == 0) return;
+    hip_check(hipSetDevice(h->device), "hipSetDevice");
+    const size_t bytes = size_t(n) * h->np * 5 * sizeof(double);
+    h->grow(h->stage, h->stage_bytes, bytes);
+    hip_check(hipMemcpyAsync(h->stage, samples, bytes, hipMemcpyHostToDevice, h->stream), "sample upload");
+    const int64_t thr = n * h->np;
+    hipLaunchKernelGGL(k_fwh_append, dim3((thr + 255) / 256), dim3(256), 0, h->stream, h->stage, h->geo, h->np, n,
+                       h->nt, h->cap, h->s, h->src);
+    hip_check(hipGetLastError(), "append kernel");
+    hip_check(hipStreamSynchronize(h->stream), "append sync");
+    h->nt += n;
+  });
+}
+
+fr_status fr_fwh_samples(const fr_fwh *h, int64_t *n) {
+  return guarded([&] {
+    if (!h || !n) fail(FR_E_ARG, "bad argument");
+    *n = h->nt;
+  });
+}
+
+fr_status fr_fwh_window(fr_fwh *h, const double *observer, double *t_start, int64_t *n_out) {
+  return guarded([&] {
+    if (!h || !observer || !t_start || !n_out) fail(FR_E_ARG, "bad argument");
+    hip_check(hipSetDevice(h->device), "hipSetDevice");
+    const Window w = h->window(observer);
+    *t_start = w.t_start;
+    *n_out = w.n_out;
+  });
+}
+
+}  // extern "C"
+
+namespace {
+// p' on the grid w (inside the common window) into host p, p_thickness, p_loading
+void fwh_compute(fr_fwh *h, const double *observer, const Window &w, double *p, double *p_thickness,
+                 double *p_loading) {
+  const int64_t nchunk = (h->np + SUM_PANELS - 1) / SUM_PANELS;
+  if (nchunk > 65535) fail(FR_E_UNSUPPORTED, "too many panels for one launch");
+  h->grow(h->part, h->part_bytes, size_t(nchunk) * 2 * w.n_out * sizeof(double));
+  h->grow(h->out, h->out_bytes, size_t(3) * w.n_out * sizeof(double));
+  Geo3 g;
+  for (int i = 0; i < 3; ++i) {
+    g.shift[i] = h->shift[i];
+    g.xo[i] = observer[i];
+  }
+  const int64_t per_block = int64_t(SUM_WG) * SUM_OUT;
+  const dim3 grid(unsigned((w.n_out + per_block - 1) / per_block), unsigned(nchunk));
+  hip_check(hipEventRecord(h->ev0, h->stream), "event");
+  hipLaunchKernelGGL(k_fwh_sum, grid, dim3(SUM_WG), 0, h->stream, h->src, h->geo, h->np, h->cap, h->ncopy, g, h->s, w,
+                     h->part);
+  hip_check(hipGetLastError(), "sum kernel");
+  hipLaunchKernelGGL(k_fwh_reduce, dim3(unsigned((w.n_out + 255) / 256)), dim3(256), 0, h->stream, h->part, nchunk,
+                     w.n_out, h->out);
+  hip_check(hipGetLastError(), "reduce kernel");
+  hip_check(hipEventRecord(h->ev1, h->stream), "event");
+  const size_t nb = size_t(w.n_out) * sizeof(double);
+  hip_check(hipMemcpyAsync(p, h->out, nb, hipMemcpyDeviceToHost, h->stream), "copy p");
+  if (p_thickness)
+    hip_check(hipMemcpyAsync(p_thickness, h->out + w.n_out, nb, hipMemcpyDeviceToHost, h->stream), "copy pT");
+  if (p_loading)
+    hip_check(hipMemcpyAsync(p_loading, h->out + 2 * w.n_out, nb, hipMemcpyDeviceToHost, h->stream), "copy pL");
+  hip_check(hipStreamSynchronize(h->stream), "pressure sync");
+  float ms = 0.f;
+  hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1), "elapsed");
+  h->last_ms = ms;
+}
+}  // namespace
+
+extern "C" {
+
+fr_status fr_fwh_pressure(fr_fwh *h, const double *observer, int64_t capacity, double *t_start, int64_t *n_out,
+                          double *p, double *p_thickness, double *p_loading) {
+  return guarded([&] {
+    if (!h || !observer || !t_start || !n_out || !p) fail(FR_E_ARG, "bad argument");
+    hip_check(hipSetDevice(h->device), "hipSetDevice");
+    const Window w = h->window(observer);
+    *t_start = w.t_start;
+    *n_out = w.n_out;
+    if (capacity < w.n_out) fail(FR_E_ARG, "output capacity below the window length");
+    fwh_compute(h, observer, w, p, p_thickness, p_loading);
+  });
+}
+
+fr_status fr_fwh_pressure_at(fr_fwh *h, const double *observer, double t_start, int64_t n, double *p,
+                             double *p_thickness, double *p_loading) {
+  return guarded([&] {
+    if (!h || !observer || !p || n <= 0) fail(FR_E_ARG, "bad argument");
+    hip_check(hipSetDevice(h->device), "hipSetDevice");
+    Window w = h->window(observer);
+    const double tol = 1e-9 * w.dt;
+    if (t_start < w.t_start - tol || t_start + double(n - 1) * w.dt > w.t_end + tol)
+      fail(FR_E_ARG, "observer times outside the common window");
+    w.t_start = t_start;
+    w.n_out = n;
+    fwh_compute(h, observer, w, p, p_thickness, p_loading);
+  });
+}
+
+fr_status fr_fwh_time_ms(const fr_fwh *h, double *ms) {
+  return guarded([&] {
+    if (!h || !ms) fail(FR_E_ARG, "bad argument");
+    *ms = h->last_ms;
+  });
+}
+
+}  // extern "C"

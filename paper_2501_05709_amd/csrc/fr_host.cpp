@@ -1205,3 +1205,5 @@ void profile_steps(fr_mesh *m, int64_t steps, double *ms, int64_t *launches) {
   }
 }
 }  // namespace
+
+void fr::set_last_error(const char *msg) { g_err = msg ? msg : ""; }

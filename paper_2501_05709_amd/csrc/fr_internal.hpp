@@ -101,4 +101,7 @@ hipError_t launch_pack(const LaunchCfg &c, const DevArrays &a, bool to_device_la
 hipError_t launch_force_reduce(const LaunchCfg &c, const DevArrays &a);
 hipError_t launch_clear_flag(const LaunchCfg &c, const DevArrays &a);
 
+// Message returned by fr_last_error() for the calling thread (fr_host.cpp).
+void set_last_error(const char *msg);
+
 }  // namespace fr

@@ -299,3 +299,93 @@ class FRPool:
         u = np.zeros(2, dtype=np.int64)
         check(_lib.load().fr_pool_usage(self.h, u.ctypes.data_as(_lib._i64p)), "fr_pool_usage")
         return int(u[0]), int(u[1])
+
+
+class FWH:
+    """Far-field acoustic pressure from a permeable data surface (FW-H, advanced time)."""
+
+    def __init__(self, points, normals, areas, mach, c0, rho0, p0, dt, capacity, n_copies=1,
+                 copy_shift=(0.0, 0.0, 0.0), tau0=0.0, device=0, use_torch_allocator=True, stream=None):
+        L = _lib.load()
+        self.stream_obj = stream if stream is not None else _new_stream(device)
+        self.allocator = _TorchAllocator(device) if use_torch_allocator else None
+        self._keep = [np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3),
+                      np.ascontiguousarray(normals, dtype=np.float64).reshape(-1, 3),
+                      np.ascontiguousarray(areas, dtype=np.float64).reshape(-1)]
+        d = _lib.FwhDesc()
+        d.n_points = self._keep[0].shape[0]
+        d.points, d.normals, d.areas = (a.ctypes.data_as(_lib._dp) for a in self._keep)
+        d.n_copies = int(n_copies)
+        for i in range(3):
+            d.copy_shift[i] = float(copy_shift[i])
+            d.mach[i] = float(mach[i])
+        d.c0, d.rho0, d.p0, d.dt, d.tau0 = float(c0), float(rho0), float(p0), float(dt), float(tau0)
+        d.capacity = int(capacity)
+        d.device = device
+        d.stream = ctypes.c_void_p(self.stream_obj.cuda_stream)
+        if self.allocator is not None:
+            d.alloc, d.free = self.allocator.alloc, self.allocator.free
+        h = ctypes.c_void_p()
+        check(L.fr_fwh_create(ctypes.byref(d), ctypes.byref(h)), "fr_fwh_create")
+        self.h = h
+        self.n_points = int(d.n_points)
+        self._dt = float(dt)
+        _LIVE.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.load().fr_fwh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def append(self, rho, u, p):
+        """Append snapshots: rho [n, np], u [n, np, 3] (disturbance velocity), p [n, np]."""
+        rho = np.asarray(rho, dtype=np.float64)
+        if rho.ndim == 1:
+            rho, u, p = rho[None], np.asarray(u)[None], np.asarray(p)[None]
+        x = np.ascontiguousarray(np.concatenate([rho[..., None], np.asarray(u, dtype=np.float64),
+                                                 np.asarray(p, dtype=np.float64)[..., None]], axis=-1))
+        check(_lib.load().fr_fwh_append(self.h, x.shape[0], x.ctypes.data_as(_lib._dp)), "fr_fwh_append")
+
+    def samples(self):
+        n = ctypes.c_int64()
+        check(_lib.load().fr_fwh_samples(self.h, ctypes.byref(n)), "fr_fwh_samples")
+        return n.value
+
+    def window(self, observer):
+        x = np.ascontiguousarray(observer, dtype=np.float64)
+        t0, n = ctypes.c_double(), ctypes.c_int64()
+        check(_lib.load().fr_fwh_window(self.h, x.ctypes.data_as(_lib._dp), ctypes.byref(t0), ctypes.byref(n)),
+              "fr_fwh_window")
+        return t0.value, n.value
+
+    def pressure_at(self, observer, t_start, n, parts=False):
+        """p' at observer times t_start + m dt (m < n) inside the common window."""
+        x = np.ascontiguousarray(observer, dtype=np.float64)
+        p, pt, pl = np.zeros(n), np.zeros(n), np.zeros(n)
+        check(_lib.load().fr_fwh_pressure_at(self.h, x.ctypes.data_as(_lib._dp), float(t_start), int(n),
+                                             p.ctypes.data_as(_lib._dp), pt.ctypes.data_as(_lib._dp),
+                                             pl.ctypes.data_as(_lib._dp)), "fr_fwh_pressure_at")
+        return (p, pt, pl) if parts else p
+
+    def pressure(self, observer, parts=False):
+        """(t, p') at the observer, plus (p'_T, p'_L) when parts is set."""
+        x = np.ascontiguousarray(observer, dtype=np.float64)
+        _, n = self.window(x)
+        p, pt, pl = np.zeros(n), np.zeros(n), np.zeros(n)
+        t0, m = ctypes.c_double(), ctypes.c_int64()
+        check(_lib.load().fr_fwh_pressure(self.h, x.ctypes.data_as(_lib._dp), n, ctypes.byref(t0), ctypes.byref(m),
+                                          p.ctypes.data_as(_lib._dp), pt.ctypes.data_as(_lib._dp),
+                                          pl.ctypes.data_as(_lib._dp)), "fr_fwh_pressure")
+        t = t0.value + np.arange(m.value) * self._dt
+        return (t, p[:m.value], pt[:m.value], pl[:m.value]) if parts else (t, p[:m.value])
+
+    def time_ms(self):
+        v = ctypes.c_double()
+        check(_lib.load().fr_fwh_time_ms(self.h, ctypes.byref(v)), "fr_fwh_time_ms")
+        return v.value

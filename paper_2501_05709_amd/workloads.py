@@ -496,3 +496,58 @@ def acoustic_case(kind="monopole", mach=(0.0, 0.0, 0.5), periods=12, dt_over_T=0
     return dict(points=pts, normals=nrm, areas=area, rho=rho0 + rho_p, u=u, p=p0 + p_p, dt=dt,
                 mach=np.asarray(mach, dtype=np.float64), c0=c0, rho0=rho0, p0=p0, kind=kind, omega=omega,
                 amplitude=amplitude)
+
+
+def fwh_airfoil_case(seed=0, spacing=0.01, span=0.2, height=1.0, wake=4.0, n_samples=4332, dt=0.009233,
+                     lz=25.0, mach=0.2, aoa_deg=5.0, gamma=GAMMA):
+    """The airfoil data surface of the paper's Section 3.1, synthetic samples.
+
+    An open surface around a unit chord at the origin: two horizontal sheets at
+    y = +-height/2 from x = -height/2 to 1 + wake (four chords into the wake) joined by a
+    vertical sheet at x = -height/2, open downstream; panels of spacing x spacing, the
+    spanwise ones half a spacing inside the periodic planes; n_samples snapshots every dt
+    (free-stream convective times) and spanwise copies filling lz chords.  The samples are
+    the exact field of a stationary lift dipole at the trailing edge in the stream, with a
+    seeded frequency near two cycles per convective time (values only set the work, not
+    its amount).  Non-dimensional: chord, rho_inf and |U_inf| are 1.
+    """
+    rng = np.random.default_rng(seed)
+    h = height / 2.0
+    x0, x1 = -h, 1.0 + wake
+    nx = int(round((x1 - x0) / spacing))
+    ny = int(round(height / spacing))
+    nz = int(round(span / spacing))
+    xs = x0 + spacing * (np.arange(nx) + 0.5)
+    ys = -h + spacing * (np.arange(ny) + 0.5)
+    zs = spacing * (np.arange(nz) + 0.5)
+    pts, nrm = [], []
+    for z in zs:
+        pts += [(x, h, z) for x in xs]
+        nrm += [(0.0, 1.0, 0.0)] * nx
+        pts += [(x, -h, z) for x in xs]
+        nrm += [(0.0, -1.0, 0.0)] * nx
+        pts += [(x0, y, z) for y in ys]
+        nrm += [(-1.0, 0.0, 0.0)] * ny
+    pts = np.asarray(pts, dtype=np.float64)
+    nrm = np.asarray(nrm, dtype=np.float64)
+    a = np.deg2rad(aoa_deg)
+    M = mach * np.array([np.cos(a), np.sin(a), 0.0])
+    c0 = 1.0 / mach
+    p0 = 1.0 / (gamma * mach ** 2)
+    n_copies = int(round(lz / span))
+    if n_copies % 2 == 0:
+        n_copies += 1
+    return dict(points=pts, normals=nrm, areas=np.full(pts.shape[0], spacing * spacing), mach=M, c0=c0, rho0=1.0,
+                p0=p0, dt=dt, n_samples=n_samples, n_copies=n_copies, copy_shift=np.array([0.0, 0.0, span]),
+                observer=np.array([1.0, -10.0, span / 2.0]), source=np.array([1.0, 0.0, span / 2.0]),
+                omega=2.0 * np.pi * rng.uniform(1.8, 2.2), amplitude=1e-3)
+
+
+def fwh_airfoil_samples(case, chunk=256):
+    """Yield (rho, u, p) of consecutive snapshot chunks of fwh_airfoil_case."""
+    x = case["points"] - case["source"]
+    for k0 in range(0, case["n_samples"], chunk):
+        t = case["dt"] * np.arange(k0, min(k0 + chunk, case["n_samples"]))
+        rho_p, u, p_p = stationary_source("dipole", x, t, case["mach"], case["c0"], case["rho0"],
+                                          amplitude=case["amplitude"], omega=case["omega"])
+        yield case["rho0"] + rho_p, u, case["p0"] + p_p
