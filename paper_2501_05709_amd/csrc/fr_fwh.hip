@@ -32,9 +32,10 @@ namespace {
 
 constexpr int NQ = 4;          // Q, L1, L2, L3
 constexpr int SUM_WG = 256;    // threads of k_fwh_sum
-constexpr int SUM_OUT = 8;     // consecutive observer times per thread
-constexpr int SUM_PANELS = 32; // panels per chunk
-constexpr int SUM_PAIRS = 64;  // (copy, panel) pairs whose weights share the LDS
+constexpr int SUM_OUT = 4;     // consecutive observer times per thread
+constexpr int SUM_PANELS = 8;  // panels per chunk
+constexpr int SUM_PAIRS = 64;  // copies of one panel whose weights share the LDS
+constexpr int SUM_SPAN = SUM_WG * SUM_OUT + 7 + 256;  // staged samples per series (delay spread up to 256)
 
 struct Err {
   fr_status code;
@@ -157,105 +158,129 @@ struct Window {
 
 // Thickness and loading integrands of every copy and panel of one chunk at the observer
 // times of one time chunk, summed; partial sums per chunk: part[chunk][2][n_out].
-// The (copy, panel) pairs of the chunk go in batches of SUM_PAIRS: one thread per pair
-// forms the pair's stencil weights into LDS, then every thread applies them to its
-// SUM_OUT consecutive observer times.
+// Per panel of the chunk, its copies go in batches of SUM_PAIRS: one thread per copy
+// forms the copy's stencil weights into LDS; the workgroup stages the stretch of the
+// panel's four series that the batch's stencils touch over the time chunk (the copies'
+// delays shift it by up to the spread of the batch), and every thread applies each
+// copy's weights to its SUM_OUT consecutive observer times out of LDS.
 __global__ __launch_bounds__(SUM_WG) void k_fwh_sum(const double *__restrict__ src, const double *__restrict__ geo,
                                                     int64_t np, int64_t cap, int ncopy, Geo3 g, Stream s, Window w,
                                                     double *__restrict__ part) {
   __shared__ double Wt[SUM_PAIRS][NQ * 8];
   __shared__ int64_t Wb[SUM_PAIRS];
-  __shared__ int Wj[SUM_PAIRS];
+  __shared__ double Xs[NQ][SUM_SPAN];
+  __shared__ int64_t lo_s, hi_s;
   const int64_t chunk = blockIdx.y;
   const int tid = threadIdx.x;
-  const int64_t m0 = (int64_t(blockIdx.x) * SUM_WG + tid) * SUM_OUT;
+  const int64_t mt0 = int64_t(blockIdx.x) * SUM_WG * SUM_OUT;  // first observer time of the chunk
+  const int64_t m0 = mt0 + int64_t(tid) * SUM_OUT;
+  const int64_t mlast = (mt0 + SUM_WG * SUM_OUT < w.n_out ? mt0 + SUM_WG * SUM_OUT : w.n_out) - 1;
   const int64_t nv = w.nt - 4;  // samples with a time derivative
   double accT[SUM_OUT], accL[SUM_OUT];
 #pragma unroll
   for (int o = 0; o < SUM_OUT; ++o) accT[o] = accL[o] = 0.0;
   const int64_t j0 = chunk * SUM_PANELS, j1 = j0 + SUM_PANELS < np ? j0 + SUM_PANELS : np;
-  const int64_t npair = (j1 - j0) * ncopy;  // pair q: panel j0 + q / ncopy, copy q % ncopy
-  for (int64_t q0 = 0; q0 < npair; q0 += SUM_PAIRS) {
-    const int nb = int(npair - q0 < SUM_PAIRS ? npair - q0 : SUM_PAIRS);
-    if (tid < nb) {
-      const int64_t j = j0 + (q0 + tid) / ncopy;
-      const int c = int((q0 + tid) % ncopy);
-      double y[3];
-      panel_position(geo, j, c, ncopy, g.shift, y);
-      const Radii r = radii(g.xo, y, s);
-      const double area = geo[j * 7 + 6];
-      // geometric factors of the integrands (Appendix B), times the panel area
-      const double MR = s.mach[0] * r.gR[0] + s.mach[1] * r.gR[1] + s.mach[2] * r.gR[2];
-      const double MRs = s.mach[0] * r.gRs[0] + s.mach[1] * r.gRs[1] + s.mach[2] * r.gRs[2];
-      double a[NQ], b[NQ];
-      a[0] = area * (1.0 - MR) / r.Rs;            // x Qdot
-      b[0] = -area * s.c0 * MRs / (r.Rs * r.Rs);  // x Q
+  for (int64_t j = j0; j < j1; ++j) {
+    const double area = geo[j * 7 + 6];
+    for (int c0 = 0; c0 < ncopy; c0 += SUM_PAIRS) {
+      const int nb = ncopy - c0 < SUM_PAIRS ? ncopy - c0 : SUM_PAIRS;
+      if (tid < nb) {
+        double y[3];
+        panel_position(geo, j, c0 + tid, ncopy, g.shift, y);
+        const Radii r = radii(g.xo, y, s);
+        // geometric factors of the integrands (Appendix B), times the panel area
+        const double MR = s.mach[0] * r.gR[0] + s.mach[1] * r.gR[1] + s.mach[2] * r.gR[2];
+        const double MRs = s.mach[0] * r.gRs[0] + s.mach[1] * r.gRs[1] + s.mach[2] * r.gRs[2];
+        double a[NQ], b[NQ];
+        a[0] = area * (1.0 - MR) / r.Rs;            // x Qdot
+        b[0] = -area * s.c0 * MRs / (r.Rs * r.Rs);  // x Q
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        a[1 + i] = area * r.gR[i] / (s.c0 * r.Rs);   // x Ldot_i
-        b[1 + i] = area * r.gRs[i] / (r.Rs * r.Rs);  // x L_i
+        for (int i = 0; i < 3; ++i) {
+          a[1 + i] = area * r.gR[i] / (s.c0 * r.Rs);   // x Ldot_i
+          b[1 + i] = area * r.gRs[i] / (r.Rs * r.Rs);  // x L_i
+        }
+        // position of observer time 0 among the panel's derivative-bearing samples; the
+        // clamp keeps every stencil inside the record (it only absorbs rounding)
+        const double pos0 = (w.t_start - w.tau0 - r.R / s.c0) / w.dt - 2.0;
+        int64_t i0 = int64_t(floor(pos0));
+        const int64_t i0max = nv - 3 - (w.n_out - 1);
+        i0 = i0 > i0max ? i0max : i0;
+        i0 = i0 < 1 ? 1 : i0;
+        const double sf = pos0 - double(i0);
+        // cubic Lagrange weights (nodes -1..2) and their composition with the
+        // fourth-order derivative (1, -8, 0, 8, -1) / 12 dt: 8 taps from sample i0 - 1
+        const double l[4] = {-sf * (sf - 1.0) * (sf - 2.0) / 6.0, (sf + 1.0) * (sf - 1.0) * (sf - 2.0) / 2.0,
+                             -(sf + 1.0) * sf * (sf - 2.0) / 2.0, (sf + 1.0) * sf * (sf - 1.0) / 6.0};
+        double wv[8], wd[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) wv[d] = wd[d] = 0.0;
+        const double fd[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
+        const double idt = 1.0 / (12.0 * w.dt);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          wv[u + 2] += l[u];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) wd[u + v] += l[u] * fd[v] * idt;
+        }
+#pragma unroll
+        for (int x = 0; x < NQ; ++x)
+#pragma unroll
+          for (int d = 0; d < 8; ++d) Wt[tid][x * 8 + d] = a[x] * wd[d] + b[x] * wv[d];
+        Wb[tid] = i0 - 1;
       }
-      // position of observer time 0 among the panel's derivative-bearing samples; the
-      // clamp keeps every stencil inside the record (it only absorbs rounding)
-      const double pos0 = (w.t_start - w.tau0 - r.R / s.c0) / w.dt - 2.0;
-      int64_t i0 = int64_t(floor(pos0));
-      const int64_t i0max = nv - 3 - (w.n_out - 1);
-      i0 = i0 > i0max ? i0max : i0;
-      i0 = i0 < 1 ? 1 : i0;
-      const double sf = pos0 - double(i0);
-      // cubic Lagrange weights (nodes -1..2) and their composition with the
-      // fourth-order derivative (1, -8, 0, 8, -1) / 12 dt: 8 taps from sample i0 - 1
-      const double l[4] = {-sf * (sf - 1.0) * (sf - 2.0) / 6.0, (sf + 1.0) * (sf - 1.0) * (sf - 2.0) / 2.0,
-                           -(sf + 1.0) * sf * (sf - 2.0) / 2.0, (sf + 1.0) * sf * (sf - 1.0) / 6.0};
-      double wv[8], wd[8];
-#pragma unroll
-      for (int d = 0; d < 8; ++d) wv[d] = wd[d] = 0.0;
-      const double fd[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
-      const double idt = 1.0 / (12.0 * w.dt);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        wv[u + 2] += l[u];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) wd[u + v] += l[u] * fd[v] * idt;
+      __syncthreads();
+      // stretch of samples the batch touches over this time chunk
+      if (tid == 0) {
+        int64_t lo = Wb[0], hi = Wb[0];
+        for (int p = 1; p < nb; ++p) {
+          lo = Wb[p] < lo ? Wb[p] : lo;
+          hi = Wb[p] > hi ? Wb[p] : hi;
+        }
+        lo_s = lo + mt0;
+        hi_s = hi + mlast + 8;  // one past the last sample
       }
+      __syncthreads();
+      const int64_t lo = lo_s, span = hi_s - lo_s;
+      // copies whose stretch does not fit are applied straight from global memory
+      const bool staged = span <= SUM_SPAN;
+      if (staged) {
+        for (int64_t t = tid; t < NQ * span; t += SUM_WG) {
+          const int x = int(t / span);
+          const int64_t k = t % span;
+          Xs[x][k] = src[(x * np + j) * cap + lo + k];
+        }
+      }
+      __syncthreads();
+      if (m0 < w.n_out) {
+        const bool full = m0 + SUM_OUT <= w.n_out;
+        for (int p = 0; p < nb; ++p) {
+          const int64_t base = Wb[p] + m0;  // sample of tap 0 for observer time m0
 #pragma unroll
-      for (int x = 0; x < NQ; ++x)
+          for (int x = 0; x < NQ; ++x) {
+            double xs[SUM_OUT + 7];
+            const int nvalid = full ? SUM_OUT + 7 : int(w.n_out - m0) + 7;
+            if (staged) {
+              const double *X = &Xs[x][base - lo];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) Wt[tid][x * 8 + d] = a[x] * wd[d] + b[x] * wv[d];
-      Wb[tid] = i0 - 1;
-      Wj[tid] = int(j - j0);
-    }
-    __syncthreads();
-    if (m0 < w.n_out) {
-      const bool full = m0 + SUM_OUT <= w.n_out;
-      for (int p = 0; p < nb; ++p) {
-        const int64_t base = Wb[p] + m0;  // sample of tap 0 for observer time m0
-        const int64_t j = j0 + Wj[p];
+              for (int d = 0; d < SUM_OUT + 7; ++d) xs[d] = d < nvalid ? X[d] : 0.0;
+            } else {
+              const double *X = src + (x * np + j) * cap + base;
 #pragma unroll
-        for (int x = 0; x < NQ; ++x) {
-          const double *X = src + (x * np + j) * cap + base;
-          double xs[SUM_OUT + 7];
-          if (full) {
+              for (int d = 0; d < SUM_OUT + 7; ++d) xs[d] = d < nvalid ? X[d] : 0.0;
+            }
 #pragma unroll
-            for (int d = 0; d < SUM_OUT + 7; ++d) xs[d] = X[d];
-          } else {
-            // last chunk: only the samples of observer times inside the window
-            const int nvalid = int(w.n_out - m0) + 7;
+            for (int o = 0; o < SUM_OUT; ++o) {
+              double sv = 0.0;
 #pragma unroll
-            for (int d = 0; d < SUM_OUT + 7; ++d) xs[d] = d < nvalid ? X[d] : 0.0;
-          }
-#pragma unroll
-          for (int o = 0; o < SUM_OUT; ++o) {
-            double sv = 0.0;
-#pragma unroll
-            for (int d = 0; d < 8; ++d) sv += Wt[p][x * 8 + d] * xs[o + d];
-            if (x == 0) accT[o] += sv;
-            else accL[o] += sv;
+              for (int d = 0; d < 8; ++d) sv += Wt[p][x * 8 + d] * xs[o + d];
+              if (x == 0) accT[o] += sv;
+              else accL[o] += sv;
+            }
           }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int o = 0; o < SUM_OUT; ++o) {
