@@ -52,6 +52,7 @@ extern "C" {
 
 typedef struct fr_mesh fr_mesh;
 typedef struct fr_pool fr_pool;
+typedef struct fr_probe fr_probe;
 
 typedef enum {
   FR_OK = 0,
@@ -228,6 +229,32 @@ fr_status fr_pool_result(fr_pool *p, int64_t slot, double *out, double *u);
 /* used[0] = bytes held, used[1] = running requests. */
 fr_status fr_pool_usage(const fr_pool *p, int64_t *used);
 
+/* ---- Sampling the solution at points ---------------------------------
+ *
+ * The discrete FR solution inside an element is the tensor-product Lagrange
+ * interpolant through its Gauss-Legendre solution points.  A probe locates
+ * each point in the mesh (Newton's method on the element geometry map; the
+ * lowest-index element whose reference cube holds the point, among those
+ * whose node bounding box, padded by a tenth of its largest extent, holds
+ * it) and evaluates that interpolant of the current state: the flow samples
+ * on the permeable data surface of the paper's Section 3.1.
+ */
+
+/* Locate n points ([n][3]; dim 2 ignores z) in design `design` of mesh m,
+ * whose descriptor is desc (the one m was built from).  The probe refers to
+ * m, which must outlive it.  FR_E_ARG if a point lies in no element. */
+fr_status fr_probe_create(fr_mesh *m, const fr_mesh_desc *desc, int32_t design, int64_t n,
+                          const double *points, fr_probe **out);
+void fr_probe_destroy(fr_probe *p);
+
+/* Host copies of the located elements (canonical index within the design,
+ * [n]) and reference coordinates ([n][3]). */
+fr_status fr_probe_locate(const fr_probe *p, int64_t *elem, double *xi);
+
+/* The current state at the points: host [n][variables], conserved, FP64.
+ * FR_E_STATE if the mesh has no state. */
+fr_status fr_probe_sample(fr_probe *p, double *out);
+
 /* ---- Far-field acoustics: FW-H from a permeable data surface ----------
  *
  * The acoustic pressure at an observer from flow samples on a stationary
@@ -281,6 +308,12 @@ void fr_fwh_destroy(fr_fwh *h);
  * disturbance velocity; their source strengths are formed on the device.
  * FR_E_ARG when the record would exceed its capacity. */
 fr_status fr_fwh_append(fr_fwh *h, int64_t n, const double *samples);
+
+/* Append one snapshot sampled by probe p (its points are the record's
+ * panels, in order): the mesh state at the points, as rho, u - U, p with U
+ * the record's stream velocity c0 M, straight from the device.  FR_E_ARG if
+ * the probe's point count differs from the record's. */
+fr_status fr_fwh_append_probe(fr_fwh *h, fr_probe *p);
 
 /* Snapshots recorded so far. */
 fr_status fr_fwh_samples(const fr_fwh *h, int64_t *n);

@@ -83,9 +83,15 @@ SIGNATURES = {
     "fr_pool_collect": (ctypes.c_int, [ctypes.c_void_p, _i64p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "fr_pool_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp, _dp]),
     "fr_pool_usage": (ctypes.c_int, [ctypes.c_void_p, _i64p]),
+    "fr_probe_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MeshDesc), ctypes.c_int32, ctypes.c_int64, _dp,
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "fr_probe_destroy": (None, [ctypes.c_void_p]),
+    "fr_probe_locate": (ctypes.c_int, [ctypes.c_void_p, _i64p, _dp]),
+    "fr_probe_sample": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "fr_fwh_create": (ctypes.c_int, [ctypes.POINTER(FwhDesc), ctypes.POINTER(ctypes.c_void_p)]),
     "fr_fwh_destroy": (None, [ctypes.c_void_p]),
     "fr_fwh_append": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp]),
+    "fr_fwh_append_probe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fr_fwh_samples": (ctypes.c_int, [ctypes.c_void_p, _i64p]),
     "fr_fwh_window": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _i64p]),
     "fr_fwh_pressure": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int64, _dp, _i64p, _dp, _dp, _dp]),

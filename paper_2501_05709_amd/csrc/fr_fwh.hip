@@ -112,6 +112,24 @@ __global__ __launch_bounds__(256) void k_fwh_append(const double *__restrict__ s
   for (int i = 0; i < 3; ++i) src[(1 + i) * np * cap + col] = (p - s.p0) * n[i] + flux * x[1 + i];
 }
 
+// samples from sampled conserved variables [n][nv]: rho, u - U (disturbance velocity), p
+__global__ __launch_bounds__(256) void k_fwh_cons(const double *__restrict__ cons, int64_t n, int nv, int dim,
+                                                  double gamma, Stream s, double *__restrict__ stage) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double *c = cons + j * nv;
+  const double rho = c[0], ir = 1.0 / rho;
+  double u[3] = {0.0, 0.0, 0.0}, ke = 0.0;
+  for (int i = 0; i < dim; ++i) {
+    u[i] = c[1 + i] * ir;
+    ke += u[i] * u[i];
+  }
+  stage[j * 5 + 0] = rho;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) stage[j * 5 + 1 + i] = u[i] - s.U[i];
+  stage[j * 5 + 4] = (gamma - 1.0) * (c[dim + 1] - 0.5 * rho * ke);
+}
+
 __device__ inline double arrival_delay(const double *geo, int64_t cj, int64_t np, int ncopy, const double *shift,
                                        const double *xo, const Stream &s) {
   double y[3];
@@ -467,6 +485,26 @@ fr_status fr_fwh_append(fr_fwh *h, int64_t n, const double *samples) {
     hip_check(hipGetLastError(), "append kernel");
     hip_check(hipStreamSynchronize(h->stream), "append sync");
     h->nt += n;
+  });
+}
+
+fr_status fr_fwh_append_probe(fr_fwh *h, fr_probe *p) {
+  return guarded([&] {
+    if (!h || !p) fail(FR_E_ARG, "bad argument");
+    if (h->nt + 1 > h->cap) fail(FR_E_ARG, "record capacity exceeded");
+    const fr::ProbeRun r = fr::probe_run(p);  // complete on return
+    if (r.n != h->np) fail(FR_E_ARG, "probe and record have different point counts");
+    hip_check(hipSetDevice(h->device), "hipSetDevice");
+    h->grow(h->stage, h->stage_bytes, size_t(h->np) * 5 * sizeof(double));
+    const unsigned blocks = unsigned((h->np + 255) / 256);
+    hipLaunchKernelGGL(k_fwh_cons, dim3(blocks), dim3(256), 0, h->stream, r.out, h->np, r.nv, r.dim, r.gamma, h->s,
+                       h->stage);
+    hip_check(hipGetLastError(), "sample kernel");
+    hipLaunchKernelGGL(k_fwh_append, dim3(blocks), dim3(256), 0, h->stream, h->stage, h->geo, h->np, int64_t(1), h->nt,
+                       h->cap, h->s, h->src);
+    hip_check(hipGetLastError(), "append kernel");
+    hip_check(hipStreamSynchronize(h->stream), "append sync");
+    h->nt += 1;
   });
 }
 

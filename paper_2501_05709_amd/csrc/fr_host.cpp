@@ -1207,3 +1207,204 @@ void profile_steps(fr_mesh *m, int64_t steps, double *ms, int64_t *launches) {
 }  // namespace
 
 void fr::set_last_error(const char *msg) { g_err = msg ? msg : ""; }
+
+// ---------------------------------------------------------------------------
+// sampling the solution at points
+// ---------------------------------------------------------------------------
+struct fr_probe {
+  fr_mesh *m = nullptr;
+  int64_t n = 0;
+  std::vector<int64_t> elem;  // canonical element within the design
+  std::vector<double> xi;     // [n][3]
+  int64_t *slot = nullptr;    // device [n]: block * EB + element slot
+  double *w = nullptr;        // device [n][dim][order + 1]
+  double *out = nullptr;      // device [n][nv]
+  ~fr_probe() {
+    (void)hipFree(slot);
+    (void)hipFree(w);
+    (void)hipFree(out);
+  }
+};
+
+namespace {
+
+// x(r) = p by Newton's method from the element centre; true with r when the
+// iteration converges inside the reference cube (tolerance 1e-10)
+bool locate_in(const fr_mesh_desc &d, int64_t e, const double *p, std::array<double, 3> &r) {
+  const int dim = d.dim;
+  r = {0.0, 0.0, 0.0};
+  for (int it = 0; it < 50; ++it) {
+    double x[3], a[3][3];
+    geom_map(d, e, r, x, a);
+    double J[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}}, b[3] = {0, 0, 0};  // J[i][k] = dx_i / dr_k
+    for (int i = 0; i < dim; ++i) {
+      b[i] = p[i] - x[i];
+      for (int k = 0; k < dim; ++k) J[i][k] = a[k][i];
+    }
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (!(std::fabs(det) > 0.0)) return false;
+    double dr[3];
+    for (int k = 0; k < 3; ++k) {  // Cramer's rule
+      double M[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int c = 0; c < 3; ++c) M[i][c] = c == k ? b[i] : J[i][c];
+      dr[k] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+               M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) / det;
+    }
+    double step = 0.0, big = 0.0;
+    for (int k = 0; k < dim; ++k) {
+      r[k] += dr[k];
+      step = std::max(step, std::fabs(dr[k]));
+      big = std::max(big, std::fabs(r[k]));
+    }
+    if (step < 1e-14) {
+      for (int k = 0; k < dim; ++k)
+        if (std::fabs(r[k]) > 1.0 + 1e-10) return false;
+      return true;
+    }
+    if (big > 3.0) return false;
+  }
+  return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+fr_status fr_probe_create(fr_mesh *m, const fr_mesh_desc *desc, int32_t design, int64_t n, const double *points,
+                          fr_probe **out) {
+  return guarded([&] {
+    if (!out) fail(FR_E_ARG, "null output");
+    *out = nullptr;
+    if (!m || !desc || n <= 0 || !points || design < 0 || design >= int(m->designs.size()))
+      fail(FR_E_ARG, "bad argument");
+    validate_desc(desc);
+    const auto &ds = m->designs[design];
+    if (desc->n_elems != ds.E || desc->dim != m->dim || desc->order != m->order)
+      fail(FR_E_ARG, "descriptor does not match the mesh design");
+    const int dim = desc->dim, na = desc->geom_order + 1;
+    const int nn = dim == 2 ? na * na : na * na * na;
+    const int64_t E = desc->n_elems;
+    // padded node bounding boxes and a uniform grid of about E cells over them
+    std::vector<double> lo(size_t(E) * 3, 0.0), hi(size_t(E) * 3, 0.0);
+    double glo[3] = {INFINITY, INFINITY, INFINITY}, ghi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t e = 0; e < E; ++e) {
+      double l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
+      for (int a = 0; a < nn; ++a) {
+        const double *X = desc->nodes + desc->elem_nodes[e * nn + a] * dim;
+        for (int i = 0; i < dim; ++i) {
+          l[i] = std::min(l[i], X[i]);
+          h[i] = std::max(h[i], X[i]);
+        }
+      }
+      double ext = 0.0;
+      for (int i = 0; i < dim; ++i) ext = std::max(ext, h[i] - l[i]);
+      for (int i = 0; i < dim; ++i) {
+        lo[e * 3 + i] = l[i] - 0.1 * ext;
+        hi[e * 3 + i] = h[i] + 0.1 * ext;
+        glo[i] = std::min(glo[i], lo[e * 3 + i]);
+        ghi[i] = std::max(ghi[i], hi[e * 3 + i]);
+      }
+    }
+    const int cells = std::max(1, int(std::pow(double(E), 1.0 / dim)));
+    auto cell = [&](int i, double x) {
+      const int c = int((x - glo[i]) / (ghi[i] - glo[i]) * cells);
+      return std::min(std::max(c, 0), cells - 1);
+    };
+    const int64_t ncell = dim == 2 ? int64_t(cells) * cells : int64_t(cells) * cells * cells;
+    std::vector<std::vector<int64_t>> grid(static_cast<size_t>(ncell));
+    for (int64_t e = 0; e < E; ++e) {
+      int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
+      for (int i = 0; i < dim; ++i) {
+        c0[i] = cell(i, lo[e * 3 + i]);
+        c1[i] = cell(i, hi[e * 3 + i]);
+      }
+      for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+          for (int x = c0[0]; x <= c1[0]; ++x) grid[size_t(x + cells * (y + int64_t(cells) * z))].push_back(e);
+    }
+    auto *p = new fr_probe();
+    try {
+      p->m = m;
+      p->n = n;
+      p->elem.assign(size_t(n), -1);
+      p->xi.assign(size_t(n) * 3, 0.0);
+      std::vector<int> bad(size_t(n), 0);
+      parallel_for(n, [&](int64_t i) {
+        const double *x = points + i * 3;
+        int c[3] = {0, 0, 0};
+        for (int k = 0; k < dim; ++k) c[k] = cell(k, x[k]);
+        const auto &cand = grid[size_t(c[0] + cells * (c[1] + int64_t(cells) * c[2]))];  // ascending
+        for (int64_t e : cand) {
+          bool in = true;
+          for (int k = 0; k < dim; ++k) in = in && x[k] >= lo[e * 3 + k] && x[k] <= hi[e * 3 + k];
+          std::array<double, 3> r;
+          if (in && locate_in(*desc, e, x, r)) {
+            p->elem[size_t(i)] = e;
+            for (int k = 0; k < 3; ++k) p->xi[size_t(i) * 3 + k] = r[k];
+            return;
+          }
+        }
+        bad[size_t(i)] = 1;
+      });
+      for (int64_t i = 0; i < n; ++i)
+        if (bad[size_t(i)]) fail(FR_E_ARG, "point " + std::to_string(i) + " lies in no element");
+      const int N = m->order + 1;
+      Basis1D B(m->order);
+      std::vector<int64_t> slot(static_cast<size_t>(n));
+      std::vector<double> w(size_t(n) * dim * N);
+      for (int64_t i = 0; i < n; ++i) {
+        const int64_t le = p->elem[size_t(i)];
+        slot[size_t(i)] = (ds.blk0 + le / EB) * EB + le % EB;
+        for (int k = 0; k < dim; ++k) {
+          const auto l = B.eval_all(p->xi[size_t(i) * 3 + k]);
+          for (int j = 0; j < N; ++j) w[(size_t(i) * dim + k) * N + j] = l[j];
+        }
+      }
+      hip_check(hipSetDevice(m->device), "hipSetDevice");
+      hip_check(hipMalloc(&p->slot, slot.size() * sizeof(int64_t)), "probe alloc");
+      hip_check(hipMalloc(&p->w, w.size() * sizeof(double)), "probe alloc");
+      hip_check(hipMalloc(&p->out, size_t(n) * m->dm.nv * sizeof(double)), "probe alloc");
+      hip_check(hipMemcpyAsync(p->slot, slot.data(), slot.size() * sizeof(int64_t), hipMemcpyHostToDevice, m->stream),
+                "probe upload");
+      hip_check(hipMemcpyAsync(p->w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, m->stream),
+                "probe upload");
+      hip_check(hipStreamSynchronize(m->stream), "probe sync");
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = p;
+  });
+}
+
+void fr_probe_destroy(fr_probe *p) { delete p; }
+
+fr_status fr_probe_locate(const fr_probe *p, int64_t *elem, double *xi) {
+  return guarded([&] {
+    if (!p || !elem || !xi) fail(FR_E_ARG, "null argument");
+    std::memcpy(elem, p->elem.data(), p->elem.size() * sizeof(int64_t));
+    std::memcpy(xi, p->xi.data(), p->xi.size() * sizeof(double));
+  });
+}
+
+fr_status fr_probe_sample(fr_probe *p, double *out) {
+  return guarded([&] {
+    if (!p || !out) fail(FR_E_ARG, "null argument");
+    const fr::ProbeRun r = fr::probe_run(p);
+    hip_check(hipMemcpy(out, r.out, size_t(r.n) * r.nv * sizeof(double), hipMemcpyDeviceToHost), "probe copy");
+  });
+}
+
+}  // extern "C"
+
+fr::ProbeRun fr::probe_run(::fr_probe *p) {
+  fr_mesh *m = p->m;
+  if (!m->state_set) fail(FR_E_STATE, "no state set");
+  hip_check(hipSetDevice(m->device), "hipSetDevice");
+  hip_check(launch_probe(m->cfg, m->a, p->n, p->slot, p->w, p->out), "probe kernel");
+  hip_check(hipStreamSynchronize(m->stream), "probe sync");
+  return ProbeRun{p->out, p->n, m->dm.nv, m->dim, m->gamma};
+}

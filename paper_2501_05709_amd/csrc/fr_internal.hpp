@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+struct fr_probe;
+
 namespace fr {
 
 constexpr int EB = 16;  // elements per block: the N extent of one MFMA tile
@@ -100,8 +102,20 @@ hipError_t launch_kernel(int kernel, const LaunchCfg &c, const DevArrays &a, int
 hipError_t launch_pack(const LaunchCfg &c, const DevArrays &a, bool to_device_layout, void *dst_res);
 hipError_t launch_force_reduce(const LaunchCfg &c, const DevArrays &a);
 hipError_t launch_clear_flag(const LaunchCfg &c, const DevArrays &a);
+hipError_t launch_probe(const LaunchCfg &c, const DevArrays &a, int64_t n, const int64_t *slot, const double *w,
+                        double *out);
 
 // Message returned by fr_last_error() for the calling thread (fr_host.cpp).
 void set_last_error(const char *msg);
+
+// Sample the state of a probe's mesh at its points: device output [n][nv] (FP64
+// conserved variables), complete on return; also the mesh's dim and gamma.
+struct ProbeRun {
+  const double *out;
+  int64_t n;
+  int nv, dim;
+  double gamma;
+};
+ProbeRun probe_run(::fr_probe *p);
 
 }  // namespace fr

@@ -1424,6 +1424,45 @@ __global__ void k_clear_flag(int *flag) {
 }
 
 // ---------------------------------------------------------------------------
+// sampling: the FR interpolant of the stage-0 state at points (one thread each)
+// ---------------------------------------------------------------------------
+// slot[p] = block * EB + element slot; w[p][DIM][N] are the 1D Lagrange weights of the
+// Gauss-Legendre solution points at the point's reference coordinates
+template <typename T, int DIM, int ORDER>
+__global__ __launch_bounds__(256) void k_probe(KArgs<T> a, int64_t n, const int64_t *__restrict__ slot,
+                                               const double *__restrict__ w, double *__restrict__ out) {
+  using S = Shape<DIM, ORDER>;
+  constexpr int N = S::N, NV = S::NV;
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t blk = slot[p] / EB;
+  const int e = int(slot[p] % EB);
+  const double *wp = w + p * DIM * N;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int c2 = 0; c2 < (DIM == 3 ? N : 1); ++c2)
+    for (int c1 = 0; c1 < N; ++c1)
+      for (int c0 = 0; c0 < N; ++c0) {
+        const double wt = wp[c0] * wp[N + c1] * (DIM == 3 ? wp[2 * N + c2] : 1.0);
+        const int i = c0 + N * c1 + N * N * c2;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += wt * double(a.U[at(blk, i, v, e, S::NUP, NV)]);
+      }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[p * NV + v] = acc[v];
+}
+
+template <typename T, int DIM, int ORDER>
+static hipError_t probe_t(const LaunchCfg &c, const DevArrays &d, int64_t n, const int64_t *slot, const double *w,
+                          double *out) {
+  KArgs<T> a = make_args<T>(c, d);
+  hipLaunchKernelGGL((k_probe<T, DIM, ORDER>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, c.stream, a, n, slot,
+                     w, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 
@@ -1549,6 +1588,11 @@ hipError_t launch_kernel(int kernel, const LaunchCfg &c, const DevArrays &a, int
 
 hipError_t launch_pack(const LaunchCfg &c, const DevArrays &a, bool to_dev, void *dst) {
   FR_DISPATCH(pack_t, c, a, to_dev, dst);
+}
+
+hipError_t launch_probe(const LaunchCfg &c, const DevArrays &a, int64_t n, const int64_t *slot, const double *w,
+                        double *out) {
+  FR_DISPATCH(probe_t, c, a, n, slot, w, out);
 }
 
 hipError_t launch_force_reduce(const LaunchCfg &c, const DevArrays &a) {

@@ -352,6 +352,10 @@ class FWH:
                                                  np.asarray(p, dtype=np.float64)[..., None]], axis=-1))
         check(_lib.load().fr_fwh_append(self.h, x.shape[0], x.ctypes.data_as(_lib._dp)), "fr_fwh_append")
 
+    def append_probe(self, probe):
+        """Append one snapshot of the probe's mesh state at the probe's points."""
+        check(_lib.load().fr_fwh_append_probe(self.h, probe.h), "fr_fwh_append_probe")
+
     def samples(self):
         n = ctypes.c_int64()
         check(_lib.load().fr_fwh_samples(self.h, ctypes.byref(n)), "fr_fwh_samples")
@@ -389,3 +393,41 @@ class FWH:
         v = ctypes.c_double()
         check(_lib.load().fr_fwh_time_ms(self.h, ctypes.byref(v)), "fr_fwh_time_ms")
         return v.value
+
+
+class Probe:
+    """Samples of the FR solution of `mesh` (an FRMesh) at points [n, 3]."""
+
+    def __init__(self, mesh, points, design=0):
+        self.mesh = mesh  # the probe refers to the mesh: keep it alive
+        pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+        self.n = pts.shape[0]
+        d, self._keep = _desc(mesh.meshes[design], "fp64")
+        h = ctypes.c_void_p()
+        check(_lib.load().fr_probe_create(mesh.h, ctypes.byref(d), design, self.n, pts.ctypes.data_as(_lib._dp),
+                                          ctypes.byref(h)), "fr_probe_create")
+        self.h = h
+        _LIVE.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.load().fr_probe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def locate(self):
+        elem = np.zeros(self.n, dtype=np.int64)
+        xi = np.zeros((self.n, 3))
+        check(_lib.load().fr_probe_locate(self.h, elem.ctypes.data_as(_lib._i64p), xi.ctypes.data_as(_lib._dp)),
+              "fr_probe_locate")
+        return elem, xi
+
+    def sample(self):
+        out = np.zeros((self.n, self.mesh.nv))
+        check(_lib.load().fr_probe_sample(self.h, out.ctypes.data_as(_lib._dp)), "fr_probe_sample")
+        return out

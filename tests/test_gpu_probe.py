@@ -1,0 +1,118 @@
+"""GPU parity of sampling the FR solution at points (fr_probe_*) and of the LES -> FW-H
+pipeline (fr_fwh_append_probe) against the oracles.
+
+Bars: located elements bit-identical to the oracle's (a unique answer: the lowest-index
+element holding the point), reference coordinates to 1e-12; FP64 samples to 1e-12 of
+the largest magnitude; FP32-form samples to 1e-6 (FP32 state).  Pipeline: the acoustic
+pressure from a sampled FP64 run to 1e-10 of its largest magnitude (the RK state
+agrees to 1e-12 and the acoustic sum adds O(1) cancellation).
+"""
+import numpy as np
+import pytest
+
+from oracle import fwh, probe
+from oracle.oracle import OracleMesh
+from paper_2501_05709_amd import _lib
+from paper_2501_05709_amd import workloads as W
+from paper_2501_05709_amd.solver import FRMesh, FWH, Probe
+
+pytestmark = pytest.mark.gpu
+
+
+def perturbed(o, mesh, amp=0.1):
+    x = o.solution_points()
+    if "init" in mesh:
+        u = o.initial_state()
+    else:
+        fs = mesh["freestream"]
+        u = W.uniform_state(o.E * o.nu, fs[0], fs[1:1 + o.dim], fs[4]).reshape(o.shape)
+    s = np.sin(0.9 * x[..., 0] + 0.3) * np.cos(1.3 * x[..., 1] - 0.2) * np.cos(0.7 * x[..., 2] + 0.1)
+    u = u.copy()
+    u[..., 0] *= 1.0 + amp * s
+    u[..., -1] *= 1.0 + amp * s
+    return u
+
+
+def case(name):
+    rng = np.random.default_rng(3)
+    if name == "airfoil":
+        m = W.config_airfoil(2, ni=24, nj=6, nk=2)
+        r = rng.uniform(0.7, 3.0, 60)
+        th = rng.uniform(0, 2 * np.pi, 60)
+        pts = np.stack([0.5 + r * np.cos(th), r * np.sin(th), rng.uniform(0.01, 0.19, 60)], axis=1)
+    else:
+        m = W.box_mesh(2, (5, 4), (0, 0), (1, 1), q=2, warp=0.05, order=3)
+        m.update(gamma=1.4, prandtl=0.72, mu=0.01, freestream=np.array([1.0, 0.2, 0.1, 0.0, 1.0]), dt=1e-3)
+        pts = np.concatenate([rng.uniform(0.02, 0.98, (50, 2)), np.zeros((50, 1))], axis=1)
+    return m, pts
+
+
+@pytest.mark.parametrize("name", ["airfoil", "box2d_curved"])
+def test_probe_matches_oracle(name):
+    m, pts = case(name)
+    o = OracleMesh(m)
+    u = perturbed(o, m)
+    e_ref, xi_ref = probe.locate(m, pts)
+    ref = probe.sample(u, m["order"], e_ref, xi_ref, m["dim"])
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        g = FRMesh(m, prec)
+        g.set_state(u)
+        pr = Probe(g, pts)
+        e, xi = pr.locate()
+        assert np.array_equal(e, e_ref)
+        assert np.abs(xi - xi_ref).max() <= 1e-12
+        got = pr.sample()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"{name} {prec}: sample max rel err {err:.2e}", flush=True)
+        assert err <= tol
+        pr.close()
+        g.close()
+
+
+def test_point_outside_is_rejected():
+    m, pts = case("box2d_curved")
+    g = FRMesh(m, "fp64")
+    with pytest.raises(_lib.FRError) as e:
+        Probe(g, np.array([[2.0, 0.5, 0.0]]))
+    assert e.value.code == _lib.FR_E_ARG
+
+
+def test_sampled_run_to_far_field_matches_oracle():
+    """Taylor-Green 4^3 p3, FP64: a sphere of 8 x 12 panels (radius 0.3) sampled every
+    step for 120 steps, far-field pressure at 2 from its centre (no stream)."""
+    m = W.config_tgv(nel=4, order=3)
+    o = OracleMesh(m)
+    u0 = o.initial_state()
+    centre = np.array([np.pi, np.pi, np.pi])
+    sp, sn, sa = W.sphere_surface(0.3, 8, 12)
+    sp = sp + centre
+    gam, mach = 1.4, 0.1
+    c0, rho0, p0 = 1.0 / mach, 1.0, 1.0 / (gam * mach ** 2)
+    nsteps = 120
+    # device pipeline
+    g = FRMesh(m, "fp64")
+    g.set_state(u0)
+    pr = Probe(g, sp)
+    f = FWH(sp, sn, sa, (0.0, 0.0, 0.0), c0, rho0, p0, m["dt"], nsteps + 1)
+    f.append_probe(pr)
+    for _ in range(nsteps):
+        g.step(1)
+        f.append_probe(pr)
+    xo = centre + np.array([2.0, 0.3, -0.4])
+    t, p = f.pressure(xo)
+    # oracle pipeline
+    e, xi = probe.locate(m, sp)
+    u = u0
+    snaps = [probe.sample(u, 3, e, xi, 3)]
+    for _ in range(nsteps):
+        u = o.rk4(u, m["dt"], 1)
+        snaps.append(probe.sample(u, 3, e, xi, 3))
+    c = np.array(snaps)
+    rho = c[..., 0]
+    vel = c[..., 1:4] / rho[..., None]
+    pres = (gam - 1.0) * (c[..., 4] - 0.5 * rho * (vel ** 2).sum(-1))
+    to, po, _, _ = fwh.observer_pressure(sp, sn, sa, rho, vel, pres, m["dt"], xo, (0.0, 0.0, 0.0), c0, rho0, p0)
+    assert t.size == to.size and t.size > 20
+    err = np.abs(p - po).max() / np.abs(po).max()
+    print(f"sampled run -> far field: {t.size} observer times, max rel err {err:.2e}", flush=True)
+    assert err <= 1e-10
