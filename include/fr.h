@@ -338,6 +338,49 @@ fr_status fr_fwh_pressure_at(fr_fwh *h, const double *observer, double t_start, 
  * events on its stream around the summation kernels). */
 fr_status fr_fwh_time_ms(const fr_fwh *h, double *ms);
 
+/* ---- Served requests with a data surface -------------------------------
+ *
+ * One candidate design of the optimisation loop (Algorithm 1): its flow is
+ * advanced, sampled on a permeable data surface and propagated to the far
+ * field by the FW-H solver above, while other candidates run beside it in
+ * the same pool.  After `warmup` steps the state is sampled at the surface
+ * points (as fr_probe_sample, design 0) every `every` steps, n_samples
+ * times, the first sample at source time 0, and each snapshot is appended to
+ * an FW-H record (as fr_fwh_append_probe) without a host round trip.  The
+ * record's medium is the request's free stream (desc->freestream = rho, u,
+ * v, w, p): c0 = sqrt(gamma p / rho), Mach vector (u, v, w) / c0, rho0 =
+ * rho, p0 = p; its sampling interval is every * desc->dt.  The running lift
+ * and drag means restart at the first sample, so the request's result
+ * (fr_pool_result) holds the means over the sampled period: the mean
+ * coefficients of the objective of Section 3.4.
+ */
+typedef struct {
+  int64_t n_points;        /* panels of one copy of the data surface */
+  const double *points;    /* [n_points][3] panel centres (copied) */
+  const double *normals;   /* [n_points][3] outward unit normals (copied) */
+  const double *areas;     /* [n_points] panel areas (copied) */
+  int32_t n_copies;        /* spanwise copies, as fr_fwh_desc */
+  double copy_shift[3];
+  int64_t warmup;          /* steps before the first sample, >= 0 */
+  int64_t every;           /* steps between samples, >= 1 */
+  int64_t n_samples;       /* snapshots, >= 8 */
+} fr_pool_surface;
+
+/* Admit a request that runs warmup + (n_samples - 1) * every steps from u0
+ * (as fr_pool_admit) and samples the surface s.  Its footprint includes the
+ * probe and the record.  FR_E_NOMEM if it does not fit now (nothing is
+ * allocated then); FR_E_ARG for an invalid surface or a point that lies in
+ * no element. */
+fr_status fr_pool_admit_sampled(fr_pool *p, const fr_mesh_desc *desc, const double *u0,
+                                const fr_pool_surface *s, int64_t *slot);
+
+/* Acoustic pressure at observer[3] of a finished sampled request, with the
+ * arguments and results of fr_fwh_pressure (no thickness and loading
+ * parts).  Call it before fr_pool_result, which frees the request.
+ * FR_E_STATE if the request has not finished, failed, or has no surface. */
+fr_status fr_pool_pressure(fr_pool *p, int64_t slot, const double *observer, int64_t capacity,
+                           double *t_start, int64_t *n_out, double *pressure);
+
 const char *fr_last_error(void);
 
 #ifdef __cplusplus

@@ -51,6 +51,14 @@ class FwhDesc(ctypes.Structure):
     ]
 
 
+class PoolSurface(ctypes.Structure):
+    _fields_ = [
+        ("n_points", ctypes.c_int64), ("points", _dp), ("normals", _dp), ("areas", _dp),
+        ("n_copies", ctypes.c_int32), ("copy_shift", ctypes.c_double * 3),
+        ("warmup", ctypes.c_int64), ("every", ctypes.c_int64), ("n_samples", ctypes.c_int64),
+    ]
+
+
 # every function declared in include/fr.h: name -> (restype, argtypes)
 SIGNATURES = {
     "fr_mesh_create": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(ctypes.c_void_p)]),
@@ -83,6 +91,9 @@ SIGNATURES = {
     "fr_pool_collect": (ctypes.c_int, [ctypes.c_void_p, _i64p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "fr_pool_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp, _dp]),
     "fr_pool_usage": (ctypes.c_int, [ctypes.c_void_p, _i64p]),
+    "fr_pool_admit_sampled": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MeshDesc), _dp,
+                                             ctypes.POINTER(PoolSurface), _i64p]),
+    "fr_pool_pressure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _i64p, _dp]),
     "fr_probe_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MeshDesc), ctypes.c_int32, ctypes.c_int64, _dp,
                                        ctypes.POINTER(ctypes.c_void_p)]),
     "fr_probe_destroy": (None, [ctypes.c_void_p]),

@@ -378,6 +378,20 @@ struct fr_fwh {
     }
     return p;
   }
+  // enqueue the source strengths of one probed snapshot (device [np][nv] conserved
+  // variables) at the end of the record, on the record's stream
+  void append_sample(const fr::ProbeRun &r) {
+    if (r.n != np) fail(FR_E_ARG, "probe and record have different point counts");
+    if (nt + 1 > cap) fail(FR_E_ARG, "record capacity exceeded");
+    hip_check(hipSetDevice(device), "hipSetDevice");
+    grow(stage, stage_bytes, size_t(np) * 5 * sizeof(double));
+    const unsigned blocks = unsigned((np + 255) / 256);
+    hipLaunchKernelGGL(k_fwh_cons, dim3(blocks), dim3(256), 0, stream, r.out, np, r.nv, r.dim, r.gamma, s, stage);
+    hip_check(hipGetLastError(), "sample kernel");
+    hipLaunchKernelGGL(k_fwh_append, dim3(blocks), dim3(256), 0, stream, stage, geo, np, int64_t(1), nt, cap, s, src);
+    hip_check(hipGetLastError(), "append kernel");
+    nt += 1;
+  }
   // observer-time window of the common record (the oracle's rule, same arithmetic)
   Window window(const double *xo) {
     if (nt < 8) fail(FR_E_STATE, "fewer than 8 samples recorded");
@@ -491,20 +505,11 @@ fr_status fr_fwh_append(fr_fwh *h, int64_t n, const double *samples) {
 fr_status fr_fwh_append_probe(fr_fwh *h, fr_probe *p) {
   return guarded([&] {
     if (!h || !p) fail(FR_E_ARG, "bad argument");
-    if (h->nt + 1 > h->cap) fail(FR_E_ARG, "record capacity exceeded");
-    const fr::ProbeRun r = fr::probe_run(p);  // complete on return
-    if (r.n != h->np) fail(FR_E_ARG, "probe and record have different point counts");
-    hip_check(hipSetDevice(h->device), "hipSetDevice");
-    h->grow(h->stage, h->stage_bytes, size_t(h->np) * 5 * sizeof(double));
-    const unsigned blocks = unsigned((h->np + 255) / 256);
-    hipLaunchKernelGGL(k_fwh_cons, dim3(blocks), dim3(256), 0, h->stream, r.out, h->np, r.nv, r.dim, r.gamma, h->s,
-                       h->stage);
-    hip_check(hipGetLastError(), "sample kernel");
-    hipLaunchKernelGGL(k_fwh_append, dim3(blocks), dim3(256), 0, h->stream, h->stage, h->geo, h->np, int64_t(1), h->nt,
-                       h->cap, h->s, h->src);
-    hip_check(hipGetLastError(), "append kernel");
+    fr::ProbeRun r{};
+    const fr_status st = fr::probe_run(p, true, &r);  // complete on return
+    if (st != FR_OK) fail(st, fr_last_error());
+    h->append_sample(r);
     hip_check(hipStreamSynchronize(h->stream), "append sync");
-    h->nt += 1;
   });
 }
 
@@ -601,3 +606,22 @@ fr_status fr_fwh_time_ms(const fr_fwh *h, double *ms) {
 }
 
 }  // extern "C"
+
+fr_status fr::fwh_append_probe_async(::fr_fwh *h, ::fr_probe *p) {
+  return guarded([&] {
+    if (!h || !p) fail(FR_E_ARG, "bad argument");
+    fr::ProbeRun r{};
+    const fr_status st = fr::probe_run(p, false, &r);
+    if (st != FR_OK) fail(st, fr_last_error());
+    if (r.stream != h->stream) fail(FR_E_ARG, "record and probe mesh run on different streams");
+    h->append_sample(r);
+  });
+}
+
+size_t fr::fwh_footprint(int64_t n_points, int64_t capacity) {
+  const size_t np = size_t(n_points), cap = size_t(capacity);
+  const size_t nchunk = (np + SUM_PANELS - 1) / SUM_PANELS;
+  // geometry, source series, one staged snapshot, delay extremes, and at most a
+  // window of capacity observer times of partial sums and outputs
+  return (np * 7 + size_t(NQ) * np * cap + np * 5 + 2 * 64 + nchunk * 2 * cap + 3 * cap) * sizeof(double);
+}

@@ -893,14 +893,14 @@ hipGraphExec_t capture_step(fr_mesh *M, bool forces) {
   return ex;
 }
 
-void step_async(fr_mesh *M, int64_t n) {
+void step_async(fr_mesh *M, int64_t n, bool clear_flag = true) {
   if (!M->state_set) fail(FR_E_STATE, "no state set");
   if (n < 0) fail(FR_E_ARG, "negative step count");
   if (n == 0) return;
   hip_check(hipSetDevice(M->device), "hipSetDevice");
   if (!M->graph_first) M->graph_first = capture_step(M, false);
   if (!M->graph_rest) M->graph_rest = capture_step(M, true);
-  hip_check(launch_clear_flag(M->cfg, M->a), "clear flag");
+  if (clear_flag) hip_check(launch_clear_flag(M->cfg, M->a), "clear flag");
   lk(M, K_INTERP, 0, 0, false);
   for (int64_t s = 0; s < n; ++s)
     hip_check(hipGraphLaunch(s == 0 ? M->graph_first : M->graph_rest, M->stream), "graph launch");
@@ -1393,18 +1393,43 @@ fr_status fr_probe_locate(const fr_probe *p, int64_t *elem, double *xi) {
 fr_status fr_probe_sample(fr_probe *p, double *out) {
   return guarded([&] {
     if (!p || !out) fail(FR_E_ARG, "null argument");
-    const fr::ProbeRun r = fr::probe_run(p);
+    fr::ProbeRun r{};
+    const fr_status st = fr::probe_run(p, true, &r);
+    if (st != FR_OK) fail(st, g_err);
     hip_check(hipMemcpy(out, r.out, size_t(r.n) * r.nv * sizeof(double), hipMemcpyDeviceToHost), "probe copy");
   });
 }
 
 }  // extern "C"
 
-fr::ProbeRun fr::probe_run(::fr_probe *p) {
-  fr_mesh *m = p->m;
-  if (!m->state_set) fail(FR_E_STATE, "no state set");
-  hip_check(hipSetDevice(m->device), "hipSetDevice");
-  hip_check(launch_probe(m->cfg, m->a, p->n, p->slot, p->w, p->out), "probe kernel");
-  hip_check(hipStreamSynchronize(m->stream), "probe sync");
-  return ProbeRun{p->out, p->n, m->dm.nv, m->dim, m->gamma};
+fr_status fr::probe_run(::fr_probe *p, bool wait, ProbeRun *out) {
+  return guarded([&] {
+    if (!p || !out) fail(FR_E_ARG, "null argument");
+    fr_mesh *m = p->m;
+    if (!m->state_set) fail(FR_E_STATE, "no state set");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    hip_check(launch_probe(m->cfg, m->a, p->n, p->slot, p->w, p->out), "probe kernel");
+    if (wait) hip_check(hipStreamSynchronize(m->stream), "probe sync");
+    *out = ProbeRun{p->out, p->n, m->dm.nv, m->dim, m->gamma, m->stream};
+  });
+}
+
+fr_status fr::step_enqueue(::fr_mesh *m, int64_t n, bool clear_flag) {
+  return guarded([&] {
+    if (!m) fail(FR_E_ARG, "null mesh");
+    step_async(m, n, clear_flag);
+  });
+}
+
+fr_status fr::means_clear(::fr_mesh *m) {
+  return guarded([&] {
+    if (!m) fail(FR_E_ARG, "null mesh");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    hip_check(hipMemsetAsync(m->a.fsum, 0, m->designs.size() * 8 * sizeof(double), m->stream), "clear sums");
+  });
+}
+
+size_t fr::probe_footprint(int64_t n, int dim, int order) {
+  // slot, interpolation weights and output buffer of fr_probe_create
+  return size_t(n) * (sizeof(int64_t) + size_t(dim) * (order + 1) * sizeof(double) + (dim + 2) * sizeof(double));
 }

@@ -6,7 +6,11 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "../../include/fr.h"
+
 struct fr_probe;
+struct fr_mesh;
+struct fr_fwh;
 
 namespace fr {
 
@@ -108,14 +112,33 @@ hipError_t launch_probe(const LaunchCfg &c, const DevArrays &a, int64_t n, const
 // Message returned by fr_last_error() for the calling thread (fr_host.cpp).
 void set_last_error(const char *msg);
 
-// Sample the state of a probe's mesh at its points: device output [n][nv] (FP64
-// conserved variables), complete on return; also the mesh's dim and gamma.
+// Sample the state of a probe's mesh at its points into a device buffer [n][nv] (FP64
+// conserved variables) on the mesh's stream; complete on return when wait is set.  Also
+// reports the mesh's dim and gamma.  Errors come back as a status with the message set
+// for fr_last_error(), never as an exception (fr_host.cpp).
 struct ProbeRun {
   const double *out;
   int64_t n;
   int nv, dim;
   double gamma;
+  hipStream_t stream;
 };
-ProbeRun probe_run(::fr_probe *p);
+fr_status probe_run(::fr_probe *p, bool wait, ProbeRun *out);
+
+// Enqueue n RK4 steps of m on its stream without waiting.  clear_flag false keeps the
+// non-finite flag raised by steps enqueued before, so one later fr_sync covers them all.
+fr_status step_enqueue(::fr_mesh *m, int64_t n, bool clear_flag);
+
+// Enqueue the reset of the running lift and drag means of every design of m.
+fr_status means_clear(::fr_mesh *m);
+
+// Enqueue one snapshot of probe p and its append to record h (fr_fwh.hip), without
+// waiting.  The record must run on the probe mesh's stream.
+fr_status fwh_append_probe_async(::fr_fwh *h, ::fr_probe *p);
+
+// Upper bounds of the device bytes held by a probe of n points and by an FW-H record
+// of n_points panels and capacity samples, including what its pressure calls grow.
+size_t probe_footprint(int64_t n, int dim, int order);
+size_t fwh_footprint(int64_t n_points, int64_t capacity);
 
 }  // namespace fr

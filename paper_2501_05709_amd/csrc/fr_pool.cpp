@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -37,6 +38,19 @@ struct fr_pool {
     size_t bytes = 0;
     bool done = false, in_flight = false;
     fr_status status = FR_OK;
+    // data surface (sampled requests): snapshot j is taken after warmup + j * every steps
+    fr_probe *probe = nullptr;
+    fr_fwh *rec = nullptr;
+    int64_t warmup = 0, every = 1, n_samples = 0, taken = 0;
+    int64_t next_sample() const { return taken < n_samples ? warmup + taken * every : -1; }
+    void release() {
+      fr_probe_destroy(probe);
+      fr_fwh_destroy(rec);
+      fr_mesh_destroy(m);
+      probe = nullptr;
+      rec = nullptr;
+      m = nullptr;
+    }
   };
   std::map<int64_t, Req> reqs;
   int64_t next_slot = 0, rr = 0;
@@ -97,7 +111,7 @@ fr_status fr_pool_create(size_t budget, int32_t device, fr_pool **out) {
 
 void fr_pool_destroy(fr_pool *p) {
   if (!p) return;
-  for (auto &kv : p->reqs) fr_mesh_destroy(kv.second.m);
+  for (auto &kv : p->reqs) kv.second.release();
   for (auto s : p->streams) {
     hipStreamSynchronize(s);
     hipStreamDestroy(s);
@@ -105,11 +119,23 @@ void fr_pool_destroy(fr_pool *p) {
   delete p;
 }
 
-fr_status fr_pool_admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, int64_t steps, int64_t *slot) {
-  if (!p || !desc || !slot || steps <= 0) return FR_E_ARG;
+}  // extern "C"
+
+namespace {
+
+bool valid_surface(const fr_pool_surface *s) {
+  return s->n_points > 0 && s->points && s->normals && s->areas && s->n_copies >= 1 && s->warmup >= 0 &&
+         s->every >= 1 && s->n_samples >= 8;
+}
+
+fr_status admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, int64_t steps, const fr_pool_surface *surf,
+                int64_t *slot) {
   size_t need = 0;
   fr_status st = fr_footprint(desc, &need);
   if (st != FR_OK) return st;
+  if (surf)
+    need += fr::probe_footprint(surf->n_points, desc->dim, desc->order) +
+            fr::fwh_footprint(surf->n_points, surf->n_samples);
   hipStream_t stream;
   {
     // reserve the footprint first so that concurrent admissions respect the budget
@@ -118,21 +144,20 @@ fr_status fr_pool_admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, 
     p->used += need;
     stream = p->streams[p->rr++ % p->streams.size()];
   }
-  auto release = [&] {
+  fr_pool::Req r;
+  auto undo = [&](fr_status code) {
+    r.release();
     std::lock_guard<std::mutex> lk(p->mu);
     p->used -= std::min(p->used, need);
+    return code;
   };
   fr_mesh_desc d = *desc;
   d.device = p->device;
   d.stream = stream;
-  fr_mesh *m = nullptr;
-  st = fr_mesh_create(&d, &m);
-  if (st != FR_OK) {
-    release();
-    return st;
-  }
+  st = fr_mesh_create(&d, &r.m);
+  if (st != FR_OK) return undo(st);
   int64_t info[10];
-  fr_mesh_info(m, info);
+  fr_mesh_info(r.m, info);
   const int64_t n = info[3] * info[4] * info[6];
   std::vector<double> u;
   if (!u0) {
@@ -149,14 +174,36 @@ fr_status fr_pool_admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, 
     }
     u0 = u.data();
   }
-  st = fr_set_state(m, u0);
-  if (st != FR_OK) {
-    fr_mesh_destroy(m);
-    release();
-    return st;
+  st = fr_set_state(r.m, u0);
+  if (st != FR_OK) return undo(st);
+  if (surf) {
+    st = fr_probe_create(r.m, &d, 0, surf->n_points, surf->points, &r.probe);
+    if (st != FR_OK) return undo(st);
+    const double *fs = desc->freestream;
+    fr_fwh_desc fd{};
+    fd.n_points = surf->n_points;
+    fd.points = surf->points;
+    fd.normals = surf->normals;
+    fd.areas = surf->areas;
+    fd.n_copies = surf->n_copies;
+    fd.c0 = std::sqrt(desc->gamma * fs[4] / fs[0]);
+    for (int i = 0; i < 3; ++i) {
+      fd.copy_shift[i] = surf->copy_shift[i];
+      fd.mach[i] = (i < desc->dim ? fs[1 + i] : 0.0) / fd.c0;
+    }
+    fd.rho0 = fs[0];
+    fd.p0 = fs[4];
+    fd.dt = double(surf->every) * desc->dt;
+    fd.tau0 = 0.0;
+    fd.capacity = surf->n_samples;
+    fd.device = p->device;
+    fd.stream = stream;
+    st = fr_fwh_create(&fd, &r.rec);
+    if (st != FR_OK) return undo(st);
+    r.warmup = surf->warmup;
+    r.every = surf->every;
+    r.n_samples = surf->n_samples;
   }
-  fr_pool::Req r;
-  r.m = m;
   r.left = r.total = steps;
   r.bytes = need;
   std::lock_guard<std::mutex> lk(p->mu);
@@ -165,21 +212,57 @@ fr_status fr_pool_admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, 
   return FR_OK;
 }
 
+// Enqueue up to k steps of a running request, with its due snapshots in between.
+fr_status enqueue(fr_pool::Req &r, int64_t k) {
+  bool first = true;
+  for (;;) {
+    const int64_t pos = r.total - r.left;
+    if (r.next_sample() == pos) {
+      fr_status st = FR_OK;
+      if (r.taken == 0) st = fr::means_clear(r.m);  // means over the sampled period
+      if (st == FR_OK) st = fr::fwh_append_probe_async(r.rec, r.probe);
+      if (st != FR_OK) return st;
+      ++r.taken;
+      continue;
+    }
+    if (k == 0 || r.left == 0) return FR_OK;
+    int64_t n = std::min(k, r.left);
+    if (r.next_sample() > pos) n = std::min(n, r.next_sample() - pos);
+    const fr_status st = fr::step_enqueue(r.m, n, first);
+    if (st != FR_OK) return st;
+    first = false;
+    r.left -= n;
+    k -= n;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+fr_status fr_pool_admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, int64_t steps, int64_t *slot) {
+  if (!p || !desc || !slot || steps <= 0) return FR_E_ARG;
+  return admit(p, desc, u0, steps, nullptr, slot);
+}
+
+fr_status fr_pool_admit_sampled(fr_pool *p, const fr_mesh_desc *desc, const double *u0, const fr_pool_surface *s,
+                                int64_t *slot) {
+  if (!p || !desc || !slot || !s || !valid_surface(s)) return FR_E_ARG;
+  return admit(p, desc, u0, s->warmup + (s->n_samples - 1) * s->every, s, slot);
+}
+
 fr_status fr_pool_launch(fr_pool *p, int64_t k) {
   if (!p || k <= 0) return FR_E_ARG;
   std::lock_guard<std::mutex> lk(p->mu);
   for (auto &kv : p->reqs) {
     auto &r = kv.second;
     if (r.done || r.in_flight) continue;
-    const int64_t n = std::min(k, r.left);
-    const fr_status st = fr_step_async(r.m, n);
+    const fr_status st = enqueue(r, k);
+    r.in_flight = true;  // collect waits for what was enqueued, also after a failure
     if (st != FR_OK) {
       r.done = true;
       r.status = st;
-      continue;
     }
-    r.left -= n;
-    r.in_flight = true;
   }
   return FR_OK;
 }
@@ -196,10 +279,10 @@ fr_status fr_pool_collect(fr_pool *p, int64_t *done, int32_t max_done, int32_t *
     }
     r.in_flight = false;
     const fr_status st = fr_sync(r.m);
-    if (st != FR_OK) {
+    if (r.status == FR_OK && st != FR_OK) {
       r.done = true;
       r.status = st;
-    } else if (r.left == 0) {
+    } else if (r.left == 0 && r.next_sample() < 0) {
       r.done = true;
     }
     if (r.done && done && *n_done < max_done) done[(*n_done)++] = kv.first;
@@ -223,10 +306,21 @@ fr_status fr_pool_result(fr_pool *p, int64_t slot, double *out, double *u) {
   fr_status st = r.status;
   if (st == FR_OK && out) st = fr_forces(r.m, 0, out);
   if (st == FR_OK && u) st = fr_get_state(r.m, u);
-  fr_mesh_destroy(r.m);
+  r.release();
   p->used -= std::min(p->used, r.bytes);
   p->reqs.erase(it);
   return st;
+}
+
+fr_status fr_pool_pressure(fr_pool *p, int64_t slot, const double *observer, int64_t capacity, double *t_start,
+                           int64_t *n_out, double *pressure) {
+  if (!p || !observer || !t_start || !n_out || !pressure) return FR_E_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  auto it = p->reqs.find(slot);
+  if (it == p->reqs.end()) return FR_E_ARG;
+  auto &r = it->second;
+  if (!r.done || r.in_flight || r.status != FR_OK || !r.rec) return FR_E_STATE;
+  return fr_fwh_pressure(r.rec, observer, capacity, t_start, n_out, pressure, nullptr, nullptr);
 }
 
 fr_status fr_pool_usage(const fr_pool *p, int64_t *used) {

@@ -269,6 +269,47 @@ class FRPool:
         check(rc, "fr_pool_admit")
         return slot.value
 
+    def admit_sampled(self, mesh, surface, warmup, every, n_samples, precision="fp32", u0=None):
+        """A request whose flow is sampled on a data surface and fed to an FW-H record.
+
+        surface: dict of points [n, 3], normals [n, 3], areas [n], and optionally
+        n_copies and copy_shift.  Runs warmup + (n_samples - 1) * every steps.
+        Returns the slot id, or None if the request does not fit now."""
+        d, keep = _desc(mesh, precision)
+        pts = np.ascontiguousarray(surface["points"], dtype=np.float64).reshape(-1, 3)
+        nrm = np.ascontiguousarray(surface["normals"], dtype=np.float64).reshape(-1, 3)
+        area = np.ascontiguousarray(surface["areas"], dtype=np.float64).reshape(-1)
+        if nrm.shape != pts.shape or area.shape[0] != pts.shape[0]:
+            raise ValueError("surface points, normals and areas differ in count")
+        s = _lib.PoolSurface()
+        s.n_points = pts.shape[0]
+        s.points, s.normals, s.areas = (a.ctypes.data_as(_lib._dp) for a in (pts, nrm, area))
+        s.n_copies = int(surface.get("n_copies", 1))
+        s.copy_shift[:] = [float(v) for v in surface.get("copy_shift", (0.0, 0.0, 0.0))]
+        s.warmup, s.every, s.n_samples = int(warmup), int(every), int(n_samples)
+        slot = ctypes.c_int64()
+        up = None
+        if u0 is not None:
+            u0 = np.ascontiguousarray(u0, dtype=np.float64)
+            up = u0.ctypes.data_as(_lib._dp)
+        rc = _lib.load().fr_pool_admit_sampled(self.h, ctypes.byref(d), up, ctypes.byref(s), ctypes.byref(slot))
+        if rc == _lib.FR_E_NOMEM:
+            return None
+        check(rc, "fr_pool_admit_sampled")
+        return slot.value
+
+    def pressure(self, slot, observer, capacity):
+        """(first observer time, p' on the times spaced by the sampling interval) at
+        observer of a finished sampled request; call before result()."""
+        xo = np.ascontiguousarray(observer, dtype=np.float64).reshape(3)
+        p = np.zeros(int(capacity))
+        t0 = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(_lib.load().fr_pool_pressure(self.h, int(slot), xo.ctypes.data_as(_lib._dp), int(capacity),
+                                           ctypes.byref(t0), ctypes.byref(n), p.ctypes.data_as(_lib._dp)),
+              "fr_pool_pressure")
+        return t0.value, p[:n.value].copy()
+
     def tick(self, k, max_done=256):
         done = np.zeros(max_done, dtype=np.int64)
         n = ctypes.c_int32()

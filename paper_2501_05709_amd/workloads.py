@@ -104,7 +104,7 @@ def naca4(m, pc, t, theta):
     x = np.clip(1.0 - np.sin(0.5 * np.pi * u), 0.0, 1.0)
     yt = 5.0 * t * (0.2969 * np.sqrt(np.maximum(x, 0.0)) - 0.1260 * x - 0.3516 * x ** 2
                     + 0.2843 * x ** 3 - 0.1036 * x ** 4)
-    if m > 0.0:
+    if m != 0.0:  # negative m: camber below the chord
         yc = np.where(x < pc, m / pc ** 2 * (2 * pc * x - x ** 2),
                       m / (1 - pc) ** 2 * ((1 - 2 * pc) + 2 * pc * x - x ** 2))
         dyc = np.where(x < pc, 2 * m / pc ** 2 * (pc - x), 2 * m / (1 - pc) ** 2 * (pc - x))
@@ -132,9 +132,13 @@ def naca_ogrid(m, pc, t, ni, nj, nk, span=0.2, radius=20.0, ratio=1.1, q=2, orde
     nIq, nJq, nKq = ni * q, nj * q + 1, nk * q + 1
     theta = 2.0 * np.pi * np.arange(nIq) / nIq
     xs, ys = naca4(m, pc, t, theta)
-    # outer points turn with the trailing-edge bisector (camber slope at x = 1)
-    # so that the rays leaving the trailing edge split its wedge
-    phi = math.atan(-2.0 * m / (1.0 - pc)) if m > 0.0 else 0.0
+    # the outer points near the trailing edge turn with its bisector (camber slope at
+    # x = 1) so that the rays leaving it split its wedge; the turn fades out quickly
+    # away from it, since turned rays from the mid-chord would cut across an aft-
+    # cambered body or the nose.  Strong camber far aft (|m| >= 0.05 at pc = 0.9)
+    # still folds elements at the trailing edge: the library rejects such meshes
+    # (non-positive Jacobian)
+    phi = math.atan(-2.0 * m / (1.0 - pc)) * (0.5 * (1.0 + np.cos(theta))) ** 8
     ox = 0.5 + radius * np.cos(phi - theta)
     oy = radius * np.sin(phi - theta)
     jj = np.arange(nJq) / q

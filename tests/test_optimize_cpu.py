@@ -1,0 +1,155 @@
+"""Host logic of the optimisation client (Section 3.4, Algorithm 1): design mapping, the
+data surface of Section 3.1, OASPL, and the pool-driving evaluator against a stand-in
+pool (continuous batching under a budget, failures as infeasible points)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import probe
+from paper_2501_05709_amd import _lib, mads
+from paper_2501_05709_amd import optimize as O
+
+
+def test_oaspl_of_a_tone():
+    pref = O.p_ref()
+    t = np.arange(4000) * (2 * np.pi / 400)   # ten whole periods
+    A = 3e-4
+    p = 71.0 + A * np.sin(t)
+    assert abs(O.oaspl(p, pref) - 20 * np.log10(A / np.sqrt(2) / pref)) < 1e-9
+    # 20 uPa at the reference dynamic pressure is 0 dB
+    assert abs(O.oaspl(pref * np.sqrt(2) * np.sin(t), pref)) < 1e-9
+
+
+def test_design_bounds_map_to_naca_parameters():
+    lo = O.profile(mads.unscale(np.zeros(4)))
+    hi = O.profile(mads.unscale(np.ones(4)))
+    assert np.allclose(lo, (-0.10, 0.4, 0.06, 0.0)) and np.allclose(hi, (0.10, 0.9, 0.18, 12.0))
+    x = np.array([0.3, 0.7, 0.1, 0.9])
+    assert np.allclose(mads.scale(mads.unscale(x)), x, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("aoa", [0.0, 6.0, 12.0])
+def test_data_surface_geometry(aoa):
+    span, sp, wake, height = 0.2, 0.05, 4.0, 1.0
+    s = O.data_surface(aoa, spacing=sp, span=span, lz=25.0)
+    pts, nrm, area = s["points"], s["normals"], s["areas"]
+    # two sheets of (1 + wake + height / 2) chords and a closing sheet of one chord, full span
+    assert abs(area.sum() - (2 * (1.0 + wake + height / 2) + height) * span) < 1e-12
+    assert np.allclose(np.linalg.norm(nrm, axis=1), 1.0)
+    # outward: away from a point inside the surface on its axis, tilted with it
+    a = math.radians(aoa)
+    axis = np.array([math.cos(a), math.sin(a), 0.0])
+    inside = 2.0 * axis + np.array([0.0, 0.0, span / 2])
+    assert np.all(np.einsum("ij,ij->i", pts - inside, nrm) > 0)
+    # the sheets run along the stream: their normals are perpendicular to it
+    sheets = np.abs(nrm @ axis) < 1e-12
+    assert sheets.sum() == 2 * round((1.0 + wake + height / 2) / sp) * round(span / sp)
+    # spanwise: half a panel inside the periodic planes; copies fill lz, odd count
+    assert np.isclose(pts[:, 2].min(), sp / 2) and np.isclose(pts[:, 2].max(), span - sp / 2)
+    assert s["n_copies"] % 2 == 1 and s["n_copies"] * span >= 25.0 - 1e-9
+
+
+@pytest.mark.parametrize("x", [[0.0, 6.5, 12.0, 6.0], [4.0, 4.0, 6.0, 12.0], [-6.0, 7.0, 18.0, 0.0]])
+def test_surface_lies_in_the_fluid(x):
+    """Every data-surface point of the tiny test study lies in an element of the design's
+    O-grid (oracle point location), so no point falls inside the body or outside the grid."""
+    st = O.Study(ni=16, nj=6, nk=1, radius=8.0, spacing=0.25, lz=1.0)
+    mesh = st.mesh(x, dt=1e-3)
+    surf = st.surface(x)
+    elem, xi = probe.locate(mesh, surf["points"])
+    assert np.all(np.abs(xi) <= 1.0 + 1e-10)
+
+
+class FakePool:
+    """Stand-in for FRPool: admits while fewer than `cap` run, finishes a request after
+    ceil(steps / k) ticks; its results are functions of the design's free stream."""
+
+    def __init__(self, budget_bytes, device=0, cap=3, fail_aoa=(), nonfinite_aoa=(), short_aoa=()):
+        self.cap, self.fail_aoa, self.nonfinite_aoa, self.short_aoa = cap, fail_aoa, nonfinite_aoa, short_aoa
+        self.run, self.done, self.next = {}, {}, 0
+        self.admitted = []
+
+    def close(self):
+        pass
+
+    def admit_sampled(self, mesh, surface, warmup, every, n_samples, precision="fp32", u0=None):
+        aoa = round(math.degrees(math.atan2(mesh["freestream"][2], mesh["freestream"][1])), 9)
+        if aoa in self.fail_aoa:
+            raise _lib.FRError(_lib.FR_E_MESH, "non-positive Jacobian")
+        if len(self.run) >= self.cap:
+            return None
+        slot = self.next
+        self.next += 1
+        self.run[slot] = [warmup + (n_samples - 1) * every, aoa, n_samples]
+        self.admitted.append(aoa)
+        return slot
+
+    def tick(self, k, max_done=256):
+        out = []
+        for slot in list(self.run):
+            self.run[slot][0] -= k
+            if self.run[slot][0] <= 0:
+                self.done[slot] = self.run.pop(slot)
+                out.append(slot)
+        return out
+
+    def pressure(self, slot, observer, capacity):
+        _, aoa, n = self.done[slot]
+        if aoa in self.nonfinite_aoa:
+            raise _lib.FRError(_lib.FR_E_STATE, "request failed")
+        if aoa in self.short_aoa:
+            raise _lib.FRError(_lib.FR_E_STATE, "record too short for the spread of arrival times")
+        return 0.0, (1.0 + aoa) * 1e-4 * np.sin(np.arange(n - 8) * 0.3)
+
+    def result(self, slot):
+        _, aoa, _ = self.done.pop(slot)
+        if aoa in self.nonfinite_aoa:
+            raise _lib.FRError(_lib.FR_E_NONFINITE, "non-finite state after a step")
+        out = np.zeros(8)
+        out[5], out[6] = 0.1 * aoa, 0.01 + 0.001 * aoa
+        return out
+
+
+def test_pool_evaluator_batches_under_the_budget(monkeypatch):
+    pools = []
+
+    def make(budget, device=0):
+        pools.append(FakePool(budget, device, cap=3, fail_aoa=(5.0,), nonfinite_aoa=(7.0,)))
+        return pools[-1]
+
+    monkeypatch.setattr(O, "FRPool", make)
+    st = O.Study(ni=8, nj=3, nk=1, radius=8.0, warmup=10, every=2, n_samples=16, chunk=7, spacing=0.5, lz=1.0)
+    ev = O.PoolEvaluator(st, [0.0, 6.5, 12.0, 3.0])
+    aoas = [1.0, 2.0, 5.0, 3.0, 7.0, 4.0, 6.0, 8.0]
+    res = ev([[0.0, 6.5, 12.0, a] for a in aoas])
+    pool = pools[0]
+    # every feasible design was admitted, in order, never more than the budget allows
+    assert pool.admitted == [a for a in aoas if a != 5.0]
+    assert ev.max_running == 3
+    for a, r in zip(aoas, res):
+        if a in (5.0, 7.0):        # no valid mesh / a non-finite run: infeasible
+            assert not r.ok and r.oaspl == math.inf
+            continue
+        assert r.ok and r.cl == pytest.approx(0.1 * a) and r.cd == pytest.approx(0.01 + 0.001 * a)
+        expect = O.oaspl((1.0 + a) * 1e-4 * np.sin(np.arange(8) * 0.3), O.p_ref())
+        assert r.oaspl == pytest.approx(expect)
+    assert not pool.run and not pool.done   # every slot was collected and freed
+
+
+def test_pool_evaluator_reports_a_design_that_never_fits(monkeypatch):
+    monkeypatch.setattr(O, "FRPool", lambda budget, device=0: FakePool(budget, device, cap=0))
+    st = O.Study(ni=8, nj=3, nk=1, radius=8.0, spacing=0.5, lz=1.0)
+    ev = O.PoolEvaluator(st, [0.0, 6.5, 12.0, 3.0])
+    with pytest.raises(RuntimeError, match="budget"):
+        ev([[0.0, 6.5, 12.0, 3.0]])
+
+
+def test_pool_evaluator_does_not_hide_a_too_short_record(monkeypatch):
+    """A run that succeeded but whose record cannot cover the observer's arrival spread
+    is a set-up error, not an infeasible design."""
+    monkeypatch.setattr(O, "FRPool", lambda budget, device=0: FakePool(budget, device, short_aoa=(2.0,)))
+    st = O.Study(ni=8, nj=3, nk=1, radius=8.0, spacing=0.5, lz=1.0, warmup=4, every=2, n_samples=16, chunk=8)
+    ev = O.PoolEvaluator(st, [0.0, 6.5, 12.0, 3.0])
+    with pytest.raises(RuntimeError, match="too short"):
+        ev([[0.0, 6.5, 12.0, 1.0], [0.0, 6.5, 12.0, 2.0]])
