@@ -6,7 +6,7 @@ built, its flow is advanced from the free stream, sampled on the permeable data 
 of Section 3.1 and fed to an FW-H record on the device, and its mean lift and drag are
 accumulated over the sampled period.  The 2n poll designs of an iteration are admitted
 together and run side by side on the GPU, so an iteration takes about as long as one
-flow solve (the two layers of parallelism of Section 2.4); a design that does not fit
+flow solve (the two layers of parallelism of Section 2.2); a design that does not fit
 the pool's HBM budget waits until another finishes.  The objective is the OASPL at the
 observer plus the lift and drag penalties of Section 3.4.
 
@@ -19,7 +19,7 @@ Set-up (non-dimensional: chord, free-stream density and speed are 1):
     free stream at the angle of attack (Mach 0.2, Re 23,000);
   * the data surface of Section 3.1 (two sheets one chord apart, reaching four chords
     into the wake, closed upstream and open downstream, spanning the periodic span),
-    tilted by the angle of attack about the leading edge (Section 3.3), duplicated along
+    tilted by the angle of attack about the leading edge (Section 3.4), duplicated along
     the span to ``lz`` chords;
   * the observer ten chords below the trailing edge, at mid-span;
   * one RK4 step for all designs (the baseline's stable step times a safety factor), so
