@@ -51,30 +51,55 @@
 #define BC_WALL 1
 #define BC_FARFIELD 2
 
+/* 1D basis of one order on [-1,1] */
 typedef struct {
-  int dim, order, q, n, nu, nfp, nf, nv;
-  long E, nnodes;
-  double gamma, pr, mu;
-  double fs[5];              /* free stream: rho, vx, vy, vz, p */
-  /* 1D basis on [-1,1] */
+  int n;
   double xi[MAXN], w[MAXN];
   double D[MAXN][MAXN];      /* D[i][j] = l_j'(xi_i) */
   double lm[MAXN], lp[MAXN]; /* l_j(-1), l_j(+1) */
   double gLd[MAXN], gRd[MAXN];
-  /* geometry */
-  double *S;    /* [E][nu][3][3]  S[k][j] = |J| dxi_k/dx_j */
-  double *detJ; /* [E][nu] */
-  double *xu;   /* [E][nu][3] */
-  double *fnv;  /* [E][nf][3] outward unit normal */
-  double *fA;   /* [E][nf] |S^T n_hat| */
-  double *fxyz; /* [E][nf][3] */
-  double *fw;   /* [nf] face quadrature weight of each flux point */
-  long *nbr;    /* [E][nf] partner e*nf+q, or -BC kind */
+} orc_basis1d;
+
+/* a face shared by elements of different orders: A has the higher order;
+ * corner c of A's face sits at corner pi[c] of B's face */
+typedef struct {
+  long eA, eB;
+  int fA, fB;
+  int pi[4];
+} orc_mortar;
+
+typedef struct {
+  int dim, order, q, nv;     /* order: the largest element order */
+  long E, nnodes;
+  double gamma, pr, mu;
+  double fs[5];              /* free stream: rho, vx, vy, vz, p */
+  orc_basis1d bas[MAXN];     /* by order */
+  int *ord;                  /* [E] element order */
+  long *uo, *fo;             /* [E+1] first solution / flux point of each element */
+  long NU, NF;               /* solution and flux points of the mesh */
+  /* geometry; element e owns points uo[e] .. uo[e+1]-1 and fo[e] .. fo[e+1]-1 */
+  double *S;    /* [NU][3][3]  S[k][j] = |J| dxi_k/dx_j */
+  double *detJ; /* [NU] */
+  double *xu;   /* [NU][3] */
+  double *fnv;  /* [NF][3] outward unit normal */
+  double *fA;   /* [NF] |S^T n_hat| */
+  double *fxyz; /* [NF][3] */
+  long *nbr;    /* [NF] partner flux point, -BC kind, or -(MORTAR0 + mortar index) */
+  long nmortar;
+  orc_mortar *mortar;
   /* scratch */
   double *uf, *gu, *guf;
   int mock;
   double mock_lambda;
 } orc_mesh;
+
+#define MORTAR0 4
+
+/* per-element sizes */
+static int el_n(const orc_mesh *M, long e) { return M->ord[e] + 1; }
+static int el_nu(const orc_mesh *M, long e) { return (int)(M->uo[e + 1] - M->uo[e]); }
+static int el_nfp(const orc_mesh *M, long e) { int n = el_n(M, e); return M->dim == 2 ? n : n * n; }
+static int el_nf(const orc_mesh *M, long e) { return (int)(M->fo[e + 1] - M->fo[e]); }
 
 /* ------------------------------------------------------------------ */
 /* 1D basis                                                           */
@@ -156,9 +181,8 @@ int orc_basis(int order, double *xi, double *w, double *D, double *lm, double *l
 /* index helpers                                                      */
 /* ------------------------------------------------------------------ */
 
-/* solution point index of the point on face-line (k, m) with i_k = j */
-static int line_pt(const orc_mesh *M, int k, int m, int j) {
-  int n = M->n;
+/* solution point index of the point on face-line (k, m) with i_k = j, n points per line */
+static int line_pt(const orc_mesh *M, int n, int k, int m, int j) {
   if (M->dim == 2) {
     if (k == 0) return j + n * m;
     return m + n * j;
@@ -170,8 +194,7 @@ static int line_pt(const orc_mesh *M, int k, int m, int j) {
 }
 
 /* position of solution point i along axis k, and its face-line index m */
-static void pt_line(const orc_mesh *M, int i, int k, int *ik, int *m) {
-  int n = M->n;
+static void pt_line(const orc_mesh *M, int n, int i, int k, int *ik, int *m) {
   int c[3] = {i % n, (i / n) % n, i / (n * n)};
   *ik = c[k];
   if (M->dim == 2) { *m = (k == 0) ? c[1] : c[0]; return; }
@@ -180,16 +203,46 @@ static void pt_line(const orc_mesh *M, int i, int k, int *ik, int *m) {
   else *m = c[0] + n * c[1];
 }
 
-/* reference coordinates of flux point (face f, face point m) */
-static void fpt_ref(const orc_mesh *M, int f, int m, double r[3]) {
-  int k = f / 2, s = f % 2, n = M->n;
+/* reference coordinates of flux point (face f, face point m) of an element with basis B */
+static void fpt_ref(const orc_mesh *M, const orc_basis1d *B, int f, int m, double r[3]) {
+  int k = f / 2, s = f % 2, n = B->n;
   r[0] = r[1] = r[2] = 0.0;
   r[k] = s ? 1.0 : -1.0;
-  if (M->dim == 2) { r[1 - k] = M->xi[m]; return; }
+  if (M->dim == 2) { r[1 - k] = B->xi[m]; return; }
   int a = m % n, b = m / n;
   int ax0 = (k == 0) ? 1 : 0, ax1 = (k == 2) ? 1 : 2;
-  r[ax0] = M->xi[a];
-  r[ax1] = M->xi[b];
+  r[ax0] = B->xi[a];
+  r[ax1] = B->xi[b];
+}
+
+/* face coordinates of face point m (along the face's first and second axis) */
+static void face_coords(const orc_mesh *M, const orc_basis1d *B, int m, double s[2]) {
+  if (M->dim == 2) { s[0] = B->xi[m]; s[1] = 0.0; return; }
+  s[0] = B->xi[m % B->n];
+  s[1] = B->xi[m / B->n];
+}
+
+/* face coordinates of face corner c */
+static void corner_coords(int dim, int c, double t[2]) {
+  if (dim == 2) { t[0] = c ? 1.0 : -1.0; t[1] = 0.0; return; }
+  t[0] = (c & 1) ? 1.0 : -1.0;
+  t[1] = ((c >> 1) & 1) ? 1.0 : -1.0;
+}
+
+/* coordinates on B's face of the point at s on A's face, when corner c of A's
+ * face sits at corner pi[c] of B's: the affine map through corners 0, 1 (and 2) */
+static void map_face(int dim, const int *pi, const double s[2], double t[2]) {
+  double T0[2], T1[2], T2[2];
+  corner_coords(dim, pi[0], T0);
+  corner_coords(dim, pi[1], T1);
+  if (dim == 2) {
+    t[0] = T0[0] + 0.5 * (s[0] + 1.0) * (T1[0] - T0[0]);
+    t[1] = 0.0;
+    return;
+  }
+  corner_coords(dim, pi[2], T2);
+  for (int i = 0; i < 2; ++i)
+    t[i] = T0[i] + 0.5 * (s[0] + 1.0) * (T1[i] - T0[i]) + 0.5 * (s[1] + 1.0) * (T2[i] - T0[i]);
 }
 
 /* ------------------------------------------------------------------ */
@@ -292,9 +345,9 @@ static void sort4(long *v, int n) {
     for (int j = i; j > 0 && v[j - 1] > v[j]; --j) { long t = v[j]; v[j] = v[j - 1]; v[j - 1] = t; }
 }
 
-/* corner c of A sits at corner pi[c] of B; write the face-point map */
-static int face_perm(const orc_mesh *M, const int *pi, int *mp) {
-  int n = M->n, d = M->dim;
+/* corner c of A sits at corner pi[c] of B; write the face-point map (n points per line) */
+static int face_perm(const orc_mesh *M, int n, const int *pi, int *mp) {
+  int d = M->dim;
   if (d == 2) {
     /* corners 0,1 are the ends of the line; pi[0] is where A's start lands */
     for (int a = 0; a < n; ++a) mp[a] = pi[0] == 0 ? a : n - 1 - a;
@@ -313,12 +366,41 @@ static int face_perm(const orc_mesh *M, const int *pi, int *mp) {
   return 0;
 }
 
+/* growable list of mortar faces (filled while faces are matched) */
+static int add_mortar(orc_mesh *M, long eA, int fA, long eB, int fB, const int *pi) {
+  int nc = M->dim == 2 ? 2 : 4;
+  orc_mortar r;
+  if (M->ord[eA] > M->ord[eB]) {
+    r.eA = eA; r.fA = fA; r.eB = eB; r.fB = fB;
+    for (int c = 0; c < 4; ++c) r.pi[c] = c < nc ? pi[c] : 0;
+  } else { /* B is the higher order: invert the corner map */
+    r.eA = eB; r.fA = fB; r.eB = eA; r.fB = fA;
+    for (int c = 0; c < 4; ++c) r.pi[c] = 0;
+    for (int c = 0; c < nc; ++c) r.pi[pi[c]] = c;
+  }
+  if ((M->nmortar & (M->nmortar - 1)) == 0) {
+    long cap = M->nmortar ? 2 * M->nmortar : 1;
+    orc_mortar *nm = realloc(M->mortar, cap * sizeof(orc_mortar));
+    if (!nm) return -1;
+    M->mortar = nm;
+  }
+  long k = M->nmortar++;
+  M->mortar[k] = r;
+  for (int side = 0; side < 2; ++side) {
+    long e = side ? r.eB : r.eA;
+    int f = side ? r.fB : r.fA, nfp = el_nfp(M, e);
+    for (int m = 0; m < nfp; ++m) M->nbr[M->fo[e] + f * nfp + m] = -(MORTAR0 + k);
+  }
+  return 0;
+}
+
 static int link_faces(orc_mesh *M, long eA, int fA, long eB, int fB, const int *pi) {
+  if (M->ord[eA] != M->ord[eB]) return add_mortar(M, eA, fA, eB, fB, pi);
   int mp[MAXN * MAXN];
-  if (face_perm(M, pi, mp)) return -1;
-  int nfp = M->nfp, nf = M->nf;
+  int n = el_n(M, eA), nfp = el_nfp(M, eA);
+  if (face_perm(M, n, pi, mp)) return -1;
   for (int m = 0; m < nfp; ++m) {
-    long qa = eA * nf + fA * nfp + m, qb = eB * nf + fB * nfp + mp[m];
+    long qa = M->fo[eA] + fA * nfp + m, qb = M->fo[eB] + fB * nfp + mp[m];
     M->nbr[qa] = qb;
     M->nbr[qb] = qa;
   }
@@ -340,7 +422,7 @@ static int build_connectivity(orc_mesh *M, const double *nodes, const long *en,
   int d = M->dim, nfe = 2 * d, nc = (d == 2) ? 2 : 4, na = M->q + 1;
   int nn = (d == 2) ? na * na : na * na * na;
   long F = E * nfe;
-  for (long i = 0; i < E * M->nf; ++i) M->nbr[i] = 0x7fffffffffffL;
+  for (long i = 0; i < M->NF; ++i) M->nbr[i] = 0x7fffffffffffL;
   face_rec *rec = malloc(F * sizeof(face_rec));
   for (long e = 0; e < E; ++e)
     for (int f = 0; f < nfe; ++f) {
@@ -378,7 +460,7 @@ static int build_connectivity(orc_mesh *M, const double *nodes, const long *en,
   for (long b = 0; b < nbf; ++b) {
     long e = bf[3 * b], f = bf[3 * b + 1], kind = bf[3 * b + 2];
     if (e < 0 || e >= E || f < 0 || f >= nfe || done[e * nfe + f]) { err = -3; continue; }
-    for (int m = 0; m < M->nfp; ++m) M->nbr[e * M->nf + f * M->nfp + m] = -kind;
+    for (int m = 0; m < el_nfp(M, e); ++m) M->nbr[M->fo[e] + f * el_nfp(M, e) + m] = -kind;
     done[e * nfe + f] = 1;
   }
   /* periodic faces: corners coincide after a listed translation.  Unmatched
@@ -589,76 +671,93 @@ static void farfield_ghost(const orc_mesh *M, const double *uL, const double *n,
 void orc_destroy(orc_mesh *M) {
   if (!M) return;
   free(M->S); free(M->detJ); free(M->xu); free(M->fnv); free(M->fA); free(M->fxyz);
-  free(M->fw); free(M->nbr); free(M->uf); free(M->gu); free(M->guf);
+  free(M->nbr); free(M->uf); free(M->gu); free(M->guf);
+  free(M->ord); free(M->uo); free(M->fo); free(M->mortar);
   free(M);
 }
 
-/* returns 0, or <0 on a bad mesh (-5: non-positive Jacobian) */
-int orc_create(int dim, int order, int q, long nnodes, const double *nodes, long E,
-               const long *elem_nodes, int nper, const double *shift, long nbf,
-               const long *bfaces, double gamma, double pr, double mu, const double *fs,
-               orc_mesh **out) {
+/* Mesh with order orders[e] in element e (orders == NULL: every element has
+ * `order`).  Returns 0, or <0 on a bad mesh (-5: non-positive Jacobian). */
+int orc_create_mixed(int dim, int order, const int *orders, int q, long nnodes, const double *nodes,
+                     long E, const long *elem_nodes, int nper, const double *shift, long nbf,
+                     const long *bfaces, double gamma, double pr, double mu, const double *fs,
+                     orc_mesh **out) {
   *out = NULL;
-  if ((dim != 2 && dim != 3) || order < 1 || order + 1 > MAXN || (q != 1 && q != 2)) return -1;
+  if ((dim != 2 && dim != 3) || (q != 1 && q != 2)) return -1;
   orc_mesh *M = calloc(1, sizeof(orc_mesh));
-  M->dim = dim; M->order = order; M->q = q; M->n = order + 1;
-  int n = M->n;
-  M->nu = dim == 2 ? n * n : n * n * n;
-  M->nfp = dim == 2 ? n : n * n;
-  M->nf = 2 * dim * M->nfp;
+  M->dim = dim; M->q = q;
   M->nv = dim + 2;
   M->E = E; M->nnodes = nnodes;
   M->gamma = gamma; M->pr = pr; M->mu = mu;
   for (int i = 0; i < 5; ++i) M->fs[i] = fs ? fs[i] : 0.0;
-  double Dflat[MAXN * MAXN];
-  orc_basis(order, M->xi, M->w, Dflat, M->lm, M->lp, M->gLd, M->gRd);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) M->D[i][j] = Dflat[i * n + j];
-  int nu = M->nu, nf = M->nf, nv = M->nv;
-  M->S = malloc(E * nu * 9 * sizeof(double));
-  M->detJ = malloc(E * nu * sizeof(double));
-  M->xu = malloc(E * nu * 3 * sizeof(double));
-  M->fnv = malloc(E * nf * 3 * sizeof(double));
-  M->fA = malloc(E * nf * sizeof(double));
-  M->fxyz = malloc(E * nf * 3 * sizeof(double));
-  M->fw = malloc(nf * sizeof(double));
-  M->nbr = malloc(E * nf * sizeof(long));
-  M->uf = malloc(E * nf * nv * sizeof(double));
-  M->gu = malloc(E * nu * 3 * nv * sizeof(double));
-  M->guf = malloc(E * nf * 3 * nv * sizeof(double));
-  /* face quadrature weights */
-  for (int f = 0; f < 2 * dim; ++f)
-    for (int m = 0; m < M->nfp; ++m)
-      M->fw[f * M->nfp + m] = dim == 2 ? M->w[m] : M->w[m % n] * M->w[m / n];
+  M->ord = malloc((E > 0 ? E : 1) * sizeof(int));
+  M->uo = malloc((E + 1) * sizeof(long));
+  M->fo = malloc((E + 1) * sizeof(long));
+  M->order = 0;
+  M->uo[0] = M->fo[0] = 0;
+  for (long e = 0; e < E; ++e) {
+    int p = orders ? orders[e] : order;
+    if (p < 1 || p + 1 > MAXN) { orc_destroy(M); return -1; }
+    M->ord[e] = p;
+    if (p > M->order) M->order = p;
+    int n = p + 1;
+    M->uo[e + 1] = M->uo[e] + (dim == 2 ? n * n : n * n * n);
+    M->fo[e + 1] = M->fo[e] + 2 * dim * (dim == 2 ? n : n * n);
+  }
+  if (E == 0) M->order = order;
+  for (int p = 1; p + 1 <= MAXN; ++p) {
+    orc_basis1d *B = &M->bas[p];
+    double Dflat[MAXN * MAXN];
+    B->n = p + 1;
+    orc_basis(p, B->xi, B->w, Dflat, B->lm, B->lp, B->gLd, B->gRd);
+    for (int i = 0; i < B->n; ++i)
+      for (int j = 0; j < B->n; ++j) B->D[i][j] = Dflat[i * B->n + j];
+  }
+  long NU = M->NU = M->uo[E], NF = M->NF = M->fo[E];
+  int nv = M->nv;
+  M->S = malloc((NU + 1) * 9 * sizeof(double));
+  M->detJ = malloc((NU + 1) * sizeof(double));
+  M->xu = malloc((NU + 1) * 3 * sizeof(double));
+  M->fnv = malloc((NF + 1) * 3 * sizeof(double));
+  M->fA = malloc((NF + 1) * sizeof(double));
+  M->fxyz = malloc((NF + 1) * 3 * sizeof(double));
+  M->nbr = malloc((NF + 1) * sizeof(long));
+  M->uf = malloc((NF + 1) * nv * sizeof(double));
+  M->gu = malloc((NU + 1) * 3 * nv * sizeof(double));
+  M->guf = malloc((NF + 1) * 3 * nv * sizeof(double));
   int bad = 0;
 #pragma omp parallel for reduction(| : bad)
   for (long e = 0; e < E; ++e) {
+    const orc_basis1d *B = &M->bas[M->ord[e]];
+    int n = B->n, nu = el_nu(M, e), nfp = el_nfp(M, e);
     for (int i = 0; i < nu; ++i) {
       int c[3] = {i % n, (i / n) % n, i / (n * n)};
-      double r[3] = {M->xi[c[0]], M->xi[c[1]], dim == 3 ? M->xi[c[2]] : 0.0};
+      double r[3] = {B->xi[c[0]], B->xi[c[1]], dim == 3 ? B->xi[c[2]] : 0.0};
       double x[3], J[3][3], S[3][3];
+      long a = M->uo[e] + i;
       map_point(M, nodes, elem_nodes, e, r, x, J);
       double det = adjugate(dim, J, S);
       if (!(det > 0.0)) bad = 1;
-      M->detJ[e * nu + i] = det;
-      memcpy(&M->S[(e * nu + i) * 9], S, sizeof(S));
-      for (int k = 0; k < 3; ++k) M->xu[(e * nu + i) * 3 + k] = x[k];
+      M->detJ[a] = det;
+      memcpy(&M->S[a * 9], S, sizeof(S));
+      for (int k = 0; k < 3; ++k) M->xu[a * 3 + k] = x[k];
     }
     for (int f = 0; f < 2 * dim; ++f)
-      for (int m = 0; m < M->nfp; ++m) {
-        int qq = f * M->nfp + m, k = f / 2;
+      for (int m = 0; m < nfp; ++m) {
+        int k = f / 2;
+        long a = M->fo[e] + f * nfp + m;
         double sg = (f % 2) ? 1.0 : -1.0;
         double r[3], x[3], J[3][3], S[3][3];
-        fpt_ref(M, f, m, r);
+        fpt_ref(M, B, f, m, r);
         map_point(M, nodes, elem_nodes, e, r, x, J);
         double det = adjugate(dim, J, S);
         if (!(det > 0.0)) bad = 1;
-        double a = 0.0;
-        for (int j = 0; j < dim; ++j) a += S[k][j] * S[k][j];
-        a = sqrt(a);
-        M->fA[e * nf + qq] = a;
-        for (int j = 0; j < 3; ++j) M->fnv[(e * nf + qq) * 3 + j] = j < dim ? sg * S[k][j] / a : 0.0;
-        for (int j = 0; j < 3; ++j) M->fxyz[(e * nf + qq) * 3 + j] = x[j];
+        double aa = 0.0;
+        for (int j = 0; j < dim; ++j) aa += S[k][j] * S[k][j];
+        aa = sqrt(aa);
+        M->fA[a] = aa;
+        for (int j = 0; j < 3; ++j) M->fnv[a * 3 + j] = j < dim ? sg * S[k][j] / aa : 0.0;
+        for (int j = 0; j < 3; ++j) M->fxyz[a * 3 + j] = x[j];
       }
   }
   if (bad) { orc_destroy(M); return -5; }
@@ -668,36 +767,123 @@ int orc_create(int dim, int order, int q, long nnodes, const double *nodes, long
   return 0;
 }
 
+int orc_create(int dim, int order, int q, long nnodes, const double *nodes, long E,
+               const long *elem_nodes, int nper, const double *shift, long nbf,
+               const long *bfaces, double gamma, double pr, double mu, const double *fs,
+               orc_mesh **out) {
+  return orc_create_mixed(dim, order, NULL, q, nnodes, nodes, E, elem_nodes, nper, shift, nbf, bfaces,
+                          gamma, pr, mu, fs, out);
+}
+
+/* face quadrature weight of face point m of an element with basis B */
+static double face_weight(const orc_mesh *M, const orc_basis1d *B, int m) {
+  return M->dim == 2 ? B->w[m] : B->w[m % B->n] * B->w[m / B->n];
+}
+
+/* Data on a face shared by elements of different orders (a mortar face).  The
+ * low-order element's face data is its polynomial interpolant through its face
+ * points; the high-order element samples it at its own face points.  Data of
+ * the high-order element reaches the low-order one as its L2 projection onto the
+ * low order's face polynomials, evaluated at the low-order face points; the
+ * projection integral is taken by the high-order face quadrature. */
+
+/* interpolant of the low side's face data g (point m at g[m * stride]) at the
+ * high-side face point mA */
+static double mortar_up(const orc_mesh *M, const orc_mortar *R, int mA, const double *g, int stride) {
+  const orc_basis1d *BA = &M->bas[M->ord[R->eA]], *BB = &M->bas[M->ord[R->eB]];
+  double sA[2], t[2];
+  face_coords(M, BA, mA, sA);
+  map_face(M->dim, R->pi, sA, t);
+  int nB = BB->n, nfpB = el_nfp(M, R->eB);
+  double s = 0.0;
+  for (int m = 0; m < nfpB; ++m) {
+    double l = lagrange(nB, BB->xi, m % nB, t[0]);
+    if (M->dim == 3) l *= lagrange(nB, BB->xi, m / nB, t[1]);
+    s += l * g[m * stride];
+  }
+  return s;
+}
+
+/* L2 projection of the high side's face data h (point j at h[j * stride]) onto
+ * the low order's face polynomials, at the low-side face point mB */
+static double mortar_down(const orc_mesh *M, const orc_mortar *R, int mB, const double *h, int stride) {
+  const orc_basis1d *BA = &M->bas[M->ord[R->eA]], *BB = &M->bas[M->ord[R->eB]];
+  int pB = M->ord[R->eB], nfpA = el_nfp(M, R->eA), d = M->dim;
+  double tB[2];
+  face_coords(M, BB, mB, tB);
+  double out = 0.0;
+  for (int k1 = 0; k1 <= (d == 3 ? pB : 0); ++k1)
+    for (int k0 = 0; k0 <= pB; ++k0) {
+      /* coefficient of L_k0(t0) L_k1(t1): (2k+1)/2 per axis times the integral */
+      double c = 0.0;
+      for (int j = 0; j < nfpA; ++j) {
+        double sA[2], t[2], P0, P1 = 1.0, dP;
+        face_coords(M, BA, j, sA);
+        map_face(d, R->pi, sA, t);
+        legendre(k0, t[0], &P0, &dP);
+        if (d == 3) legendre(k1, t[1], &P1, &dP);
+        c += face_weight(M, BA, j) * h[j * stride] * P0 * P1;
+      }
+      c *= 0.5 * (2 * k0 + 1);
+      if (d == 3) c *= 0.5 * (2 * k1 + 1);
+      double L0, L1 = 1.0, dP;
+      legendre(k0, tB[0], &L0, &dP);
+      if (d == 3) legendre(k1, tB[1], &L1, &dP);
+      out += c * L0 * L1;
+    }
+  return out;
+}
+
 /* ------------------------------------------------------------------ */
 /* residual                                                           */
 /* ------------------------------------------------------------------ */
 
 /* interior trace of u at every flux point */
 static void pass_interp(orc_mesh *M, const double *u) {
-  int nf = M->nf, nv = M->nv, nfp = M->nfp, n = M->n, nu = M->nu;
+  int nv = M->nv;
 #pragma omp parallel for
-  for (long e = 0; e < M->E; ++e)
+  for (long e = 0; e < M->E; ++e) {
+    const orc_basis1d *B = &M->bas[M->ord[e]];
+    int n = B->n, nfp = el_nfp(M, e);
     for (int f = 0; f < 2 * M->dim; ++f) {
-      const double *l = (f % 2) ? M->lp : M->lm;
+      const double *l = (f % 2) ? B->lp : B->lm;
       for (int m = 0; m < nfp; ++m)
         for (int v = 0; v < nv; ++v) {
           double s = 0.0;
-          for (int j = 0; j < n; ++j) s += l[j] * u[(e * nu + line_pt(M, f / 2, m, j)) * nv + v];
-          M->uf[(e * nf + f * nfp + m) * nv + v] = s;
+          for (int j = 0; j < n; ++j) s += l[j] * u[(M->uo[e] + line_pt(M, n, f / 2, m, j)) * nv + v];
+          M->uf[(M->fo[e] + f * nfp + m) * nv + v] = s;
         }
     }
+  }
 }
+
+/* face point m of face f of element e on a mortar face: which side it is on */
+static const orc_mortar *mortar_of(const orc_mesh *M, long code) { return &M->mortar[-code - MORTAR0]; }
 
 /* common solution at flux point qq of element e (BR1 mean, or boundary value) */
 static void common_solution(const orc_mesh *M, long e, int qq, double *uc) {
-  int nf = M->nf, nv = M->nv, d = M->dim;
-  const double *uL = &M->uf[(e * nf + qq) * nv];
-  long nb = M->nbr[e * nf + qq];
+  int nv = M->nv, d = M->dim;
+  long a = M->fo[e] + qq;
+  const double *uL = &M->uf[a * nv];
+  long nb = M->nbr[a];
   if (nb >= 0) {
     const double *uR = &M->uf[nb * nv];
     for (int v = 0; v < nv; ++v) uc[v] = 0.5 * (uL[v] + uR[v]);
+  } else if (nb <= -MORTAR0) {
+    /* mean of the own trace and the other side's trace brought to this point:
+     * interpolated up on the high side, projected down on the low side */
+    const orc_mortar *R = mortar_of(M, nb);
+    int nfp = el_nfp(M, e), m = qq % nfp;
+    for (int v = 0; v < nv; ++v) {
+      double uo;
+      if (e == R->eA && qq / nfp == R->fA)
+        uo = mortar_up(M, R, m, &M->uf[(M->fo[R->eB] + R->fB * el_nfp(M, R->eB)) * nv + v], nv);
+      else
+        uo = mortar_down(M, R, m, &M->uf[(M->fo[R->eA] + R->fA * el_nfp(M, R->eA)) * nv + v], nv);
+      uc[v] = 0.5 * (uL[v] + uo);
+    }
   } else if (nb == -BC_FARFIELD) {
-    farfield_ghost(M, uL, &M->fnv[(e * nf + qq) * 3], uc);
+    farfield_ghost(M, uL, &M->fnv[a * 3], uc);
   } else { /* wall: zero velocity, same density and internal energy */
     double ke = 0.0;
     for (int i = 0; i < d; ++i) ke += uL[1 + i] * uL[1 + i] / uL[0];
@@ -709,46 +895,49 @@ static void common_solution(const orc_mesh *M, long e, int qq, double *uc) {
 
 /* corrected physical gradient at solution points and its trace at flux points */
 static void pass_gradient(orc_mesh *M, const double *u) {
-  int nf = M->nf, nv = M->nv, nfp = M->nfp, n = M->n, nu = M->nu, d = M->dim;
+  int nv = M->nv, d = M->dim;
 #pragma omp parallel for
   for (long e = 0; e < M->E; ++e) {
+    const orc_basis1d *B = &M->bas[M->ord[e]];
+    int n = B->n, nu = el_nu(M, e), nf = el_nf(M, e), nfp = el_nfp(M, e);
+    long uo = M->uo[e], fo = M->fo[e];
     double du[6 * MAXN * MAXN][5];
     for (int qq = 0; qq < nf; ++qq) {
       double uc[5];
       common_solution(M, e, qq, uc);
-      for (int v = 0; v < nv; ++v) du[qq][v] = uc[v] - M->uf[(e * nf + qq) * nv + v];
+      for (int v = 0; v < nv; ++v) du[qq][v] = uc[v] - M->uf[(fo + qq) * nv + v];
     }
     for (int i = 0; i < nu; ++i) {
       double G[3][5];
       for (int k = 0; k < d; ++k) {
         int ik, m;
-        pt_line(M, i, k, &ik, &m);
+        pt_line(M, n, i, k, &ik, &m);
         int qm = (2 * k) * nfp + m, qp = (2 * k + 1) * nfp + m;
         for (int v = 0; v < nv; ++v) {
           double s = 0.0;
-          for (int j = 0; j < n; ++j) s += M->D[ik][j] * u[(e * nu + line_pt(M, k, m, j)) * nv + v];
-          s += du[qp][v] * M->gRd[ik] + du[qm][v] * M->gLd[ik];
+          for (int j = 0; j < n; ++j) s += B->D[ik][j] * u[(uo + line_pt(M, n, k, m, j)) * nv + v];
+          s += du[qp][v] * B->gRd[ik] + du[qm][v] * B->gLd[ik];
           G[k][v] = s;
         }
       }
-      const double *S = &M->S[(e * nu + i) * 9];
-      double J = M->detJ[e * nu + i];
+      const double *S = &M->S[(uo + i) * 9];
+      double J = M->detJ[uo + i];
       for (int j = 0; j < d; ++j)
         for (int v = 0; v < nv; ++v) {
           double s = 0.0;
           for (int k = 0; k < d; ++k) s += S[k * 3 + j] * G[k][v];
-          M->gu[((e * nu + i) * 3 + j) * nv + v] = s / J;
+          M->gu[((uo + i) * 3 + j) * nv + v] = s / J;
         }
     }
     for (int f = 0; f < 2 * d; ++f) {
-      const double *l = (f % 2) ? M->lp : M->lm;
+      const double *l = (f % 2) ? B->lp : B->lm;
       for (int m = 0; m < nfp; ++m)
         for (int j = 0; j < d; ++j)
           for (int v = 0; v < nv; ++v) {
             double s = 0.0;
             for (int jj = 0; jj < n; ++jj)
-              s += l[jj] * M->gu[((e * nu + line_pt(M, f / 2, m, jj)) * 3 + j) * nv + v];
-            M->guf[((e * nf + f * nfp + m) * 3 + j) * nv + v] = s;
+              s += l[jj] * M->gu[((uo + line_pt(M, n, f / 2, m, jj)) * 3 + j) * nv + v];
+            M->guf[((fo + f * nfp + m) * 3 + j) * nv + v] = s;
           }
     }
   }
@@ -769,6 +958,35 @@ static void interior_flux(const orc_mesh *M, long aL, long aR, double *Fn) {
   vis_normal(M, uL, gL, n, FvL, 0);
   vis_normal(M, uR, gR, n, FvR, 0);
   for (int v = 0; v < nv; ++v) Fn[v] = FI[v] - 0.5 * (FvL[v] + FvR[v]);
+}
+
+/* Transformed common normal flux A F*.n at the high-side point mA of a mortar
+ * face.  The low side enters through the interpolants of its trace and of its
+ * half viscous normal flux F_v(u, grad u).n / 2 (with its own normal). */
+static void mortar_flux_high(const orc_mesh *M, const orc_mortar *R, int mA, double *T) {
+  int nv = M->nv;
+  long a = M->fo[R->eA] + R->fA * el_nfp(M, R->eA) + mA;
+  int nfpB = el_nfp(M, R->eB);
+  long b0 = M->fo[R->eB] + R->fB * nfpB;
+  const double *uL = &M->uf[a * nv];
+  const double *n = &M->fnv[a * 3];
+  double uR[5], gL[3][5], FI[5], FvL[5], PB[MAXN * MAXN][5];
+  for (int v = 0; v < nv; ++v) uR[v] = mortar_up(M, R, mA, &M->uf[b0 * nv + v], nv);
+  for (int j = 0; j < 3; ++j)
+    for (int v = 0; v < nv; ++v) gL[j][v] = M->guf[(a * 3 + j) * nv + v];
+  for (int m = 0; m < nfpB; ++m) {
+    double gB[3][5], Fv[5];
+    for (int j = 0; j < 3; ++j)
+      for (int v = 0; v < nv; ++v) gB[j][v] = M->guf[((b0 + m) * 3 + j) * nv + v];
+    vis_normal(M, &M->uf[(b0 + m) * nv], gB, &M->fnv[(b0 + m) * 3], Fv, 0);
+    for (int v = 0; v < nv; ++v) PB[m][v] = 0.5 * Fv[v];
+  }
+  rusanov(M, uL, uR, n, FI);
+  vis_normal(M, uL, gL, n, FvL, 0);
+  for (int v = 0; v < nv; ++v) {
+    double pb = mortar_up(M, R, mA, &PB[0][v], 5);
+    T[v] = M->fA[a] * (FI[v] - 0.5 * FvL[v] + pb);
+  }
 }
 
 static void boundary_flux(const orc_mesh *M, long a, long kind, double *Fn) {
@@ -798,19 +1016,22 @@ static void boundary_flux(const orc_mesh *M, long a, long kind, double *Fn) {
 
 /* transformed flux at solution points, corrected divergence, R = -div/|J| */
 static void pass_divergence(orc_mesh *M, const double *u, double *R) {
-  int nf = M->nf, nv = M->nv, nfp = M->nfp, n = M->n, nu = M->nu, d = M->dim;
+  int nv = M->nv, d = M->dim;
 #pragma omp parallel for
   for (long e = 0; e < M->E; ++e) {
+    const orc_basis1d *B = &M->bas[M->ord[e]];
+    int n = B->n, nu = el_nu(M, e), nfp = el_nfp(M, e);
+    long uo = M->uo[e], fo = M->fo[e];
     double Ft[MAXN * MAXN * MAXN][3][5];
     double dlt[6 * MAXN * MAXN][5];
     for (int i = 0; i < nu; ++i) {
-      const double *ui = &u[(e * nu + i) * nv];
+      const double *ui = &u[(uo + i) * nv];
       double g[3][5], FI[3][5], FV[3][5];
       for (int j = 0; j < 3; ++j)
-        for (int v = 0; v < nv; ++v) g[j][v] = j < d ? M->gu[((e * nu + i) * 3 + j) * nv + v] : 0.0;
+        for (int v = 0; v < nv; ++v) g[j][v] = j < d ? M->gu[((uo + i) * 3 + j) * nv + v] : 0.0;
       flux_inv(M, ui, FI);
       flux_vis(M, ui, g, FV, 0);
-      const double *S = &M->S[(e * nu + i) * 9];
+      const double *S = &M->S[(uo + i) * 9];
       for (int k = 0; k < d; ++k)
         for (int v = 0; v < nv; ++v) {
           double s = 0.0;
@@ -821,48 +1042,63 @@ static void pass_divergence(orc_mesh *M, const double *u, double *R) {
     for (int f = 0; f < 2 * d; ++f) {
       int k = f / 2;
       double sg = (f % 2) ? 1.0 : -1.0;
-      const double *l = (f % 2) ? M->lp : M->lm;
+      const double *l = (f % 2) ? B->lp : B->lm;
       for (int m = 0; m < nfp; ++m) {
         int qq = f * nfp + m;
-        long a = e * nf + qq, b = M->nbr[a];
-        double Fn[5];
+        long a = fo + qq, b = M->nbr[a];
+        double T[5];
         if (b >= 0) {
+          double Fn[5];
           if (a < b) {
             interior_flux(M, a, b, Fn);
           } else { /* the partner is the L side; its normal is opposite */
             interior_flux(M, b, a, Fn);
             for (int v = 0; v < nv; ++v) Fn[v] = -Fn[v];
           }
+          for (int v = 0; v < nv; ++v) T[v] = M->fA[a] * Fn[v];
+        } else if (b <= -MORTAR0) {
+          const orc_mortar *Rm = mortar_of(M, b);
+          if (e == Rm->eA && f == Rm->fA) {
+            mortar_flux_high(M, Rm, m, T);
+          } else {
+            /* the low side takes minus the projection of the high side's flux */
+            double TH[MAXN * MAXN][5];
+            int nfpA = el_nfp(M, Rm->eA);
+            for (int j = 0; j < nfpA; ++j) mortar_flux_high(M, Rm, j, TH[j]);
+            for (int v = 0; v < nv; ++v) T[v] = -mortar_down(M, Rm, m, &TH[0][v], 5);
+          }
         } else {
+          double Fn[5];
           boundary_flux(M, a, -b, Fn);
+          for (int v = 0; v < nv; ++v) T[v] = M->fA[a] * Fn[v];
         }
         for (int v = 0; v < nv; ++v) {
           double fd = 0.0;
-          for (int j = 0; j < n; ++j) fd += l[j] * Ft[line_pt(M, k, m, j)][k][v];
-          dlt[qq][v] = M->fA[a] * Fn[v] - sg * fd;
+          for (int j = 0; j < n; ++j) fd += l[j] * Ft[line_pt(M, n, k, m, j)][k][v];
+          dlt[qq][v] = T[v] - sg * fd;
         }
       }
     }
     for (int i = 0; i < nu; ++i) {
-      double J = M->detJ[e * nu + i];
+      double J = M->detJ[uo + i];
       for (int v = 0; v < nv; ++v) {
         double div = 0.0;
         for (int k = 0; k < d; ++k) {
           int ik, m;
-          pt_line(M, i, k, &ik, &m);
+          pt_line(M, n, i, k, &ik, &m);
           double s = 0.0;
-          for (int j = 0; j < n; ++j) s += M->D[ik][j] * Ft[line_pt(M, k, m, j)][k][v];
-          s += dlt[(2 * k + 1) * nfp + m][v] * M->gRd[ik] - dlt[(2 * k) * nfp + m][v] * M->gLd[ik];
+          for (int j = 0; j < n; ++j) s += B->D[ik][j] * Ft[line_pt(M, n, k, m, j)][k][v];
+          s += dlt[(2 * k + 1) * nfp + m][v] * B->gRd[ik] - dlt[(2 * k) * nfp + m][v] * B->gLd[ik];
           div += s;
         }
-        R[(e * nu + i) * nv + v] = -div / J;
+        R[(uo + i) * nv + v] = -div / J;
       }
     }
   }
 }
 
 int orc_residual(orc_mesh *M, const double *u, double *R) {
-  long N = M->E * M->nu * M->nv;
+  long N = M->NU * M->nv;
   if (M->mock) {
     for (long i = 0; i < N; ++i) R[i] = M->mock_lambda * u[i];
     return 0;
@@ -873,15 +1109,25 @@ int orc_residual(orc_mesh *M, const double *u, double *R) {
   return 0;
 }
 
+/* corrected physical gradient of u at the solution points, [NU][3][nv] */
+int orc_gradient(orc_mesh *M, const double *u, double *g) {
+  pass_interp(M, u);
+  pass_gradient(M, u);
+  memcpy(g, M->gu, M->NU * 3 * M->nv * sizeof(double));
+  return 0;
+}
+
 /* wall force F = sum over wall flux points of W A (p n - tau . n) */
 int orc_forces(orc_mesh *M, const double *u, double *F) {
   pass_interp(M, u);
   pass_gradient(M, u);
-  int nf = M->nf, nv = M->nv, d = M->dim;
+  int nv = M->nv, d = M->dim;
   F[0] = F[1] = F[2] = 0.0;
-  for (long e = 0; e < M->E; ++e)
+  for (long e = 0; e < M->E; ++e) {
+    const orc_basis1d *B = &M->bas[M->ord[e]];
+    int nf = el_nf(M, e), nfp = el_nfp(M, e);
     for (int qq = 0; qq < nf; ++qq) {
-      long a = e * nf + qq;
+      long a = M->fo[e] + qq;
       if (M->nbr[a] != -BC_WALL) continue;
       const double *uL = &M->uf[a * nv];
       const double *nn = &M->fnv[a * 3];
@@ -890,20 +1136,21 @@ int orc_forces(orc_mesh *M, const double *u, double *F) {
       for (int j = 0; j < 3; ++j)
         for (int vv = 0; vv < nv; ++vv) g[j][vv] = M->guf[(a * 3 + j) * nv + vv];
       flux_vis(M, uL, g, Fv, 0);
-      double wA = M->fw[qq] * M->fA[a];
+      double wA = face_weight(M, B, qq % nfp) * M->fA[a];
       for (int i = 0; i < d; ++i) {
         double tn = 0.0;
         for (int j = 0; j < d; ++j) tn += Fv[j][1 + i] * nn[j]; /* tau_ij n_j */
         F[i] += wA * (p * nn[i] - tn);
       }
     }
+  }
   return 0;
 }
 
 /* classic RK4 steps; if Fhist is non-NULL the wall force after each step is
  * stored in Fhist[step*3 .. step*3+2] */
 int orc_rk4(orc_mesh *M, double *u, double dt, long nsteps, double *Fhist) {
-  long N = M->E * M->nu * M->nv;
+  long N = M->NU * M->nv;
   double *k = malloc(N * sizeof(double)), *acc = malloc(N * sizeof(double)),
          *us = malloc(N * sizeof(double));
   const double c[4] = {0.0, 0.5, 0.5, 1.0}, b[4] = {1.0, 2.0, 2.0, 1.0};
@@ -929,20 +1176,18 @@ int orc_rk4(orc_mesh *M, double *u, double dt, long nsteps, double *Fhist) {
 /* ------------------------------------------------------------------ */
 
 void orc_sizes(const orc_mesh *M, long *out) {
-  out[0] = M->dim; out[1] = M->order; out[2] = M->nu; out[3] = M->nf; out[4] = M->nv;
-  out[5] = M->E; out[6] = M->nfp;
+  int n = M->order + 1;
+  out[0] = M->dim; out[1] = M->order; out[2] = M->dim == 2 ? n * n : n * n * n;
+  out[3] = 2 * M->dim * (M->dim == 2 ? n : n * n); out[4] = M->nv; out[5] = M->E;
+  out[6] = M->dim == 2 ? n : n * n; out[7] = M->NU; out[8] = M->NF; out[9] = M->nmortar;
 }
-void orc_neighbours(const orc_mesh *M, long *out) { memcpy(out, M->nbr, M->E * M->nf * sizeof(long)); }
-void orc_solution_points(const orc_mesh *M, double *xyz) {
-  memcpy(xyz, M->xu, M->E * M->nu * 3 * sizeof(double));
-}
-void orc_flux_points(const orc_mesh *M, double *xyz) {
-  memcpy(xyz, M->fxyz, M->E * M->nf * 3 * sizeof(double));
-}
+void orc_neighbours(const orc_mesh *M, long *out) { memcpy(out, M->nbr, M->NF * sizeof(long)); }
+void orc_solution_points(const orc_mesh *M, double *xyz) { memcpy(xyz, M->xu, M->NU * 3 * sizeof(double)); }
+void orc_flux_points(const orc_mesh *M, double *xyz) { memcpy(xyz, M->fxyz, M->NF * 3 * sizeof(double)); }
 void orc_metrics(const orc_mesh *M, double *detJ, double *fA, double *fn) {
-  if (detJ) memcpy(detJ, M->detJ, M->E * M->nu * sizeof(double));
-  if (fA) memcpy(fA, M->fA, M->E * M->nf * sizeof(double));
-  if (fn) memcpy(fn, M->fnv, M->E * M->nf * 3 * sizeof(double));
+  if (detJ) memcpy(detJ, M->detJ, M->NU * sizeof(double));
+  if (fA) memcpy(fA, M->fA, M->NF * sizeof(double));
+  if (fn) memcpy(fn, M->fnv, M->NF * 3 * sizeof(double));
 }
 void orc_set_mock(orc_mesh *M, int on, double lambda) { M->mock = on; M->mock_lambda = lambda; }
 int orc_num_threads(void) {

@@ -44,6 +44,12 @@ def lib():
                                  ctypes.c_long, _lp, ctypes.c_int, _dp, ctypes.c_long, _lp,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp,
                                  ctypes.POINTER(ctypes.c_void_p)]
+        L.orc_create_mixed.restype = ctypes.c_int
+        L.orc_create_mixed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                       ctypes.c_long, _dp, ctypes.c_long, _lp, ctypes.c_int, _dp, ctypes.c_long,
+                                       _lp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.orc_gradient.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_residual.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.orc_forces.argtypes = [ctypes.c_void_p, _dp, _dp]
@@ -85,7 +91,10 @@ def num_threads():
 
 
 class OracleMesh:
-    """A mesh dict bound to the oracle: residual, RK4 and forces in FP64."""
+    """A mesh dict bound to the oracle: residual, RK4 and forces in FP64.
+
+    A mesh with ``orders`` (one order per element) has a ragged state: arrays are
+    [NU][nv] with element e's solution points contiguous, in element order."""
 
     def __init__(self, mesh):
         L = lib()
@@ -97,19 +106,23 @@ class OracleMesh:
         per = np.ascontiguousarray(mesh.get("periodic", np.zeros((0, self.dim))), dtype=np.float64)
         bf = np.ascontiguousarray(mesh.get("bfaces", np.zeros((0, 3))), dtype=np.int64)
         fs = np.ascontiguousarray(mesh.get("freestream", np.array([1.0, 0, 0, 0, 1.0])), dtype=np.float64)
-        self._keep = (nodes, en, per, bf, fs)
+        self.mixed = mesh.get("orders") is not None
+        orders = np.ascontiguousarray(mesh["orders"], dtype=np.int32) if self.mixed else None
+        self._keep = (nodes, en, per, bf, fs, orders)
         h = ctypes.c_void_p()
-        rc = L.orc_create(self.dim, self.order, int(mesh["q"]), nodes.shape[0], _d(nodes),
-                          en.shape[0], _l(en), per.shape[0], _d(per) if per.size else None,
-                          bf.shape[0], _l(bf) if bf.size else None,
-                          float(mesh.get("gamma", 1.4)), float(mesh.get("prandtl", 0.72)),
-                          float(mesh.get("mu", 0.0)), _d(fs), ctypes.byref(h))
+        rc = L.orc_create_mixed(self.dim, self.order,
+                                orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if self.mixed else None,
+                                int(mesh["q"]), nodes.shape[0], _d(nodes),
+                                en.shape[0], _l(en), per.shape[0], _d(per) if per.size else None,
+                                bf.shape[0], _l(bf) if bf.size else None,
+                                float(mesh.get("gamma", 1.4)), float(mesh.get("prandtl", 0.72)),
+                                float(mesh.get("mu", 0.0)), _d(fs), ctypes.byref(h))
         if rc != 0:
             raise ValueError(f"oracle rejected the mesh (code {rc})")
         self.h = h
-        sz = np.zeros(7, dtype=np.int64)
+        sz = np.zeros(10, dtype=np.int64)
         L.orc_sizes(h, _l(sz))
-        _, _, self.nu, self.nf, self.nv, self.E, self.nfp = (int(v) for v in sz)
+        _, _, self.nu, self.nf, self.nv, self.E, self.nfp, self.NU, self.NF, self.n_mortar = (int(v) for v in sz)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -118,29 +131,39 @@ class OracleMesh:
 
     @property
     def shape(self):
-        return (self.E, self.nu, self.nv)
+        return (self.NU, self.nv) if self.mixed else (self.E, self.nu, self.nv)
+
+    def _pts(self, per_elem, total):
+        return (total,) if self.mixed else (self.E, per_elem)
 
     def solution_points(self):
-        x = np.zeros((self.E, self.nu, 3))
+        x = np.zeros(self._pts(self.nu, self.NU) + (3,))
         lib().orc_solution_points(self.h, _d(x))
         return x
 
     def flux_points(self):
-        x = np.zeros((self.E, self.nf, 3))
+        x = np.zeros(self._pts(self.nf, self.NF) + (3,))
         lib().orc_flux_points(self.h, _d(x))
         return x
 
     def neighbours(self):
-        nb = np.zeros((self.E, self.nf), dtype=np.int64)
+        nb = np.zeros(self._pts(self.nf, self.NF), dtype=np.int64)
         lib().orc_neighbours(self.h, _l(nb))
         return nb
 
     def metrics(self):
-        detJ = np.zeros((self.E, self.nu))
-        fA = np.zeros((self.E, self.nf))
-        fn = np.zeros((self.E, self.nf, 3))
+        detJ = np.zeros(self._pts(self.nu, self.NU))
+        fA = np.zeros(self._pts(self.nf, self.NF))
+        fn = np.zeros(self._pts(self.nf, self.NF) + (3,))
         lib().orc_metrics(self.h, _d(detJ), _d(fA), _d(fn))
         return detJ, fA, fn
+
+    def gradient(self, u):
+        """Corrected physical gradient at the solution points: [..., 3, nv]."""
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(self.shape)
+        g = np.zeros(self.shape[:-1] + (3, self.nv))
+        lib().orc_gradient(self.h, _d(u), _d(g))
+        return g
 
     def initial_state(self):
         xyz = self.solution_points().reshape(-1, 3)

@@ -172,6 +172,20 @@ def naca_ogrid(m, pc, t, ni, nj, nk, span=0.2, radius=20.0, ratio=1.1, q=2, orde
                 periodic=np.array([[0.0, 0.0, span]]), bfaces=bfaces)
 
 
+def ring_orders(ni, nj, nk, bands):
+    """Per-element orders of a ``naca_ogrid`` mesh by radial layer j: ``bands`` is a
+    list of (first layer beyond the band, order), e.g. ((16, 3), (32, 2), (48, 1)) gives
+    P3 in layers 0-15, P2 in 16-31 and P1 beyond (element (i, j, k) is
+    (k nj + j) ni + i)."""
+    j = (np.arange(ni * nj * nk) // ni) % nj
+    out = np.full(j.shape, bands[-1][1], dtype=np.int32)
+    lo = 0
+    for hi, p in bands:
+        out[(j >= lo) & (j < hi)] = p
+        lo = hi
+    return out
+
+
 def min_width(mesh, order=None):
     """Smallest element width across a pair of opposite faces, 2|J| / |grad_x xi_k|^-1,
     over the Gauss-Legendre points of the mesh's order (captures sliver elements)."""
