@@ -95,7 +95,26 @@ typedef struct {
   fr_alloc_fn alloc;       /* optional device allocator (e.g. a framework's caching allocator) */
   fr_free_fn free;
   void *alloc_ctx;
+  const int32_t *elem_order; /* [n_elems] per-element order 1..4, or NULL: `order` everywhere.
+                              * See "Variable order" below. */
 } fr_mesh_desc;
+
+/* Variable order (Section 3.1: the paper lowers the solution order toward the
+ * far-field boundaries so that acoustic waves leave without reflecting).
+ * With elem_order set, element e carries order elem_order[e] and `order`
+ * is ignored.  A face shared by elements of different orders carries a
+ * mortar: the lower-order element's trace and half viscous normal flux
+ * enter the higher-order side as their interpolants at its flux points,
+ * where the common flux is formed; the lower-order side takes the L2
+ * projection of the higher-order side's transformed common flux onto its
+ * own face polynomials (exact in the higher order's face quadrature), so
+ * the face integrals of both sides agree and the scheme stays
+ * conservative.  The state of such a mesh is ragged: [sum of n_u(e)][nv],
+ * element e's solution points contiguous, in element order (fr_set_state,
+ * fr_get_state, fr_residual, fr_solution_points).  Variable-order meshes run
+ * the fused two-launch stage only; they are built one at a time (not in a
+ * batch), and fr_neighbours, fr_state_device, fr_profile_kernels and probes
+ * report FR_E_UNSUPPORTED for them. */
 
 /* Build a solver for one mesh: connectivity (faces matched by node ids,
  * periodic faces by the listed translations, flux points by position),
@@ -128,6 +147,10 @@ fr_status fr_solution_points(const fr_mesh *m, double *xyz);
  * interior or periodic face, -kind for a boundary face (element indices
  * are positions in the concatenated arrays). */
 fr_status fr_neighbours(const fr_mesh *m, int64_t *nbr);
+
+/* Solution points of the mesh: n_elems * n_u, or the sum of n_u(e) over the
+ * elements of a variable-order mesh (the length of its ragged state). */
+fr_status fr_mesh_points(const fr_mesh *m, int64_t *n_points);
 
 /* Host-only variant of the neighbour table for a single descriptor: runs
  * the connectivity and geometry checks without touching a device.  nbr is

@@ -37,6 +37,7 @@ class MeshDesc(ctypes.Structure):
         ("dt", ctypes.c_double),
         ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
         ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
+        ("elem_order", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -91,6 +92,7 @@ SIGNATURES = {
     "fr_pool_collect": (ctypes.c_int, [ctypes.c_void_p, _i64p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "fr_pool_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp, _dp]),
     "fr_pool_usage": (ctypes.c_int, [ctypes.c_void_p, _i64p]),
+    "fr_mesh_points": (ctypes.c_int, [ctypes.c_void_p, _i64p]),
     "fr_pool_admit_sampled": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MeshDesc), _dp,
                                              ctypes.POINTER(PoolSurface), _i64p]),
     "fr_pool_pressure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _i64p, _dp]),

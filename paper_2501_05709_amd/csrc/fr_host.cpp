@@ -335,7 +335,11 @@ struct KeyHash {
   }
 };
 
-HostMesh build_host_mesh(const fr_mesh_desc &d) {
+// boundary-list kind of a face shared with an element of another order, as the
+// order groups of a variable-order mesh list them (never in a caller's descriptor)
+constexpr int64_t KIND_MORTAR = BC_MORTAR;
+
+HostMesh build_host_mesh(const fr_mesh_desc &d, bool allow_mortar = false) {
   const int dim = d.dim, order = d.order, q = d.geom_order;
   RefElem R(dim, order);
   Basis1D b(order);
@@ -425,7 +429,8 @@ HostMesh build_host_mesh(const fr_mesh_desc &d) {
   }
   for (int64_t i = 0; i < d.n_bfaces; ++i) {
     const int64_t e = d.bfaces[3 * i], f = d.bfaces[3 * i + 1], kind = d.bfaces[3 * i + 2];
-    if (e < 0 || e >= E || f < 0 || f >= nfe || (kind != FR_BC_WALL && kind != FR_BC_FARFIELD))
+    if (e < 0 || e >= E || f < 0 || f >= nfe ||
+        (kind != FR_BC_WALL && kind != FR_BC_FARFIELD && !(allow_mortar && kind == KIND_MORTAR)))
       fail(FR_E_ARG, "invalid boundary face entry");
     if (done[e * nfe + f]) fail(FR_E_MESH, "boundary face is also an interior face");
     done[e * nfe + f] = 2;
@@ -560,6 +565,24 @@ struct fr_mesh {
   bool state_set = false;
   hipGraphExec_t graph_first = nullptr, graph_rest = nullptr;
 
+  // variable order: one uniform-order solver per order present (ascending order),
+  // all on this handle's stream and sharing its mortar buffers (DevArrays MU, MX, MT)
+  std::vector<std::unique_ptr<fr_mesh>> groups;
+  std::vector<int> eorder;              // [E] element order
+  std::vector<int> egroup;              // [E] group of the element
+  std::vector<int64_t> elocal;          // [E] index of the element within its group
+  std::vector<int64_t> uoff;            // [E + 1] first solution point of the element
+  int64_t n_mortar = 0;                 // mortar points
+  // gather rows: [0, rA) higher-order points (partner = lower order, interpolation);
+  // [rA, rB) lower-order points (partner = higher order, projection); then, per
+  // group g, rows [rC[g], rC[g + 1]) of lower-order points whose higher-order side is
+  // g, reading the higher side's transformed flux MT (projection, sign -1)
+  int64_t rA = 0, rB = 0;
+  std::vector<int64_t> rC;
+  int *row_out = nullptr, *row_off = nullptr, *ent_grp = nullptr, *ent_code = nullptr;
+  double *ent_w = nullptr;
+  bool mixed() const { return !groups.empty(); }
+
   size_t real_size() const { return prec == FR_FP32 ? 4 : 8; }
 
   void *dalloc(size_t n) {
@@ -584,6 +607,7 @@ struct fr_mesh {
   ~fr_mesh() {
     if (graph_first) hipGraphExecDestroy(graph_first);
     if (graph_rest) hipGraphExecDestroy(graph_rest);
+    groups.clear();  // they run on this handle's stream
     if (stream) hipStreamSynchronize(stream);
     for (void *p : allocations) {
       if (dfree)
@@ -622,7 +646,13 @@ constexpr unsigned FUSED = 1u;  // variant-mask bit 0: two fused launches per st
 
 void drop_graphs(fr_mesh *M);
 
-void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
+// Mortar points of one order group: for (element, face) of the group, the first
+// mortar point of the face and the side (1: the lower-order element)
+struct MortarMap {
+  std::unordered_map<int64_t, std::pair<int64_t, int>> face;  // key element * 2 dim + face
+};
+
+void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap *mm = nullptr) {
   const fr_mesh_desc &d0 = descs[0];
   M->dim = d0.dim;
   M->order = d0.order;
@@ -649,7 +679,7 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
   hm.reserve(nd);
   int64_t e0 = 0, blk0 = 0, w0 = 0;
   for (int i = 0; i < nd; ++i) {
-    hm.push_back(build_host_mesh(descs[i]));
+    hm.push_back(build_host_mesh(descs[i], mm != nullptr));
     DesignInfo di;
     di.e0 = e0;
     di.E = descs[i].n_elems;
@@ -737,6 +767,11 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
           auto bs = dev_slot(gp);
           code = int(lay(bs.first, qp, 0, bs.second, NFPAD, 1));
           M->nbr_canon[size_t(g) * nf + qq] = gp * nf + qp;
+        } else if (-p == KIND_MORTAR) {
+          const auto &fs = mm->face.at(e * 2 * dim + qq / D.nfp);
+          const int64_t idx = ((fs.first + qq % D.nfp) << 1) | fs.second;
+          code = -int(BC_MORTAR | (idx << 2));
+          M->nbr_canon[size_t(g) * nf + qq] = p;
         } else {
           const int kind = int(-p);
           code = kind == FR_BC_WALL ? -int(kind | (widx++ << 2)) : -kind;
@@ -841,6 +876,279 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
   hip_check(hipStreamSynchronize(M->stream), "mesh upload");
 }
 
+// ---------------------------------------------------------------------------
+// variable order: order groups coupled by mortar faces
+// ---------------------------------------------------------------------------
+
+// Legendre polynomial P_k(t)
+double legendre(int k, double t) {
+  double P, Pm1;
+  Basis1D::legendre_pair(k, t, P, Pm1);
+  return P;
+}
+
+// A face shared by elements of different orders, seen from its higher-order
+// element H: the orientation O maps H's face coordinates to L's, t = O s
+struct MortarFace {
+  int64_t eH, eL;  // canonical elements
+  int fH, fL;
+  int O[2][2];
+  int64_t baseH = 0, baseL = 0;  // first mortar point of each side
+};
+
+void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
+  const int dim = d.dim, nfe = 2 * dim;
+  const int64_t E = d.n_elems;
+  M->dim = dim;
+  M->prec = d.precision;
+  M->device = d.device;
+  M->gamma = d.gamma;
+  M->prandtl = d.prandtl;
+  M->mu = d.mu;
+  M->alloc = d.alloc;
+  M->dfree = d.free;
+  M->alloc_ctx = d.alloc_ctx;
+  M->E = E;
+  hip_check(hipSetDevice(d.device), "hipSetDevice");
+  if (d.stream) {
+    M->stream = (hipStream_t)d.stream;
+  } else {
+    hip_check(hipStreamCreateWithFlags(&M->stream, hipStreamNonBlocking), "hipStreamCreate");
+    M->own_stream = true;
+  }
+  // orders present
+  M->eorder.assign(d.elem_order, d.elem_order + E);
+  std::vector<int> present;
+  for (int p : M->eorder) {
+    if (!kernels_available(d.precision, dim, p)) fail(FR_E_UNSUPPORTED, "element order not compiled in (1..4)");
+    if (std::find(present.begin(), present.end(), p) == present.end()) present.push_back(p);
+  }
+  std::sort(present.begin(), present.end());
+  M->order = present.back();
+  M->dm = Dims(dim, M->order);
+  // faces and their orientation from the whole mesh at order 1 (2 or 2 x 2 face points
+  // at +-1/sqrt(3) along each face axis, matched by position)
+  fr_mesh_desc d1 = d;
+  d1.order = 1;
+  d1.elem_order = nullptr;
+  const HostMesh H1 = build_host_mesh(d1);
+  const int nfp1 = dim == 2 ? 2 : 4, nf1 = nfe * nfp1;
+  const double x1 = 1.0 / std::sqrt(3.0);
+  auto coords1 = [&](int m, double s[2]) {
+    s[0] = (m & 1) ? x1 : -x1;
+    s[1] = dim == 3 ? (((m >> 1) & 1) ? x1 : -x1) : 0.0;
+  };
+  M->egroup.resize(size_t(E));
+  M->elocal.resize(size_t(E));
+  M->uoff.assign(size_t(E) + 1, 0);
+  std::vector<int64_t> gcount(present.size(), 0);
+  for (int64_t e = 0; e < E; ++e) {
+    const int g = int(std::find(present.begin(), present.end(), M->eorder[size_t(e)]) - present.begin());
+    M->egroup[size_t(e)] = g;
+    M->elocal[size_t(e)] = gcount[size_t(g)]++;
+    const int n = M->eorder[size_t(e)] + 1;
+    M->uoff[size_t(e) + 1] = M->uoff[size_t(e)] + (dim == 2 ? n * n : n * n * n);
+  }
+  std::vector<MortarFace> faces;
+  for (int64_t e = 0; e < E; ++e)
+    for (int f = 0; f < nfe; ++f) {
+      const int64_t p = H1.nbr[size_t(e) * nf1 + f * nfp1];
+      if (p < 0) continue;
+      const int64_t ep = p / nf1;
+      const int fp = int((p % nf1) / nfp1);
+      const int oe = M->eorder[size_t(e)], op = M->eorder[size_t(ep)];
+      if (oe <= op) continue;  // each mortar face once, from its higher-order side
+      MortarFace mf;
+      mf.eH = e; mf.fH = f; mf.eL = ep; mf.fL = fp;
+      // O from the images of face points 1 and 2 (steps along each face axis) of point 0
+      double t[3][2];
+      for (int m = 0; m < (dim == 2 ? 2 : 3); ++m) {
+        const int64_t q = H1.nbr[size_t(e) * nf1 + f * nfp1 + m];
+        coords1(int(q % nf1) % nfp1, t[m]);
+      }
+      for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) mf.O[r][c] = 0;
+      for (int r = 0; r < (dim == 2 ? 1 : 2); ++r) {
+        mf.O[r][0] = int(std::lround((t[1][r] - t[0][r]) / (2.0 * x1)));
+        if (dim == 3) mf.O[r][1] = int(std::lround((t[2][r] - t[0][r]) / (2.0 * x1)));
+      }
+      faces.push_back(mf);
+    }
+  // mortar points: each face's higher-order points, then its lower-order points
+  std::vector<MortarMap> maps(present.size());
+  int64_t np = 0;
+  auto nfp_of = [&](int p) { return dim == 2 ? p + 1 : (p + 1) * (p + 1); };
+  for (auto &mf : faces) {
+    mf.baseH = np;
+    np += nfp_of(M->eorder[size_t(mf.eH)]);
+    mf.baseL = np;
+    np += nfp_of(M->eorder[size_t(mf.eL)]);
+    maps[size_t(M->egroup[size_t(mf.eH)])].face[M->elocal[size_t(mf.eH)] * nfe + mf.fH] = {mf.baseH, 0};
+    maps[size_t(M->egroup[size_t(mf.eL)])].face[M->elocal[size_t(mf.eL)] * nfe + mf.fL] = {mf.baseL, 1};
+  }
+  M->n_mortar = np;
+  if ((np << 3) >= (int64_t(1) << 31)) fail(FR_E_UNSUPPORTED, "too many mortar points for 32-bit codes");
+  // the order groups: sub-meshes whose faces to other orders are listed as mortar faces
+  for (size_t g = 0; g < present.size(); ++g) {
+    std::vector<int64_t> en, bf;
+    const int na = d.geom_order + 1, nn = dim == 2 ? na * na : na * na * na;
+    for (int64_t e = 0; e < E; ++e)
+      if (M->egroup[size_t(e)] == int(g)) en.insert(en.end(), d.elem_nodes + e * nn, d.elem_nodes + (e + 1) * nn);
+    for (int64_t i = 0; i < d.n_bfaces; ++i) {
+      const int64_t e = d.bfaces[3 * i];
+      if (e < 0 || e >= E) fail(FR_E_ARG, "invalid boundary face entry");
+      if (M->egroup[size_t(e)] != int(g)) continue;
+      bf.insert(bf.end(), {M->elocal[size_t(e)], d.bfaces[3 * i + 1], d.bfaces[3 * i + 2]});
+    }
+    for (const auto &kv : maps[g].face) bf.insert(bf.end(), {kv.first / nfe, kv.first % nfe, KIND_MORTAR});
+    fr_mesh_desc dg = d;
+    dg.order = present[g];
+    dg.elem_order = nullptr;
+    dg.n_elems = gcount[g];
+    dg.elem_nodes = en.data();
+    dg.n_bfaces = int64_t(bf.size() / 3);
+    dg.bfaces = bf.empty() ? nullptr : bf.data();
+    dg.stream = M->stream;
+    std::unique_ptr<fr_mesh> G(new fr_mesh());
+    build_solver(G.get(), &dg, 1, &maps[g]);
+    G->cfg.variant_mask = FUSED | (1u << K_INTERP);
+    M->groups.push_back(std::move(G));
+  }
+  for (auto &G : M->groups) {
+    M->nblk += G->nblk;
+    M->nwall += G->nwall;
+  }
+  M->designs.push_back(M->groups[0]->designs[0]);
+  M->designs[0].e0 = 0;
+  M->designs[0].E = E;
+  // gather tables
+  auto code_of = [&](int64_t e, int f, int m) {  // partner code of a face point in its group
+    const fr_mesh &G = *M->groups[size_t(M->egroup[size_t(e)])];
+    const int64_t le = M->elocal[size_t(e)];
+    const int q = f * G.dm.nfp + m;
+    return int(lay(le / EB, q, 0, int(le % EB), G.dm.nfpad, 1));
+  };
+  std::vector<int> row_out, row_off{0}, ent_grp, ent_code;
+  std::vector<double> ent_w;
+  struct LowRow { int g; int out; std::vector<int> code; std::vector<double> w; };
+  std::vector<LowRow> low;
+  std::vector<std::vector<int>> rowsB_code(0);
+  // face geometry helpers on each side
+  for (int pass = 0; pass < 2; ++pass) {
+    for (const auto &mf : faces) {
+      const int pH = M->eorder[size_t(mf.eH)], pL = M->eorder[size_t(mf.eL)];
+      const Basis1D bH(pH), bL(pL);
+      const int nH = pH + 1, nL = pL + 1, nfpH = nfp_of(pH), nfpL = nfp_of(pL);
+      const int gH = M->egroup[size_t(mf.eH)], gL = M->egroup[size_t(mf.eL)];
+      // L-face coordinates of every H point
+      std::vector<std::array<double, 2>> tH(static_cast<size_t>(nfpH));
+      for (int j = 0; j < nfpH; ++j) {
+        const double sj[2] = {bH.x[j % nH], dim == 3 ? bH.x[j / nH] : 0.0};
+        for (int r = 0; r < 2; ++r) tH[size_t(j)][size_t(r)] = mf.O[r][0] * sj[0] + mf.O[r][1] * sj[1];
+      }
+      if (pass == 0) {
+        // higher-order points: interpolants of the lower-order side's face data
+        for (int j = 0; j < nfpH; ++j) {
+          row_out.push_back(int(mf.baseH + j));
+          const auto l0 = bL.eval_all(tH[size_t(j)][0]);
+          const auto l1 = dim == 3 ? bL.eval_all(tH[size_t(j)][1]) : std::vector<double>(1, 1.0);
+          for (int i = 0; i < nfpL; ++i) {
+            ent_grp.push_back(gL);
+            ent_code.push_back(code_of(mf.eL, mf.fL, i));
+            ent_w.push_back(l0[size_t(i % nL)] * (dim == 3 ? l1[size_t(i / nL)] : 1.0));
+          }
+          row_off.push_back(int(ent_w.size()));
+        }
+        continue;
+      }
+      // lower-order points: L2 projection onto the lower order's face polynomials of
+      // the higher-order side's face data, integrated by the higher-order face quadrature
+      std::vector<double> P(size_t(nfpL) * nfpH, 0.0);
+      for (int i = 0; i < nfpL; ++i) {
+        const double ti[2] = {bL.x[i % nL], dim == 3 ? bL.x[i / nL] : 0.0};
+        for (int j = 0; j < nfpH; ++j) {
+          const double W = dim == 2 ? bH.w[j] : bH.w[j % nH] * bH.w[j / nH];
+          double acc = 0.0;
+          for (int k1 = 0; k1 <= (dim == 3 ? pL : 0); ++k1)
+            for (int k0 = 0; k0 <= pL; ++k0) {
+              double c = 0.5 * (2 * k0 + 1) * legendre(k0, ti[0]) * legendre(k0, tH[size_t(j)][0]);
+              if (dim == 3) c *= 0.5 * (2 * k1 + 1) * legendre(k1, ti[1]) * legendre(k1, tH[size_t(j)][1]);
+              acc += c;
+            }
+          P[size_t(i) * nfpH + j] = W * acc;
+        }
+      }
+      for (int i = 0; i < nfpL; ++i) {
+        row_out.push_back(int(mf.baseL + i));
+        LowRow lr{gH, int(mf.baseL + i), {}, {}};
+        for (int j = 0; j < nfpH; ++j) {
+          ent_grp.push_back(gH);
+          ent_code.push_back(code_of(mf.eH, mf.fH, j));
+          ent_w.push_back(P[size_t(i) * nfpH + j]);
+          lr.code.push_back(int(mf.baseH + j));
+          lr.w.push_back(P[size_t(i) * nfpH + j]);
+        }
+        row_off.push_back(int(ent_w.size()));
+        low.push_back(std::move(lr));
+      }
+    }
+    if (pass == 0) M->rA = int64_t(row_out.size());
+  }
+  M->rB = int64_t(row_out.size());
+  std::stable_sort(low.begin(), low.end(), [](const LowRow &a, const LowRow &b) { return a.g < b.g; });
+  M->rC.assign(present.size() + 1, M->rB);
+  for (size_t g = 0; g < present.size(); ++g) {
+    M->rC[g] = int64_t(row_out.size());
+    for (const auto &lr : low) {
+      if (lr.g != int(g)) continue;
+      row_out.push_back(lr.out);
+      for (size_t j = 0; j < lr.code.size(); ++j) {
+        ent_grp.push_back(-1);
+        ent_code.push_back(lr.code[j]);
+        ent_w.push_back(lr.w[j]);
+      }
+      row_off.push_back(int(ent_w.size()));
+    }
+  }
+  M->rC[present.size()] = int64_t(row_out.size());
+  if (ent_w.empty()) {  // no mortar face: keep the tables valid
+    ent_grp.push_back(0);
+    ent_code.push_back(0);
+    ent_w.push_back(0.0);
+    row_out.push_back(0);
+    row_off.push_back(1);
+  }
+  M->row_out = M->upload(row_out);
+  M->row_off = M->upload(row_off);
+  M->ent_grp = M->upload(ent_grp);
+  M->ent_code = M->upload(ent_code);
+  M->ent_w = M->upload(ent_w);
+  const size_t mb = size_t(std::max<int64_t>(np, 1)) * (dim + 2) * M->real_size();
+  M->a.MU = M->dalloc(mb);
+  M->a.MX = M->dalloc(mb);
+  M->a.MT = M->dalloc(mb);
+  for (auto &G : M->groups) {
+    G->a.MU = M->a.MU;
+    G->a.MX = M->a.MX;
+    G->a.MT = M->a.MT;
+  }
+  M->a.flag = (int *)M->dalloc(sizeof(int));
+  M->cfg = M->groups[0]->cfg;
+  M->cfg.variant_mask = FUSED | (1u << K_INTERP);
+  hip_check(hipStreamSynchronize(M->stream), "mesh upload");
+}
+
+// gather rows [r0, r1) from the groups' array `which` (0: traces UF, 1: half viscous
+// fluxes PV) or, for rows of the C range, from MT
+void gather(fr_mesh *M, int64_t r0, int64_t r1, int which, void *out, double sign) {
+  MortarSrc src{};
+  for (size_t g = 0; g < M->groups.size() && g < 8; ++g)
+    src.g[g] = which == 0 ? M->groups[g]->a.UF : M->groups[g]->a.PV;
+  hip_check(launch_mortar_gather(M->prec, M->dim + 2, r0, r1, M->row_out, M->row_off, M->ent_grp, M->ent_code,
+                                 M->ent_w, src, M->a.MT, out, sign, M->stream),
+            "mortar gather");
+}
+
 void profile_steps(fr_mesh *m, int64_t steps, double *ms, int64_t *launches);
 
 void drop_graphs(fr_mesh *M) {
@@ -853,8 +1161,31 @@ void lk(fr_mesh *M, int kernel, int stage, int mode, bool forces) {
   hip_check(launch_kernel(kernel, M->cfg, M->a, stage, mode, forces), "kernel launch");
 }
 
+// one RK4 stage (or the residual, mode MODE_RESID) of a variable-order mesh: the
+// other sides' traces at every mortar point, the first fused launch of every group,
+// the lower-order sides' half viscous fluxes at the higher-order points, then the
+// second launch group by group from the highest order down, each followed by the
+// projection of its transformed mortar fluxes onto the lower-order points
+void enqueue_stage_mixed(fr_mesh *M, int stage, int mode, bool forces) {
+  gather(M, 0, M->rB, 0, M->a.MU, 1.0);
+  for (auto &G : M->groups) {
+    const bool f = forces && G->nwall > 0;
+    lk(G.get(), K_STAGE_A, stage, 0, f);
+    if (f) hip_check(launch_force_reduce(G->cfg, G->a), "force reduce");
+  }
+  gather(M, 0, M->rA, 1, M->a.MX, 1.0);
+  for (size_t g = M->groups.size(); g-- > 0;) {
+    lk(M->groups[g].get(), K_STAGE_B, stage, mode, false);
+    gather(M, M->rC[g], M->rC[g + 1], 2, M->a.MX, -1.0);
+  }
+}
+
 // one RK4 step; force terms of the step's input state are reduced if `forces`
 void enqueue_step(fr_mesh *M, bool forces) {
+  if (M->mixed()) {
+    for (int s = 0; s < 4; ++s) enqueue_stage_mixed(M, s, s, forces && s == 0);
+    return;
+  }
   if (M->cfg.variant_mask & FUSED) {
     for (int s = 0; s < 4; ++s) {
       const bool f = forces && s == 0 && M->nwall > 0;
@@ -900,6 +1231,23 @@ void step_async(fr_mesh *M, int64_t n, bool clear_flag = true) {
   hip_check(hipSetDevice(M->device), "hipSetDevice");
   if (!M->graph_first) M->graph_first = capture_step(M, false);
   if (!M->graph_rest) M->graph_rest = capture_step(M, true);
+  if (M->mixed()) {
+    for (auto &G : M->groups) {
+      if (clear_flag) hip_check(launch_clear_flag(G->cfg, G->a), "clear flag");
+      lk(G.get(), K_INTERP, 0, 0, false);
+    }
+    for (int64_t s = 0; s < n; ++s)
+      hip_check(hipGraphLaunch(s == 0 ? M->graph_first : M->graph_rest, M->stream), "graph launch");
+    if (M->nwall > 0) {  // wall force of the final state
+      gather(M, 0, M->rB, 0, M->a.MU, 1.0);
+      for (auto &G : M->groups)
+        if (G->nwall > 0) {
+          lk(G.get(), K_STAGE_A, 0, 0, true);
+          hip_check(launch_force_reduce(G->cfg, G->a), "force reduce");
+        }
+    }
+    return;
+  }
   if (clear_flag) hip_check(launch_clear_flag(M->cfg, M->a), "clear flag");
   lk(M, K_INTERP, 0, 0, false);
   for (int64_t s = 0; s < n; ++s)
@@ -917,10 +1265,17 @@ void step_async(fr_mesh *M, int64_t n, bool clear_flag = true) {
 }
 
 void sync_check(fr_mesh *M) {
-  int flag = 0;
-  hip_check(hipMemcpyAsync(&flag, M->a.flag, sizeof(int), hipMemcpyDeviceToHost, M->stream), "flag copy");
+  std::vector<int> flags(std::max<size_t>(M->groups.size(), 1), 0);
+  if (M->mixed()) {
+    for (size_t g = 0; g < M->groups.size(); ++g)
+      hip_check(hipMemcpyAsync(&flags[g], M->groups[g]->a.flag, sizeof(int), hipMemcpyDeviceToHost, M->stream),
+                "flag copy");
+  } else {
+    hip_check(hipMemcpyAsync(&flags[0], M->a.flag, sizeof(int), hipMemcpyDeviceToHost, M->stream), "flag copy");
+  }
   hip_check(hipStreamSynchronize(M->stream), "stream sync");
-  if (flag) fail(FR_E_NONFINITE, "non-finite state after a step");
+  for (int f : flags)
+    if (f) fail(FR_E_NONFINITE, "non-finite state after a step");
 }
 
 }  // namespace
@@ -937,6 +1292,17 @@ fr_status fr_batch_create(const fr_mesh_desc *descs, int32_t n, fr_mesh **out) {
     if (!out) fail(FR_E_ARG, "null output");
     *out = nullptr;
     if (!descs || n <= 0) fail(FR_E_ARG, "no descriptors");
+    for (int i = 0; i < n; ++i)
+      if (descs[i].elem_order) {
+        if (n != 1) fail(FR_E_UNSUPPORTED, "variable-order meshes are built one at a time");
+        fr_mesh_desc d = descs[0];
+        d.order = 1;  // each element's own order is checked when the groups are built
+        validate_desc(&d);
+        std::unique_ptr<fr_mesh> M(new fr_mesh());
+        build_mixed(M.get(), descs[0]);
+        *out = M.release();
+        return;
+      }
     for (int i = 0; i < n; ++i) {
       validate_desc(&descs[i]);
       const auto &a = descs[0], &b = descs[i];
@@ -960,6 +1326,10 @@ fr_status fr_mesh_info(const fr_mesh *m, int64_t *info) {
     info[0] = m->dim; info[1] = m->order; info[2] = int64_t(m->designs.size()); info[3] = m->E;
     info[4] = m->dm.nu; info[5] = m->dm.nf; info[6] = m->dm.nv; info[7] = m->prec; info[8] = m->nblk;
     info[9] = int64_t(m->bytes);
+    if (m->mixed()) {  // ragged: no single point count per element
+      info[4] = info[5] = 0;
+      for (auto &G : m->groups) info[9] += int64_t(G->bytes);
+    }
   });
 }
 
@@ -974,13 +1344,30 @@ fr_status fr_design_range(const fr_mesh *m, int32_t design, int64_t *first, int6
 fr_status fr_solution_points(const fr_mesh *m, double *xyz) {
   return guarded([&] {
     if (!m || !xyz) fail(FR_E_ARG, "null argument");
+    if (m->mixed()) {
+      for (int64_t e = 0; e < m->E; ++e) {
+        const fr_mesh &G = *m->groups[size_t(m->egroup[size_t(e)])];
+        const size_t nu = size_t(G.dm.nu);
+        std::memcpy(xyz + m->uoff[size_t(e)] * 3, G.xu.data() + size_t(m->elocal[size_t(e)]) * nu * 3,
+                    nu * 3 * sizeof(double));
+      }
+      return;
+    }
     std::memcpy(xyz, m->xu.data(), m->xu.size() * sizeof(double));
+  });
+}
+
+fr_status fr_mesh_points(const fr_mesh *m, int64_t *n_points) {
+  return guarded([&] {
+    if (!m || !n_points) fail(FR_E_ARG, "null argument");
+    *n_points = m->mixed() ? m->uoff.back() : m->E * m->dm.nu;
   });
 }
 
 fr_status fr_neighbours(const fr_mesh *m, int64_t *nbr) {
   return guarded([&] {
     if (!m || !nbr) fail(FR_E_ARG, "null argument");
+    if (m->mixed()) fail(FR_E_UNSUPPORTED, "neighbour table of a variable-order mesh");
     std::memcpy(nbr, m->nbr_canon.data(), m->nbr_canon.size() * sizeof(int64_t));
   });
 }
@@ -988,6 +1375,7 @@ fr_status fr_neighbours(const fr_mesh *m, int64_t *nbr) {
 fr_status fr_connectivity(const fr_mesh_desc *desc, int64_t *nbr, double *xyz) {
   return guarded([&] {
     if (!nbr) fail(FR_E_ARG, "null argument");
+    if (desc && desc->elem_order) fail(FR_E_UNSUPPORTED, "neighbour table of a variable-order mesh");
     validate_desc(desc);
     HostMesh H = build_host_mesh(*desc);
     std::memcpy(nbr, H.nbr.data(), H.nbr.size() * sizeof(int64_t));
@@ -995,9 +1383,36 @@ fr_status fr_connectivity(const fr_mesh_desc *desc, int64_t *nbr, double *xyz) {
   });
 }
 
+// the part of a ragged canonical state held by group g, or back
+static void split_state(const fr_mesh *m, size_t g, const double *u, double *ug, bool to_group) {
+  const int nv = m->dim + 2;
+  const fr_mesh &G = *m->groups[g];
+  const size_t per = size_t(G.dm.nu) * nv;
+  for (int64_t e = 0; e < m->E; ++e) {
+    if (m->egroup[size_t(e)] != int(g)) continue;
+    double *a = ug + size_t(m->elocal[size_t(e)]) * per;
+    const double *b = u + size_t(m->uoff[size_t(e)]) * nv;
+    if (to_group)
+      std::memcpy(a, b, per * sizeof(double));
+    else
+      std::memcpy(const_cast<double *>(b), a, per * sizeof(double));
+  }
+}
+
 fr_status fr_set_state(fr_mesh *m, const double *u) {
   return guarded([&] {
     if (!m || !u) fail(FR_E_ARG, "null argument");
+    if (m->mixed()) {
+      for (size_t g = 0; g < m->groups.size(); ++g) {
+        fr_mesh &G = *m->groups[g];
+        std::vector<double> ug(size_t(G.E) * G.dm.nu * G.dm.nv);
+        split_state(m, g, u, ug.data(), true);
+        const fr_status st = fr_set_state(&G, ug.data());
+        if (st != FR_OK) fail(st, g_err);
+      }
+      m->state_set = true;
+      return;
+    }
     hip_check(hipSetDevice(m->device), "hipSetDevice");
     const size_t n = size_t(m->E) * m->dm.nu * m->dm.nv;
     hip_check(hipMemcpyAsync(m->a.stage64, u, n * sizeof(double), hipMemcpyHostToDevice, m->stream), "state upload");
@@ -1012,6 +1427,16 @@ fr_status fr_get_state(const fr_mesh *m, double *u) {
   return guarded([&] {
     if (!m || !u) fail(FR_E_ARG, "null argument");
     if (!m->state_set) fail(FR_E_STATE, "no state set");
+    if (m->mixed()) {
+      for (size_t g = 0; g < m->groups.size(); ++g) {
+        const fr_mesh &G = *m->groups[g];
+        std::vector<double> ug(size_t(G.E) * G.dm.nu * G.dm.nv);
+        const fr_status st = fr_get_state(&G, ug.data());
+        if (st != FR_OK) fail(st, g_err);
+        split_state(m, g, u, ug.data(), false);
+      }
+      return;
+    }
     hip_check(hipSetDevice(m->device), "hipSetDevice");
     const size_t n = size_t(m->E) * m->dm.nu * m->dm.nv;
     hip_check(launch_pack(m->cfg, m->a, false, m->a.U), "unpack");
@@ -1045,9 +1470,20 @@ fr_status fr_step(fr_mesh *m, int64_t n) {
 fr_status fr_forces(const fr_mesh *m, int32_t design, double *out) {
   return guarded([&] {
     if (!m || !out || design < 0 || design >= int(m->designs.size())) fail(FR_E_ARG, "bad argument");
-    double s[8];
-    hip_check(hipMemcpyAsync(s, m->a.fsum + 8 * design, sizeof(s), hipMemcpyDeviceToHost, m->stream), "forces");
-    hip_check(hipStreamSynchronize(m->stream), "forces");
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (m->mixed()) {  // the groups' wall sums add up; their step counts agree
+      for (auto &G : m->groups) {
+        if (G->nwall == 0) continue;
+        double sg[8];
+        hip_check(hipMemcpyAsync(sg, G->a.fsum, sizeof(sg), hipMemcpyDeviceToHost, m->stream), "forces");
+        hip_check(hipStreamSynchronize(m->stream), "forces");
+        for (int k : {0, 1, 2, 4, 5, 6}) s[k] += sg[k];
+        s[3] = sg[3];
+      }
+    } else {
+      hip_check(hipMemcpyAsync(s, m->a.fsum + 8 * design, sizeof(s), hipMemcpyDeviceToHost, m->stream), "forces");
+      hip_check(hipStreamSynchronize(m->stream), "forces");
+    }
     const auto &d = m->designs[design];
     double U2 = 0.0;
     for (int k = 1; k <= 3; ++k) U2 += d.fs[k] * d.fs[k];
@@ -1072,6 +1508,28 @@ fr_status fr_residual(fr_mesh *m, const double *u, double *r) {
   return guarded([&] {
     if (!m || !u || !r) fail(FR_E_ARG, "null argument");
     hip_check(hipSetDevice(m->device), "hipSetDevice");
+    if (m->mixed()) {
+      std::vector<std::vector<double>> ug(m->groups.size());
+      for (size_t g = 0; g < m->groups.size(); ++g) {
+        fr_mesh &G = *m->groups[g];
+        ug[g].resize(size_t(G.E) * G.dm.nu * G.dm.nv);
+        split_state(m, g, u, ug[g].data(), true);
+        hip_check(hipMemcpyAsync(G.a.stage64, ug[g].data(), ug[g].size() * sizeof(double), hipMemcpyHostToDevice,
+                                 m->stream), "upload");
+        hip_check(launch_pack(G.cfg, G.a, true, G.a.US), "pack");
+        lk(&G, K_INTERP, 1, 0, false);
+      }
+      enqueue_stage_mixed(m, 1, MODE_RESID, false);
+      for (size_t g = 0; g < m->groups.size(); ++g) {
+        fr_mesh &G = *m->groups[g];
+        hip_check(launch_pack(G.cfg, G.a, false, G.a.RES), "unpack");
+        hip_check(hipMemcpyAsync(ug[g].data(), G.a.stage64, ug[g].size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 m->stream), "download");
+      }
+      hip_check(hipStreamSynchronize(m->stream), "residual");
+      for (size_t g = 0; g < m->groups.size(); ++g) split_state(m, g, r, ug[g].data(), false);
+      return;
+    }
     const size_t n = size_t(m->E) * m->dm.nu * m->dm.nv;
     hip_check(hipMemcpyAsync(m->a.stage64, u, n * sizeof(double), hipMemcpyHostToDevice, m->stream), "upload");
     hip_check(launch_pack(m->cfg, m->a, true, m->a.US), "pack");
@@ -1094,6 +1552,7 @@ fr_status fr_residual(fr_mesh *m, const double *u, double *r) {
 fr_status fr_state_device(const fr_mesh *m, void **ptr, int64_t *bytes) {
   return guarded([&] {
     if (!m || !ptr || !bytes) fail(FR_E_ARG, "null argument");
+    if (m->mixed()) fail(FR_E_UNSUPPORTED, "a variable-order state lives in several arrays");
     *ptr = m->a.U;
     *bytes = int64_t(m->nblk) * m->dm.nup * m->dm.nv * EB * int64_t(m->real_size());
   });
@@ -1102,6 +1561,10 @@ fr_status fr_state_device(const fr_mesh *m, void **ptr, int64_t *bytes) {
 fr_status fr_select_kernels(fr_mesh *m, int32_t mask) {
   return guarded([&] {
     if (!m) fail(FR_E_ARG, "null mesh");
+    if (m->mixed()) {
+      if (!(unsigned(mask) & FUSED)) fail(FR_E_UNSUPPORTED, "variable-order meshes run the fused stage only");
+      return;
+    }
     m->cfg.variant_mask = unsigned(mask) & (FUSED | (1u << K_INTERP) | (1u << K_GRAD) | (1u << K_VISC) | (1u << K_DIVRK));
     drop_graphs(m);
   });
@@ -1118,6 +1581,10 @@ fr_status fr_autotune(fr_mesh *m, int64_t steps, int32_t *mask_out) {
   return guarded([&] {
     if (!m || steps <= 0) fail(FR_E_ARG, "bad argument");
     if (!m->state_set) fail(FR_E_STATE, "no state set");
+    if (m->mixed()) {  // one structure only
+      if (mask_out) *mask_out = int32_t(m->cfg.variant_mask);
+      return;
+    }
     hip_check(hipSetDevice(m->device), "hipSetDevice");
     const size_t nb = size_t(m->nblk) * m->dm.nup * m->dm.nv * EB * m->real_size();
     // keep the state: time on a copy, restore it afterwards
@@ -1152,6 +1619,7 @@ fr_status fr_autotune(fr_mesh *m, int64_t steps, int32_t *mask_out) {
 fr_status fr_profile_kernels(fr_mesh *m, int64_t steps, double *ms, int64_t *launches) {
   return guarded([&] {
     if (!m || !ms || !launches || steps <= 0) fail(FR_E_ARG, "bad argument");
+    if (m->mixed()) fail(FR_E_UNSUPPORTED, "per-kernel profile of a variable-order mesh");
     if (!m->state_set) fail(FR_E_STATE, "no state set");
     hip_check(hipSetDevice(m->device), "hipSetDevice");
     profile_steps(m, steps, ms, launches);
@@ -1280,6 +1748,7 @@ fr_status fr_probe_create(fr_mesh *m, const fr_mesh_desc *desc, int32_t design, 
     *out = nullptr;
     if (!m || !desc || n <= 0 || !points || design < 0 || design >= int(m->designs.size()))
       fail(FR_E_ARG, "bad argument");
+    if (m->mixed() || desc->elem_order) fail(FR_E_UNSUPPORTED, "probes of a variable-order mesh");
     validate_desc(desc);
     const auto &ds = m->designs[design];
     if (desc->n_elems != ds.E || desc->dim != m->dim || desc->order != m->order)

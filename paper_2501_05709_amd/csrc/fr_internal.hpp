@@ -31,6 +31,10 @@ __host__ __device__ inline size_t lay(int64_t blk, int pt, int ch, int e, int NP
 // index = position of a wall flux point in the compact wall list.
 constexpr int BC_WALL = 1;
 constexpr int BC_FARFIELD = 2;
+// A flux point on a face shared with an element of another order: index =
+// (mortar point << 1) | side, side 1 on the lower-order element.  Its partner data
+// come from the mortar buffers (DevArrays::MU, MX), filled by k_mortar_gather.
+constexpr int BC_MORTAR = 3;
 
 enum Kernel {
   K_FACE = 1,    // common solution and Rusanov flux at every flux point
@@ -70,6 +74,11 @@ struct DevArrays {
   double *fsum = nullptr;  // [design][8]: sum Fx,Fy,Fz, count, last Fx,Fy,Fz, spare
   int *flag = nullptr;     // non-finite flag
   double *stage64 = nullptr;  // canonical FP64 staging [E][nu][nv]
+  // mortar buffers of a variable-order mesh, [mortar point][nv] (real), shared by its
+  // order groups: MU the other side's trace at the point; MX the other side's half
+  // viscous normal flux (higher-order side) or the complete transformed common flux
+  // (lower-order side); MT the transformed common flux of the higher-order side
+  void *MU = nullptr, *MX = nullptr, *MT = nullptr;
 };
 
 struct LaunchCfg {
@@ -106,6 +115,17 @@ hipError_t launch_kernel(int kernel, const LaunchCfg &c, const DevArrays &a, int
 hipError_t launch_pack(const LaunchCfg &c, const DevArrays &a, bool to_device_layout, void *dst_res);
 hipError_t launch_force_reduce(const LaunchCfg &c, const DevArrays &a);
 hipError_t launch_clear_flag(const LaunchCfg &c, const DevArrays &a);
+
+// Mortar gather: for rows r in [r0, r1), out[row_out[r]][v] = sign * sum over the row's
+// entries j in [row_off[r], row_off[r+1]) of w[j] * source value, the source being
+// group ent_grp[j]'s face array (a partner code ent_code[j], as in the neighbour table)
+// or, for ent_grp[j] < 0, the compact array `compact` at point ent_code[j].
+struct MortarSrc {
+  const void *g[8];
+};
+hipError_t launch_mortar_gather(int prec, int nv, int64_t r0, int64_t r1, const int *row_out, const int *row_off,
+                                const int *ent_grp, const int *ent_code, const double *ent_w, MortarSrc src,
+                                const void *compact, void *out, double sign, hipStream_t stream);
 hipError_t launch_probe(const LaunchCfg &c, const DevArrays &a, int64_t n, const int64_t *slot, const double *w,
                         double *out);
 

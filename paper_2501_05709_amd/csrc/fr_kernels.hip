@@ -77,6 +77,8 @@ template <typename T> struct KArgs {
   const int *NB, *bcount, *bdesign;
   const int64_t *bcanon, *wall_first;
   int *flag;
+  const T *MU, *MX;
+  T *MT;
   int64_t nblk, n_canon;
   int ndesign;
   T gam, mu, kappa;
@@ -991,6 +993,11 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       const size_t base = size_t(nbv[it] / SB) * NV * SB + (nbv[it] % SB);
 #pragma unroll
       for (int v = 0; v < NV; ++v) ur[it][v] = a.UF[base + v * SB];
+    } else if (((-nbv[it]) & 3) == BC_MORTAR) {
+      // the other side's trace, brought to this point by the mortar gather
+      const size_t base = size_t((-nbv[it]) >> 3) * NV;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ur[it][v] = a.MU[base + v];
     }
   }
   double Sm[PI][DIM][DIM], ijv[PI];
@@ -1033,7 +1040,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       }
       const int nb = nbv[it];
       T ub[NV];
-      if (nb >= 0) {
+      if (nb >= 0 || ((-nb) & 3) == BC_MORTAR) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           ub[v] = ur[it][v];
@@ -1143,7 +1150,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       }
     const int nb = nbv[it];
     T fn[NV];
-    if (nb >= 0) {
+    if (nb >= 0 || ((-nb) & 3) == BC_MORTAR) {
       gas.flux_vis_n(ufv[it], gf, nrm[it], fn, false);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -1257,6 +1264,12 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
       const size_t base = size_t(nbv[it] / SB) * NV * SB + (nbv[it] % SB);
 #pragma unroll
       for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[base + v * SB];
+    } else if (((-nbv[it]) & 3) == BC_MORTAR) {
+      // higher-order side: the other side's half viscous flux; lower-order side: the
+      // complete transformed common flux (projected from the higher-order side)
+      const size_t base = size_t((-nbv[it]) >> 3) * NV;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) pn[it][v] = a.MX[base + v];
     }
   }
   T rv[PI][NV], un[PI][NV], ac[PI][NV];
@@ -1286,9 +1299,22 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) b[v] = 0;
     if (eg < nvalid) {
+      const int code = -nbv[it];
       if (nbv[it] >= 0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) b[v] = T(Av[it] * double(qv[it][v] + pn[it][v]));
+      } else if ((code & 3) == BC_MORTAR) {
+        const size_t base = size_t(code >> 3) * NV;
+        if ((code >> 2) & 1) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) b[v] = pn[it][v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            b[v] = T(Av[it] * double(qv[it][v] + pn[it][v]));
+            a.MT[base + v] = b[v];
+          }
+        }
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) b[v] = T(Av[it] * double(qv[it][v]));
@@ -1476,6 +1502,7 @@ template <typename T> static KArgs<T> make_args(const LaunchCfg &c, const DevArr
   a.FC = d.FC; a.fsum = d.fsum; a.stage64 = d.stage64;
   a.NB = d.NB; a.bcount = d.bcount; a.bdesign = d.bdesign; a.bcanon = d.bcanon; a.wall_first = d.wall_first;
   a.flag = d.flag;
+  a.MU = (const T *)d.MU; a.MX = (const T *)d.MX; a.MT = (T *)d.MT;
   a.nblk = c.nblk; a.n_canon = c.n_canon; a.ndesign = c.ndesign;
   a.gam = T(c.gamma); a.mu = T(c.mu); a.kappa = T(c.mu * c.gamma / c.prandtl);
   return a;
@@ -1551,6 +1578,45 @@ static hipError_t pack_t(const LaunchCfg &c, const DevArrays &d, bool to_dev, vo
   const int64_t thr = c.nblk * S::NUP * S::NV * EB;
   hipLaunchKernelGGL((k_pack<T, DIM, ORDER>), dim3((thr + 255) / 256), dim3(256), 0, c.stream, a, (T *)dst,
                      int(to_dev));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// mortar gather (faces between elements of different orders): one thread per
+// (row, variable), a short FP64 dot product over the other side's face points
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_mortar_gather(int64_t r0, int64_t r1, int nv, const int *__restrict__ row_out,
+                                                       const int *__restrict__ row_off, const int *__restrict__ ent_grp,
+                                                       const int *__restrict__ ent_code, const double *__restrict__ ent_w,
+                                                       MortarSrc src, const T *__restrict__ compact, T *__restrict__ out,
+                                                       double sign) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t r = r0 + t / nv;
+  const int v = int(t % nv);
+  if (r >= r1) return;
+  double acc = 0.0;
+  for (int j = row_off[r]; j < row_off[r + 1]; ++j) {
+    const int g = ent_grp[j], c = ent_code[j];
+    const T x = g >= 0 ? ((const T *)src.g[g])[size_t(c / SB) * nv * SB + (c % SB) + size_t(v) * SB]
+                       : compact[size_t(c) * nv + v];
+    acc += ent_w[j] * double(x);
+  }
+  out[size_t(row_out[r]) * nv + v] = T(sign * acc);
+}
+
+hipError_t launch_mortar_gather(int prec, int nv, int64_t r0, int64_t r1, const int *row_out, const int *row_off,
+                                const int *ent_grp, const int *ent_code, const double *ent_w, MortarSrc src,
+                                const void *compact, void *out, double sign, hipStream_t stream) {
+  if (r1 <= r0) return hipSuccess;
+  const int64_t thr = (r1 - r0) * nv;
+  const dim3 grid(unsigned((thr + 255) / 256));
+  if (prec == 1)
+    hipLaunchKernelGGL(k_mortar_gather<float>, grid, dim3(256), 0, stream, r0, r1, nv, row_out, row_off, ent_grp,
+                       ent_code, ent_w, src, (const float *)compact, (float *)out, sign);
+  else
+    hipLaunchKernelGGL(k_mortar_gather<double>, grid, dim3(256), 0, stream, r0, r1, nv, row_out, row_off, ent_grp,
+                       ent_code, ent_w, src, (const double *)compact, (double *)out, sign);
   return hipGetLastError();
 }
 

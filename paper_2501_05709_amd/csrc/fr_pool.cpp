@@ -59,7 +59,42 @@ struct fr_pool {
 extern "C" {
 
 fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
-  if (!d || !bytes || d->n_elems <= 0 || (d->dim != 2 && d->dim != 3) || d->order < 1) return FR_E_ARG;
+  if (!d || !bytes || d->n_elems <= 0 || (d->dim != 2 && d->dim != 3)) return FR_E_ARG;
+  if (d->elem_order) {
+    // variable order: the order groups' footprints, plus the mortar buffers and
+    // gather tables for at most every face point of every element
+    size_t total = 0;
+    std::vector<int64_t> en_count(8, 0);
+    for (int64_t e = 0; e < d->n_elems; ++e) {
+      const int p = d->elem_order[e];
+      if (p < 1 || p > 7) return FR_E_ARG;
+      ++en_count[size_t(p)];
+    }
+    for (int p = 1; p < 8; ++p) {
+      if (!en_count[size_t(p)]) continue;
+      fr_mesh_desc g = *d;
+      g.elem_order = nullptr;
+      g.order = p;
+      g.n_elems = en_count[size_t(p)];
+      g.n_bfaces = 0;
+      size_t b = 0;
+      const fr_status st = fr_footprint(&g, &b);
+      if (st != FR_OK) return st;
+      total += b;
+    }
+    int64_t nwall = 0, maxp = 1;
+    for (int64_t e = 0; e < d->n_elems; ++e) maxp = std::max<int64_t>(maxp, d->elem_order[e]);
+    for (int64_t i = 0; i < d->n_bfaces; ++i)
+      if (d->bfaces[3 * i + 2] == FR_BC_WALL) ++nwall;
+    const fr::Dims D(d->dim, int(maxp));
+    const size_t rs = d->precision == FR_FP32 ? 4 : 8;
+    const size_t pts = size_t(d->n_elems) * D.nf;
+    total += size_t(nwall) * D.nfp * 3 * 8;
+    total += pts * D.nv * rs * 3 + pts * (2 * 4) + pts * D.nfp * (4 + 4 + 8);
+    *bytes = total;
+    return FR_OK;
+  }
+  if (d->order < 1) return FR_E_ARG;
   const fr::Dims D(d->dim, d->order);
   const size_t rs = d->precision == FR_FP32 ? 4 : 8;
   const int64_t nblk = (d->n_elems + fr::EB - 1) / fr::EB;
@@ -156,9 +191,10 @@ fr_status admit(fr_pool *p, const fr_mesh_desc *desc, const double *u0, int64_t 
   d.stream = stream;
   st = fr_mesh_create(&d, &r.m);
   if (st != FR_OK) return undo(st);
-  int64_t info[10];
+  int64_t info[10], npts = 0;
   fr_mesh_info(r.m, info);
-  const int64_t n = info[3] * info[4] * info[6];
+  fr_mesh_points(r.m, &npts);
+  const int64_t n = npts * info[6];
   std::vector<double> u;
   if (!u0) {
     u.resize(size_t(n));

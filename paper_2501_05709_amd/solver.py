@@ -87,6 +87,12 @@ def _desc(mesh, precision, device=0, stream=None, allocator=None):
     for i, v in enumerate(mesh.get("drag_dir", [1.0, 0.0, 0.0])):
         d.drag_dir[i] = v
     d.dt = float(mesh.get("dt", 1e-3))
+    if mesh.get("orders") is not None:
+        orders = np.ascontiguousarray(mesh["orders"], dtype=np.int32)
+        if orders.shape != (en.shape[0],):
+            raise ValueError("one order per element expected")
+        keep.append(orders)
+        d.elem_order = orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     d.device = device
     d.stream = stream
     if allocator is not None:
@@ -127,6 +133,10 @@ class FRMesh:
         info = self.info()
         self.dim, self.order, self.n_designs, self.E, self.nu, self.nf, self.nv = (int(v) for v in info[:7])
         self.nblk = int(info[8])
+        npts = ctypes.c_int64()
+        check(L.fr_mesh_points(self.h, ctypes.byref(npts)), "fr_mesh_points")
+        self.n_points = npts.value
+        self.mixed = any(m.get("orders") is not None for m in meshes)
 
     def close(self):
         if getattr(self, "h", None):
@@ -141,7 +151,8 @@ class FRMesh:
 
     @property
     def shape(self):
-        return (self.E, self.nu, self.nv)
+        """Canonical state shape: [E][n_u][nv], or [points][nv] for a variable-order mesh."""
+        return (self.n_points, self.nv) if self.mixed else (self.E, self.nu, self.nv)
 
     def info(self):
         out = np.zeros(10, dtype=np.int64)
@@ -154,7 +165,7 @@ class FRMesh:
         return a.value, b.value
 
     def solution_points(self):
-        x = np.zeros((self.E, self.nu, 3))
+        x = np.zeros(self.shape[:-1] + (3,))
         check(_lib.load().fr_solution_points(self.h, x.ctypes.data_as(_lib._dp)), "fr_solution_points")
         return x
 

@@ -1,0 +1,198 @@
+"""GPU parity of variable per-element order (Section 3.1's P-distribution) through the
+C ABI against the FP64 oracle.
+
+Meshes: curved 2D boxes with orders 1..4 (P1 next to P4), straight 3D boxes with
+orders 1..4 and re-oriented elements (every face orientation between orders), curved
+3D boxes with orders 2..4, and NACA O-grids whose order falls from 3 at the wall to
+1 toward the far field, as the paper lowers it toward the boundaries.
+
+Bars (as for one order, relative L2 per physical field): FP64 residual and FP64 RK4
+state 1e-12; FP32 form 1e-5 after 100 steps; wall force means 1e-10; a variable-order
+mesh whose orders are all equal bit-identical to the one-order mesh; a pool request
+bit-identical to its solo run.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleMesh
+from paper_2501_05709_amd import _lib
+from paper_2501_05709_amd import workloads as W
+from paper_2501_05709_amd.solver import FRMesh, FRPool, Probe
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_err(x, ref):
+    nv = ref.shape[-1]
+    x = x.reshape(-1, nv)
+    ref = ref.reshape(-1, nv)
+    errs = []
+    for cols in ([0], list(range(1, nv - 1)), [nv - 1]):
+        errs.append(np.linalg.norm(x[:, cols] - ref[:, cols]) / np.linalg.norm(ref[:, cols]))
+    return max(errs)
+
+
+def rotate_element(conn, q, dim, rot):
+    na = q + 1
+    new = np.empty_like(conn)
+    for idx in range(na ** dim):
+        a = np.array([(idx // na ** k) % na for k in range(dim)])
+        b = rot(a, q)
+        new[idx] = conn[sum(int(b[k]) * na ** k for k in range(dim))]
+    return new
+
+
+ROT2 = [lambda a, q: np.array([q - a[1], a[0]]), lambda a, q: np.array([q - a[0], q - a[1]])]
+ROT3 = [lambda a, q: np.array([q - a[1], a[0], a[2]]), lambda a, q: np.array([a[0], q - a[2], a[1]]),
+        lambda a, q: np.array([a[1], a[2], a[0]]), lambda a, q: np.array([q - a[0], q - a[1], a[2]])]
+
+
+def box(dim, q, warp, lo, seed, rotate, nel=None):
+    nel = nel or ((5, 4) if dim == 2 else (3, 3, 2))
+    m = W.box_mesh(dim, nel, (0,) * dim, (1.0,) * dim, q=q, warp=warp, order=3)
+    m.update(gamma=1.4, prandtl=0.72, mu=0.02, freestream=np.array([1.0, 0.3, -0.2, 0.1, 1.0]), dt=2e-4)
+    E = len(m["elem_nodes"])
+    orders = np.random.default_rng(seed).integers(lo, 5, size=E)
+    orders[:4] = (lo, 4, 2, 3)
+    m["orders"] = orders.astype(np.int32)
+    if rotate:
+        rots = ROT2 if dim == 2 else ROT3
+        conn = m["elem_nodes"].copy()
+        for e in range(1, E, 2):
+            conn[e] = rotate_element(conn[e], q, dim, rots[(e // 2) % len(rots)])
+        m["elem_nodes"] = conn
+    return m
+
+
+def ogrid(seed=1, ni=24, nj=6, nk=2):
+    m = W.config_airfoil(seed, ni=ni, nj=nj, nk=nk)
+    m["orders"] = W.ring_orders(ni, nj, nk, ((2, 3), (4, 2), (nj, 1)))
+    m["dt"] = W.airfoil_dt(dict(m, order=3), 3)
+    return m
+
+
+def case(name):
+    return {"box2d_curved_p1-4": lambda: box(2, 2, 0.05, 1, 0, True),
+            "box3d_rotated_p1-4": lambda: box(3, 1, 0.0, 1, 1, True),
+            "box3d_curved_p2-4": lambda: box(3, 2, 0.05, 2, 2, False),
+            "ogrid_p3-1": lambda: ogrid()}[name]()
+
+
+def state(o, m, amp=0.1, seed=0):
+    x = o.solution_points().reshape(-1, 3)
+    fs = m["freestream"]
+    u = W.uniform_state(len(x), fs[0], fs[1:1 + o.dim], fs[4])
+    k = np.random.default_rng(seed).uniform(0.5, 2.0, size=3)
+    s = np.sin(k[0] * x[:, 0] + 0.3) * np.cos(k[1] * x[:, 1] - 0.2) * np.cos(k[2] * x[:, 2] + 0.1)
+    u[:, 0] *= 1.0 + amp * s
+    u[:, -1] *= 1.0 + amp * s
+    return u
+
+
+CASES = ["box2d_curved_p1-4", "box3d_rotated_p1-4", "box3d_curved_p2-4", "ogrid_p3-1"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_mixed_residual_fp64_matches_oracle(name):
+    m = case(name)
+    o = OracleMesh(m)
+    g = FRMesh(m, "fp64")
+    print(f"{name}: {o.E} elements, {o.NU} points, {o.n_mortar} mortar faces", flush=True)
+    assert g.shape == o.shape and o.n_mortar > 0
+    assert np.allclose(g.solution_points(), o.solution_points(), rtol=0, atol=1e-13)
+    u = state(o, m)
+    err = rel_err(g.residual(u), o.residual(u))
+    print(f"  residual rel err {err:.2e}", flush=True)
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_mixed_rk4_fp64_matches_oracle(name):
+    m = case(name)
+    o = OracleMesh(m)
+    g = FRMesh(m, "fp64")
+    u0 = state(o, m)
+    n = 20
+    ref, hist = o.rk4(u0, m["dt"], n, forces=True)
+    g.set_state(u0)
+    g.step(n)
+    err = rel_err(g.get_state(), ref)
+    print(f"{name}: {n} steps, state rel err {err:.2e}", flush=True)
+    assert err <= 1e-12
+    if (np.asarray(m.get("bfaces", np.zeros((0, 3))))[:, 2] == W.BC_WALL).any():
+        f = g.forces()
+        fs = m["freestream"]
+        qref = 0.5 * fs[0] * (fs[1:4] @ fs[1:4]) * m["ref_area"]
+        mean = hist.mean(axis=0)
+        cl, cd = mean @ m["lift_dir"] / qref, mean @ m["drag_dir"] / qref
+        scale = max(abs(cl), abs(cd))
+        assert f[7] == n and abs(f[5] - cl) <= 1e-10 * scale and abs(f[6] - cd) <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("name", ["box2d_curved_p1-4", "box3d_rotated_p1-4", "ogrid_p3-1"])
+def test_mixed_fp32_form_matches_oracle(name):
+    m = case(name)
+    o = OracleMesh(m)
+    g = FRMesh(m, "fp32")
+    u0 = state(o, m)
+    n = 100
+    ref = o.rk4(u0, m["dt"], n)
+    g.set_state(u0)
+    g.step(n)
+    err = rel_err(g.get_state(), ref)
+    print(f"{name}: FP32 form after {n} steps, rel err {err:.2e}", flush=True)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_equal_orders_bit_identical_to_one_order(precision):
+    m = W.config_airfoil(3, ni=24, nj=5, nk=2)
+    mm = dict(m, orders=np.full(len(m["elem_nodes"]), 3, dtype=np.int32))
+    g1, g2 = FRMesh(m, precision), FRMesh(mm, precision)
+    g1.select_kernels(1 | (1 << 5))   # the structure variable-order meshes run
+    o = OracleMesh(m)
+    u0 = state(o, m).reshape(o.shape)
+    g1.set_state(u0)
+    g2.set_state(u0.reshape(-1, o.nv))
+    g1.step(7)
+    g2.step(7)
+    assert np.array_equal(g1.get_state().reshape(-1, o.nv), g2.get_state())
+    assert np.array_equal(g1.forces(), g2.forces())
+
+
+def test_mixed_pool_request_bit_identical_to_solo():
+    m = ogrid(seed=4, ni=16, nj=5, nk=1)
+    g = FRMesh(m, "fp32")
+    fs = m["freestream"]
+    u0 = W.uniform_state(g.n_points, fs[0], fs[1:4], fs[4])
+    g.set_state(u0)
+    g.step(30)
+    pool = FRPool(4 << 30)
+    slot = pool.admit(m, 30, precision="fp32", u0=u0)
+    done = []
+    while not done:
+        done = pool.tick(7)
+    out, u = pool.result(slot, shape=g.shape)
+    pool.close()
+    assert np.array_equal(u, g.get_state()) and np.array_equal(out, g.forces())
+
+
+def test_mixed_unsupported_calls_are_rejected():
+    m = box(2, 1, 0.0, 1, 5, False)
+    g = FRMesh(m, "fp64")
+    with pytest.raises(_lib.FRError) as e:
+        g.select_kernels(0)
+    assert e.value.code == _lib.FR_E_UNSUPPORTED
+    with pytest.raises(_lib.FRError) as e:
+        g.neighbours()
+    assert e.value.code == _lib.FR_E_UNSUPPORTED
+    with pytest.raises(_lib.FRError) as e:
+        Probe(g, np.array([[0.5, 0.5, 0.0]]))
+    assert e.value.code == _lib.FR_E_UNSUPPORTED
+    with pytest.raises(_lib.FRError) as e:
+        FRMesh([m, m], "fp64")
+    assert e.value.code == _lib.FR_E_UNSUPPORTED
+    bad = dict(m, orders=np.full(len(m["elem_nodes"]), 6, dtype=np.int32))
+    with pytest.raises(_lib.FRError) as e:
+        FRMesh(bad, "fp64")
+    assert e.value.code == _lib.FR_E_UNSUPPORTED
