@@ -7,13 +7,15 @@ Mach 0.1, RK4 with dt = 1e-3.  A "step" is one full RK4 step (four FR
 residual evaluations and the fused stage updates) of the whole mesh; the
 state is resident in HBM before the timed region starts.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--workload tgv|airfoil|batch|serve]
+    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--workload tgv|airfoil|batch|serve|fwh|pmix]
 
 ``--workload batch``: sixteen NACA 4-digit O-grids of uneven size advanced by
 one graph of launches per step (aggregate DOF-updates/s, latency of the
 batched solve).  ``--workload serve``: a Poisson stream of airfoil solve
 requests (mean 4/s, order 2..4, 500 steps each) through the request pool
 (p50/p99 latency from arrival to result, aggregate DOF-updates/s).
+``--workload pmix``: the airfoil grid with the order falling from 3 at the wall to 1
+toward the far field (variable order), against the same grid at order 3.
 
 Prints one JSON line.  ``value`` is FP32-form DOF-updates/s (DOF = elements x
 solution points x conserved variables, one update = one RK4 step); the plain
@@ -360,12 +362,89 @@ def bench_fwh(args):
     print(json.dumps(res))
 
 
+def bench_pmix(args):
+    """Variable order on the airfoil O-grid (Section 3.1): P3 in the 16 wall layers, P2
+    in the next 16, P1 in the outer 16 of the 160 x 48 x 8 grid, as the paper lowers the
+    order toward the far field; timed against the same grid at P3 everywhere."""
+    import torch
+    from paper_2501_05709_amd import workloads as W
+    from paper_2501_05709_amd.solver import FRMesh
+    ni, nj, nk = 160, 48, 8
+    m = W.config_airfoil(0, ni=ni, nj=nj, nk=nk, order=3)
+    m["orders"] = W.ring_orders(ni, nj, nk, ((16, 3), (32, 2), (48, 1)))
+    desc = {"workload": "naca4_ogrid_160x48x8_quadratic_hex_p3_p2_p1_rings", "elements": ni * nj * nk,
+            "orders": "P3 layers 0-15, P2 16-31, P1 32-47", "reynolds": 23000, "mach": 0.2, "aoa_deg": 5.0,
+            "dt": m["dt"], "mesh": "curved quadratic hexes, wall + far field + spanwise periodic"}
+    g32 = FRMesh(m, "fp32")
+    xyz = g32.solution_points()
+    u0 = np.ascontiguousarray(m["init"](xyz))
+    dof = g32.n_points * g32.nv
+    cpu = ref = err32_oracle = err64_oracle = None
+    n_sample = args.cpu_steps or 3
+    if not args.no_cpu_baseline:
+        from oracle.oracle import OracleMesh, num_threads
+        o = OracleMesh(m)
+        o.rk4(u0, m["dt"], 1)
+        t0 = time.perf_counter()
+        ref = o.rk4(u0, m["dt"], n_sample)
+        tc = time.perf_counter() - t0
+        cpu = {"value": dof * n_sample / tc, "unit": "DOF-updates/s", "cores": num_threads(), "kind": "oracle",
+               "sample": f"{n_sample} RK4 steps of the full {desc['workload']} mesh, FP64, OpenMP over elements, "
+                         f"{tc:.1f} s"}
+    g64 = FRMesh(m, "fp64")
+    if ref is not None:
+        for g in (g64, g32):
+            g.set_state(u0)
+            g.step(n_sample)
+        err64_oracle = rel_l2(g64.get_state(), ref)
+        err32_oracle = rel_l2(g32.get_state(), ref)
+    t64 = timed_run(g64, u0, args.steps, args.warmup)
+    t32 = timed_run(g32, u0, args.steps, args.warmup)
+    err32_vs64 = rel_l2(g32.get_state(), g64.get_state())
+    # the same grid at P3 everywhere, fused stage
+    m3 = dict(m)
+    m3.pop("orders")
+    g3 = FRMesh(m3, "fp32")
+    g3.select_kernels(1 | (1 << 5))
+    u3 = np.ascontiguousarray(m3["init"](g3.solution_points().reshape(-1, 3)).reshape(g3.shape))
+    t3 = timed_run(g3, u3, args.steps, args.warmup)
+    dof3 = g3.E * g3.nu * g3.nv
+    # step roofline: algorithmic bytes of both fused launches of every order group, four
+    # stages, plus the mortar gathers (each mortar point: its weights, codes and partner
+    # values in, one value out), over the measured step time
+    orders, counts = np.unique(m["orders"], return_counts=True)
+    step_bytes = 0.0
+    for p, c in zip(orders, counts):
+        cost, _ = per_element_cost(3, int(p), 4)
+        step_bytes += 4 * c * (cost[6]["bytes"] + cost[7]["bytes"])
+    achieved = step_bytes / (t32 / args.steps) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK["hbm"], "unit": "GB/s",
+            "frac": round(achieved / PEAK["hbm"], 4), "kernel": "whole step (all order groups)", "traffic": None}
+    out = {
+        "metric": "FR DOF-updates/s (FP32 form; FP64 beside it) at stated L2 error vs the FP64 oracle",
+        "value": round(dof * args.steps / t32, 1), "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t32 / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": dict(desc, form="fp32 operators/fluxes/state, fp64 metrics and force sums", dof=dof,
+                       parallelism="single GPU"),
+        "fp64": {"value": round(dof * args.steps / t64, 1), "ms_per_step": round(t64 / args.steps * 1e3, 4),
+                 "rel_l2_vs_oracle": err64_oracle},
+        "fp32_rel_l2_vs_oracle": err32_oracle, "fp32_rel_l2_vs_fp64_gpu": err32_vs64,
+        "oracle_sample_steps": n_sample if ref is not None else None,
+        "uniform_p3_same_grid": {"value": round(dof3 * args.steps / t3, 1), "dof": dof3,
+                                 "ms_per_step": round(t3 / args.steps * 1e3, 4)},
+        "step_time_vs_uniform_p3": round(t32 / t3, 3),
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="tgv", choices=["tgv", "airfoil", "batch", "serve", "fwh"])
+    ap.add_argument("--workload", default="tgv", choices=["tgv", "airfoil", "batch", "serve", "fwh", "pmix"])
     ap.add_argument("--requests", type=int, default=64, help="serve: requests in the trace")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: mean arrivals per second")
     ap.add_argument("--budget-gb", type=float, default=96.0, help="serve: HBM budget of the pool")
@@ -398,6 +477,8 @@ def main():
         return bench_serve(args)
     if args.workload == "fwh":
         return bench_fwh(args)
+    if args.workload == "pmix":
+        return bench_pmix(args)
     m, desc = build_workload(args.workload)
     g32 = FRMesh(m, "fp32")
     xyz = g32.solution_points().reshape(-1, 3)
