@@ -74,7 +74,7 @@ typedef void (*fr_free_fn)(void *ptr, void *ctx, void *stream);
 /* One mesh and its flow constants.  All pointers are host pointers. */
 typedef struct {
   int32_t dim;             /* 2 or 3 */
-  int32_t order;           /* polynomial order p, 1..4 */
+  int32_t order;           /* polynomial order p, 0..4 (0: one solution point, a finite volume) */
   int32_t geom_order;      /* q = 1 (straight) or 2 (quadratic, curved) */
   int32_t precision;       /* FR_FP64 or FR_FP32 (metrics and force sums are FP64 in both) */
   int64_t n_nodes;
@@ -95,7 +95,7 @@ typedef struct {
   fr_alloc_fn alloc;       /* optional device allocator (e.g. a framework's caching allocator) */
   fr_free_fn free;
   void *alloc_ctx;
-  const int32_t *elem_order; /* [n_elems] per-element order 1..4, or NULL: `order` everywhere.
+  const int32_t *elem_order; /* [n_elems] per-element order 0..4, or NULL: `order` everywhere.
                               * See "Variable order" below. */
 } fr_mesh_desc;
 

@@ -140,7 +140,7 @@ static double lagrange_d(int n, const double *x, int j, double t) {
 int orc_basis(int order, double *xi, double *w, double *D, double *lm, double *lp,
               double *gLd, double *gRd) {
   int n = order + 1;
-  if (order < 1 || n > MAXN) return -1;
+  if (order < 0 || n > MAXN) return -1;
   /* Gauss-Legendre nodes: roots of P_n by Newton from the cosine guess */
   double x[MAXN], ww[MAXN];
   for (int i = 0; i < n; ++i) {
@@ -697,7 +697,7 @@ int orc_create_mixed(int dim, int order, const int *orders, int q, long nnodes, 
   M->uo[0] = M->fo[0] = 0;
   for (long e = 0; e < E; ++e) {
     int p = orders ? orders[e] : order;
-    if (p < 1 || p + 1 > MAXN) { orc_destroy(M); return -1; }
+    if (p < 0 || p + 1 > MAXN) { orc_destroy(M); return -1; }
     M->ord[e] = p;
     if (p > M->order) M->order = p;
     int n = p + 1;
@@ -705,7 +705,7 @@ int orc_create_mixed(int dim, int order, const int *orders, int q, long nnodes, 
     M->fo[e + 1] = M->fo[e] + 2 * dim * (dim == 2 ? n : n * n);
   }
   if (E == 0) M->order = order;
-  for (int p = 1; p + 1 <= MAXN; ++p) {
+  for (int p = 0; p + 1 <= MAXN; ++p) {
     orc_basis1d *B = &M->bas[p];
     double Dflat[MAXN * MAXN];
     B->n = p + 1;

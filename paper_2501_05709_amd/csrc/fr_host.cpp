@@ -507,11 +507,14 @@ HostMesh build_host_mesh(const fr_mesh_desc &d, bool allow_mortar = false) {
   for (const auto &P : pairs) {
     const int64_t eA = P.a / nfe, eB = P.b / nfe;
     const int fA = int(P.a % nfe), fB = int(P.b % nfe);
+    // length scale of the face: the spread of its flux points, or (one flux point,
+    // order 0) the distance from the element's solution point to it
     double hA = 0.0;
     for (int m = 0; m < nfp; ++m)
       for (int k = 0; k < dim; ++k)
         hA = std::max(hA, std::fabs(H.fx[(size_t(eA) * nf + fA * nfp + m) * 3 + k] -
-                                    H.fx[(size_t(eA) * nf + fA * nfp) * 3 + k]));
+                                    (nfp > 1 ? H.fx[(size_t(eA) * nf + fA * nfp) * 3 + k]
+                                             : H.xu[size_t(eA) * nu * 3 + k])));
     const double ptol = 1e-7 * std::max(hA, 1e-300);
     for (int m = 0; m < nfp; ++m) {
       const double *xa = &H.fx[(size_t(eA) * nf + fA * nfp + m) * 3];
@@ -626,7 +629,7 @@ void validate_desc(const fr_mesh_desc *d) {
   if (d->dim != 2 && d->dim != 3) fail(FR_E_ARG, "dim must be 2 or 3");
   if (d->geom_order != 1 && d->geom_order != 2) fail(FR_E_ARG, "geom_order must be 1 or 2");
   if (d->precision != FR_FP64 && d->precision != FR_FP32) fail(FR_E_ARG, "unknown precision");
-  if (!kernels_available(d->precision, d->dim, d->order)) fail(FR_E_UNSUPPORTED, "order not compiled in (1..4)");
+  if (!kernels_available(d->precision, d->dim, d->order)) fail(FR_E_UNSUPPORTED, "order not compiled in (0..4)");
   if (d->n_elems <= 0 || !d->elem_nodes || d->n_nodes <= 0 || !d->nodes) fail(FR_E_ARG, "empty mesh");
   if (d->n_periodic < 0 || (d->n_periodic > 0 && !d->periodic_shift)) fail(FR_E_ARG, "bad periodic list");
   if (d->n_bfaces < 0 || (d->n_bfaces > 0 && !d->bfaces)) fail(FR_E_ARG, "bad boundary list");
@@ -920,7 +923,7 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
   M->eorder.assign(d.elem_order, d.elem_order + E);
   std::vector<int> present;
   for (int p : M->eorder) {
-    if (!kernels_available(d.precision, dim, p)) fail(FR_E_UNSUPPORTED, "element order not compiled in (1..4)");
+    if (!kernels_available(d.precision, dim, p)) fail(FR_E_UNSUPPORTED, "element order not compiled in (0..4)");
     if (std::find(present.begin(), present.end(), p) == present.end()) present.push_back(p);
   }
   std::sort(present.begin(), present.end());

@@ -1624,18 +1624,22 @@ hipError_t launch_mortar_gather(int prec, int nv, int64_t r0, int64_t r1, const 
   do {                                                                                    \
     const int key = c.prec * 100 + c.dim * 10 + c.order;                                  \
     switch (key) {                                                                        \
+      case 20: return FN<double, 2, 0>(__VA_ARGS__);                                      \
       case 21: return FN<double, 2, 1>(__VA_ARGS__);                                      \
       case 22: return FN<double, 2, 2>(__VA_ARGS__);                                      \
       case 23: return FN<double, 2, 3>(__VA_ARGS__);                                      \
       case 24: return FN<double, 2, 4>(__VA_ARGS__);                                      \
+      case 30: return FN<double, 3, 0>(__VA_ARGS__);                                      \
       case 31: return FN<double, 3, 1>(__VA_ARGS__);                                      \
       case 32: return FN<double, 3, 2>(__VA_ARGS__);                                      \
       case 33: return FN<double, 3, 3>(__VA_ARGS__);                                      \
       case 34: return FN<double, 3, 4>(__VA_ARGS__);                                      \
+      case 120: return FN<float, 2, 0>(__VA_ARGS__);                                      \
       case 121: return FN<float, 2, 1>(__VA_ARGS__);                                      \
       case 122: return FN<float, 2, 2>(__VA_ARGS__);                                      \
       case 123: return FN<float, 2, 3>(__VA_ARGS__);                                      \
       case 124: return FN<float, 2, 4>(__VA_ARGS__);                                      \
+      case 130: return FN<float, 3, 0>(__VA_ARGS__);                                      \
       case 131: return FN<float, 3, 1>(__VA_ARGS__);                                      \
       case 132: return FN<float, 3, 2>(__VA_ARGS__);                                      \
       case 133: return FN<float, 3, 3>(__VA_ARGS__);                                      \
@@ -1645,7 +1649,7 @@ hipError_t launch_mortar_gather(int prec, int nv, int64_t r0, int64_t r1, const 
   } while (0)
 
 bool kernels_available(int prec, int dim, int order) {
-  return (prec == 0 || prec == 1) && (dim == 2 || dim == 3) && order >= 1 && order <= 4;
+  return (prec == 0 || prec == 1) && (dim == 2 || dim == 3) && order >= 0 && order <= 4;
 }
 
 hipError_t launch_kernel(int kernel, const LaunchCfg &c, const DevArrays &a, int stage, int mode, bool forces) {

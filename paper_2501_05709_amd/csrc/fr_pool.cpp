@@ -67,10 +67,10 @@ fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
     std::vector<int64_t> en_count(8, 0);
     for (int64_t e = 0; e < d->n_elems; ++e) {
       const int p = d->elem_order[e];
-      if (p < 1 || p > 7) return FR_E_ARG;
+      if (p < 0 || p > 7) return FR_E_ARG;
       ++en_count[size_t(p)];
     }
-    for (int p = 1; p < 8; ++p) {
+    for (int p = 0; p < 8; ++p) {
       if (!en_count[size_t(p)]) continue;
       fr_mesh_desc g = *d;
       g.elem_order = nullptr;
@@ -94,7 +94,7 @@ fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
     *bytes = total;
     return FR_OK;
   }
-  if (d->order < 1) return FR_E_ARG;
+  if (d->order < 0) return FR_E_ARG;
   const fr::Dims D(d->dim, d->order);
   const size_t rs = d->precision == FR_FP32 ? 4 : 8;
   const int64_t nblk = (d->n_elems + fr::EB - 1) / fr::EB;

@@ -105,22 +105,23 @@ def test_mixed_free_stream_preservation(dim, q, warp, lo):
 
 
 def test_mixed_free_stream_preservation_ogrid():
-    """Order falling from 3 at the wall to 1 at the far field, as the paper lowers it
+    """Order falling from 3 at the wall to 0 at the far field, as the paper lowers it
     toward the boundaries; inner and outer boundary both far field."""
-    ni, nj, nk = 24, 6, 2
+    ni, nj, nk = 24, 8, 2
     m = W.naca_ogrid(0.04, 0.4, 0.12, ni, nj, nk, inner_bc=W.BC_FARFIELD, outer_bc=W.BC_FARFIELD)
     m.update(W.airfoil_flow())
-    m["orders"] = W.ring_orders(ni, nj, nk, ((2, 3), (4, 2), (6, 1)))
+    m["orders"] = W.ring_orders(ni, nj, nk, ((2, 3), (4, 2), (6, 1), (8, 0)))
     o = OracleMesh(m)
-    assert o.n_mortar == 2 * ni * nk
+    assert o.n_mortar == 3 * ni * nk
     fs = m["freestream"]
     r = o.residual(W.uniform_state(o.NU, fs[0], fs[1:4], fs[4]))
     assert np.abs(r).max() < 1e-9 * fs[4]
 
 
-@pytest.mark.parametrize("dim,q,warp", [(2, 2, 0.06), (3, 1, 0.0), (3, 2, 0.04)])
-def test_mixed_conservation(dim, q, warp):
-    m = mixed_box(dim, q, warp, seed=5, mu=0.05)
+@pytest.mark.parametrize("dim,q,warp,lo", [(2, 2, 0.06, 1), (3, 1, 0.0, 1), (3, 2, 0.04, 1), (2, 2, 0.06, 0),
+                                           (3, 1, 0.0, 0)])
+def test_mixed_conservation(dim, q, warp, lo):
+    m = mixed_box(dim, q, warp, seed=5, mu=0.05, lo=lo)
     o = OracleMesh(m)
     x = o.solution_points()
     u = smooth(x, dim) + 0.01 * np.random.default_rng(1).standard_normal((o.NU, o.nv))
@@ -216,3 +217,66 @@ def test_mixed_vortex_accuracy():
     e3 = err(np.full(nel * nel, 3, dtype=np.int32))
     print(f"vortex L2 error: uniform P2 {e2:.3e}, mixed {e_mixed:.3e}, uniform P3 {e3:.3e}")
     assert e_mixed < 0.5 * e2 and e_mixed < 2.0 * e3
+
+
+# --------------------------------------------------------------------------
+# order 0: one solution point per element, a finite volume
+# --------------------------------------------------------------------------
+
+def fv_rusanov(uL, uR, n, dim):
+    """Rusanov flux of the Euler equations (the textbook formula, written out here)."""
+    def parts(u):
+        rho = u[..., 0]
+        v = u[..., 1:1 + dim] / rho[..., None]
+        p = (G - 1.0) * (u[..., -1] - 0.5 * rho * (v * v).sum(-1))
+        vn = (v * n).sum(-1)
+        F = np.empty_like(u)
+        F[..., 0] = rho * vn
+        F[..., 1:1 + dim] = u[..., 1:1 + dim] * vn[..., None] + p[..., None] * n
+        F[..., -1] = (u[..., -1] + p) * vn
+        return F, np.abs(vn) + np.sqrt(G * p / rho)
+    FL, aL = parts(uL)
+    FR, aR = parts(uR)
+    lam = np.maximum(aL, aR)[..., None]
+    return 0.5 * (FL + FR) - 0.5 * lam * (uR - uL)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_p0_is_the_rusanov_finite_volume_scheme(dim):
+    """On a periodic Cartesian box, order 0 is the first-order finite volume scheme:
+    R_e = -(1/V) sum over faces of area x Rusanov flux (inviscid)."""
+    nel = (5, 4) if dim == 2 else (4, 3, 3)
+    hi = (1.0, 0.7, 0.5)[:dim]
+    m = flow(W.box_mesh(dim, nel, (0,) * dim, hi, order=0), mu=0.0)
+    o = OracleMesh(m)
+    x = o.solution_points().reshape(-1, 3)
+    u = smooth(x, dim) + 0.02 * np.random.default_rng(3).standard_normal((len(x), o.nv))
+    r = o.residual(u).reshape(-1, o.nv)
+    h = np.array(hi) / np.array(nel)
+    ugrid = u.reshape(tuple(reversed(nel)) + (o.nv,))       # [k][j][i] (element e = i + nx (j + ny k))
+    expect = np.zeros_like(ugrid)
+    for k in range(dim):
+        ax = dim - 1 - k                                       # array axis of coordinate k
+        n = np.zeros(dim)
+        n[k] = 1.0
+        area = np.prod(h) / h[k]
+        Fp = fv_rusanov(ugrid, np.roll(ugrid, -1, axis=ax), n, dim)   # through the + face
+        Fm = np.roll(Fp, 1, axis=ax)                                   # the - face is the neighbour's +
+        expect -= area * (Fp - Fm) / np.prod(h)
+    assert np.abs(r - expect.reshape(-1, o.nv)).max() <= 1e-12 * np.abs(expect).max()
+
+
+def test_p0_gradient_is_the_central_difference():
+    """The BR1 corrected gradient at order 0 on a periodic Cartesian box is the central
+    difference (u[i+1] - u[i-1]) / (2 h) along each axis."""
+    nel, hi = (6, 5), (1.2, 1.0)
+    m = flow(W.box_mesh(2, nel, (0, 0), hi, order=0), mu=0.01)
+    o = OracleMesh(m)
+    u = 1.0 + np.random.default_rng(4).uniform(0.0, 1.0, size=(o.E, o.nv))
+    g = o.gradient(u).reshape(nel[1], nel[0], 3, o.nv)
+    ug = u.reshape(nel[1], nel[0], o.nv)
+    h = np.array(hi) / np.array(nel)
+    cdx = (np.roll(ug, -1, axis=1) - np.roll(ug, 1, axis=1)) / (2 * h[0])
+    cdy = (np.roll(ug, -1, axis=0) - np.roll(ug, 1, axis=0)) / (2 * h[1])
+    assert np.abs(g[:, :, 0] - cdx).max() < 1e-12 * np.abs(cdx).max()
+    assert np.abs(g[:, :, 1] - cdy).max() < 1e-12 * np.abs(cdy).max()
