@@ -14,7 +14,7 @@ one graph of launches per step (aggregate DOF-updates/s, latency of the
 batched solve).  ``--workload serve``: a Poisson stream of airfoil solve
 requests (mean 4/s, order 2..4, 500 steps each) through the request pool
 (p50/p99 latency from arrival to result, aggregate DOF-updates/s).
-``--workload pmix``: the airfoil grid with the order falling from 3 at the wall to 1
+``--workload pmix``: the airfoil grid with the order falling from 3 at the wall to 0
 toward the far field (variable order), against the same grid at order 3.
 
 Prints one JSON line.  ``value`` is FP32-form DOF-updates/s (DOF = elements x
@@ -363,17 +363,19 @@ def bench_fwh(args):
 
 
 def bench_pmix(args):
-    """Variable order on the airfoil O-grid (Section 3.1): P3 in the 16 wall layers, P2
-    in the next 16, P1 in the outer 16 of the 160 x 48 x 8 grid, as the paper lowers the
-    order toward the far field; timed against the same grid at P3 everywhere."""
+    """Variable order on the airfoil O-grid (Section 3.1): P3 in the 12 wall layers, then
+    P2, P1 and P0 in bands of 12 layers of the 160 x 48 x 8 grid, the paper's
+    low-resolution P0-P3 distribution lowering the order toward the far field; timed
+    against the same grid at P3 everywhere."""
     import torch
     from paper_2501_05709_amd import workloads as W
     from paper_2501_05709_amd.solver import FRMesh
     ni, nj, nk = 160, 48, 8
     m = W.config_airfoil(0, ni=ni, nj=nj, nk=nk, order=3)
-    m["orders"] = W.ring_orders(ni, nj, nk, ((16, 3), (32, 2), (48, 1)))
-    desc = {"workload": "naca4_ogrid_160x48x8_quadratic_hex_p3_p2_p1_rings", "elements": ni * nj * nk,
-            "orders": "P3 layers 0-15, P2 16-31, P1 32-47", "reynolds": 23000, "mach": 0.2, "aoa_deg": 5.0,
+    m["orders"] = W.ring_orders(ni, nj, nk, ((12, 3), (24, 2), (36, 1), (48, 0)))
+    desc = {"workload": "naca4_ogrid_160x48x8_quadratic_hex_p3_to_p0_rings", "elements": ni * nj * nk,
+            "orders": "P3 layers 0-11, P2 12-23, P1 24-35, P0 36-47", "reynolds": 23000, "mach": 0.2,
+            "aoa_deg": 5.0,
             "dt": m["dt"], "mesh": "curved quadratic hexes, wall + far field + spanwise periodic"}
     g32 = FRMesh(m, "fp32")
     xyz = g32.solution_points()

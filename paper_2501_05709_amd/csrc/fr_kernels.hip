@@ -940,7 +940,9 @@ template <typename T, int DIM, int ORDER> struct FS {
   static constexpr int WG_B = S::NU * EW_B >= 256 ? 256 : (S::NU * EW_B + 63) / 64 * 64;
 };
 
-template <typename T, int DIM, int ORDER>
+// MORTAR: the mesh is one order group of a variable-order mesh, whose neighbour codes
+// may name mortar points (compiled out otherwise)
+template <typename T, int DIM, int ORDER, bool MORTAR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2, 8)))
 void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   using S = Shape<DIM, ORDER>;
@@ -993,7 +995,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       const size_t base = size_t(nbv[it] / SB) * NV * SB + (nbv[it] % SB);
 #pragma unroll
       for (int v = 0; v < NV; ++v) ur[it][v] = a.UF[base + v * SB];
-    } else if (((-nbv[it]) & 3) == BC_MORTAR) {
+    } else if (MORTAR && ((-nbv[it]) & 3) == BC_MORTAR) {
       // the other side's trace, brought to this point by the mortar gather
       const size_t base = size_t((-nbv[it]) >> 3) * NV;
 #pragma unroll
@@ -1040,7 +1042,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       }
       const int nb = nbv[it];
       T ub[NV];
-      if (nb >= 0 || ((-nb) & 3) == BC_MORTAR) {
+      if (nb >= 0 || (MORTAR && ((-nb) & 3) == BC_MORTAR)) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           ub[v] = ur[it][v];
@@ -1150,7 +1152,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       }
     const int nb = nbv[it];
     T fn[NV];
-    if (nb >= 0 || ((-nb) & 3) == BC_MORTAR) {
+    if (nb >= 0 || (MORTAR && ((-nb) & 3) == BC_MORTAR)) {
       gas.flux_vis_n(ufv[it], gf, nrm[it], fn, false);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -1218,7 +1220,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   }
 }
 
-template <typename T, int DIM, int ORDER, int MODE>
+template <typename T, int DIM, int ORDER, int MODE, bool MORTAR>
 __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
   constexpr int mode = MODE;  // RK stage or residual: fixes what is read and written
   using S = Shape<DIM, ORDER>;
@@ -1264,7 +1266,7 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
       const size_t base = size_t(nbv[it] / SB) * NV * SB + (nbv[it] % SB);
 #pragma unroll
       for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[base + v * SB];
-    } else if (((-nbv[it]) & 3) == BC_MORTAR) {
+    } else if (MORTAR && ((-nbv[it]) & 3) == BC_MORTAR) {
       // higher-order side: the other side's half viscous flux; lower-order side: the
       // complete transformed common flux (projected from the higher-order side)
       const size_t base = size_t((-nbv[it]) >> 3) * NV;
@@ -1303,7 +1305,7 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
       if (nbv[it] >= 0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) b[v] = T(Av[it] * double(qv[it][v] + pn[it][v]));
-      } else if ((code & 3) == BC_MORTAR) {
+      } else if (MORTAR && (code & 3) == BC_MORTAR) {
         const size_t base = size_t(code >> 3) * NV;
         if ((code >> 2) & 1) {
 #pragma unroll
@@ -1508,6 +1510,21 @@ template <typename T> static KArgs<T> make_args(const LaunchCfg &c, const DevArr
   return a;
 }
 
+template <typename T, int DIM, int ORDER, bool MORTAR>
+static hipError_t launch_stage_b(int mode, dim3 grid, dim3 wgs, hipStream_t stream, const KArgs<T> &a) {
+  switch (mode) {
+    case MODE_RK0: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK0, MORTAR>), grid, wgs, 0, stream, a); break;
+    case MODE_RK1: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK1, MORTAR>), grid, wgs, 0, stream, a); break;
+    case MODE_RK2: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK2, MORTAR>), grid, wgs, 0, stream, a); break;
+    case MODE_RK3: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK3, MORTAR>), grid, wgs, 0, stream, a); break;
+    case MODE_RESID:
+      hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RESID, MORTAR>), grid, wgs, 0, stream, a);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename T, int DIM, int ORDER>
 static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, int stage, int mode,
                            bool forces) {
@@ -1543,21 +1560,18 @@ static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, i
         hipLaunchKernelGGL((k_visc<T, DIM, ORDER>), dim3((c.nblk * S::RTF + 3) / 4), blk, 0, c.stream, a,
                            int(forces));
       break;
-    case K_STAGE_A:
-      hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER>), dim3(c.nblk * (EB / FS<T, DIM, ORDER>::EW_A)),
-                         dim3(FS<T, DIM, ORDER>::WG_A), 0, c.stream, a, X, int(forces));
+    case K_STAGE_A: {
+      const dim3 grid(c.nblk * (EB / FS<T, DIM, ORDER>::EW_A)), wgs(FS<T, DIM, ORDER>::WG_A);
+      if (d.MU)
+        hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER, true>), grid, wgs, 0, c.stream, a, X, int(forces));
+      else
+        hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER, false>), grid, wgs, 0, c.stream, a, X, int(forces));
       break;
+    }
     case K_STAGE_B: {
       const dim3 grid(c.nblk * (EB / FS<T, DIM, ORDER>::EW_B)), wgs(FS<T, DIM, ORDER>::WG_B);
-      switch (mode) {
-        case MODE_RK0: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK0>), grid, wgs, 0, c.stream, a); break;
-        case MODE_RK1: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK1>), grid, wgs, 0, c.stream, a); break;
-        case MODE_RK2: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK2>), grid, wgs, 0, c.stream, a); break;
-        case MODE_RK3: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK3>), grid, wgs, 0, c.stream, a); break;
-        case MODE_RESID: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RESID>), grid, wgs, 0, c.stream, a); break;
-        default: return hipErrorInvalidValue;
-      }
-      break;
+      if (d.MU) return launch_stage_b<T, DIM, ORDER, true>(mode, grid, wgs, c.stream, a);
+      return launch_stage_b<T, DIM, ORDER, false>(mode, grid, wgs, c.stream, a);
     }
     case K_DIVRK:
       if (tensor)
