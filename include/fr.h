@@ -113,8 +113,9 @@ typedef struct {
  * element e's solution points contiguous, in element order (fr_set_state,
  * fr_get_state, fr_residual, fr_solution_points).  Variable-order meshes run
  * the fused two-launch stage only; they are built one at a time (not in a
- * batch), and fr_neighbours, fr_state_device, fr_profile_kernels and probes
- * report FR_E_UNSUPPORTED for them. */
+ * batch), and fr_neighbours, fr_state_device and fr_profile_kernels report
+ * FR_E_UNSUPPORTED for them.  Probes and served requests with a data surface
+ * work on them (each point is evaluated with its element's order). */
 
 /* Build a solver for one mesh: connectivity (faces matched by node ids,
  * periodic faces by the listed translations, flux points by position),

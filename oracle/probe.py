@@ -90,7 +90,18 @@ def locate(mesh, points, tol=1e-10):
 
 
 def sample(u, order, elem, xi, dim):
-    """Interpolant of the canonical state u [E][n^dim][V] at (elem, xi)."""
+    """Interpolant of the canonical state u [E][n^dim][V] at (elem, xi).
+
+    ``order`` may be an array of per-element orders; u is then the ragged state
+    [sum of n_e^dim][V] with element e's points contiguous, in element order."""
+    if np.ndim(order) == 1:
+        orders = np.asarray(order)
+        off = np.concatenate([[0], np.cumsum((orders + 1) ** dim)])
+        out = np.zeros((len(elem), u.shape[-1]))
+        for i, (e, r) in enumerate(zip(elem, xi)):
+            ue = u[off[e]:off[e + 1]][None]
+            out[i] = sample(ue, int(orders[e]), np.array([0]), np.asarray(r)[None], dim)[0]
+        return out
     n = order + 1
     x = np.polynomial.legendre.leggauss(n)[0]
     out = np.zeros((len(elem), u.shape[-1]))

@@ -1690,10 +1690,24 @@ struct fr_probe {
   int64_t *slot = nullptr;    // device [n]: block * EB + element slot
   double *w = nullptr;        // device [n][dim][order + 1]
   double *out = nullptr;      // device [n][nv]
+  // variable-order mesh: the points in each order group, evaluated by that group's
+  // kernel into their rows of `out`
+  struct Part {
+    int group = 0;
+    int64_t n = 0;
+    int64_t *slot = nullptr, *dst = nullptr;
+    double *w = nullptr;
+  };
+  std::vector<Part> parts;
   ~fr_probe() {
     (void)hipFree(slot);
     (void)hipFree(w);
     (void)hipFree(out);
+    for (auto &q : parts) {
+      (void)hipFree(q.slot);
+      (void)hipFree(q.dst);
+      (void)hipFree(q.w);
+    }
   }
 };
 
@@ -1751,10 +1765,16 @@ fr_status fr_probe_create(fr_mesh *m, const fr_mesh_desc *desc, int32_t design, 
     *out = nullptr;
     if (!m || !desc || n <= 0 || !points || design < 0 || design >= int(m->designs.size()))
       fail(FR_E_ARG, "bad argument");
-    if (m->mixed() || desc->elem_order) fail(FR_E_UNSUPPORTED, "probes of a variable-order mesh");
-    validate_desc(desc);
+    if (m->mixed() != (desc->elem_order != nullptr)) fail(FR_E_ARG, "descriptor does not match the mesh design");
+    if (m->mixed()) {
+      fr_mesh_desc d1 = *desc;
+      d1.order = 1;
+      validate_desc(&d1);
+    } else {
+      validate_desc(desc);
+    }
     const auto &ds = m->designs[design];
-    if (desc->n_elems != ds.E || desc->dim != m->dim || desc->order != m->order)
+    if (desc->n_elems != ds.E || desc->dim != m->dim || (!m->mixed() && desc->order != m->order))
       fail(FR_E_ARG, "descriptor does not match the mesh design");
     const int dim = desc->dim, na = desc->geom_order + 1;
     const int nn = dim == 2 ? na * na : na * na * na;
@@ -1823,6 +1843,45 @@ fr_status fr_probe_create(fr_mesh *m, const fr_mesh_desc *desc, int32_t design, 
       });
       for (int64_t i = 0; i < n; ++i)
         if (bad[size_t(i)]) fail(FR_E_ARG, "point " + std::to_string(i) + " lies in no element");
+      hip_check(hipSetDevice(m->device), "hipSetDevice");
+      if (m->mixed()) {
+        hip_check(hipMalloc(&p->out, size_t(n) * (dim + 2) * sizeof(double)), "probe alloc");
+        for (size_t g = 0; g < m->groups.size(); ++g) {
+          const fr_mesh &G = *m->groups[g];
+          Basis1D B(G.order);
+          std::vector<int64_t> slot, dst;
+          std::vector<double> w;
+          for (int64_t i = 0; i < n; ++i) {
+            const int64_t e = p->elem[size_t(i)];
+            if (m->egroup[size_t(e)] != int(g)) continue;
+            const int64_t le = m->elocal[size_t(e)];
+            slot.push_back((le / EB) * EB + le % EB);
+            dst.push_back(i);
+            for (int k = 0; k < dim; ++k) {
+              const auto l = B.eval_all(p->xi[size_t(i) * 3 + k]);
+              w.insert(w.end(), l.begin(), l.end());
+            }
+          }
+          if (slot.empty()) continue;
+          fr_probe::Part q;
+          q.group = int(g);
+          q.n = int64_t(slot.size());
+          p->parts.push_back(q);
+          auto &pq = p->parts.back();
+          hip_check(hipMalloc(&pq.slot, slot.size() * sizeof(int64_t)), "probe alloc");
+          hip_check(hipMalloc(&pq.dst, dst.size() * sizeof(int64_t)), "probe alloc");
+          hip_check(hipMalloc(&pq.w, w.size() * sizeof(double)), "probe alloc");
+          hip_check(hipMemcpyAsync(pq.slot, slot.data(), slot.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                                   m->stream), "probe upload");
+          hip_check(hipMemcpyAsync(pq.dst, dst.data(), dst.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                                   m->stream), "probe upload");
+          hip_check(hipMemcpyAsync(pq.w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, m->stream),
+                    "probe upload");
+          hip_check(hipStreamSynchronize(m->stream), "probe sync");
+        }
+        *out = p;
+        return;
+      }
       const int N = m->order + 1;
       Basis1D B(m->order);
       std::vector<int64_t> slot(static_cast<size_t>(n));
@@ -1835,7 +1894,6 @@ fr_status fr_probe_create(fr_mesh *m, const fr_mesh_desc *desc, int32_t design, 
           for (int j = 0; j < N; ++j) w[(size_t(i) * dim + k) * N + j] = l[j];
         }
       }
-      hip_check(hipSetDevice(m->device), "hipSetDevice");
       hip_check(hipMalloc(&p->slot, slot.size() * sizeof(int64_t)), "probe alloc");
       hip_check(hipMalloc(&p->w, w.size() * sizeof(double)), "probe alloc");
       hip_check(hipMalloc(&p->out, size_t(n) * m->dm.nv * sizeof(double)), "probe alloc");
@@ -1880,9 +1938,16 @@ fr_status fr::probe_run(::fr_probe *p, bool wait, ProbeRun *out) {
     fr_mesh *m = p->m;
     if (!m->state_set) fail(FR_E_STATE, "no state set");
     hip_check(hipSetDevice(m->device), "hipSetDevice");
-    hip_check(launch_probe(m->cfg, m->a, p->n, p->slot, p->w, p->out), "probe kernel");
+    if (m->mixed()) {
+      for (const auto &q : p->parts) {
+        const fr_mesh &G = *m->groups[size_t(q.group)];
+        hip_check(launch_probe(G.cfg, G.a, q.n, q.slot, q.w, q.dst, p->out), "probe kernel");
+      }
+    } else {
+      hip_check(launch_probe(m->cfg, m->a, p->n, p->slot, p->w, nullptr, p->out), "probe kernel");
+    }
     if (wait) hip_check(hipStreamSynchronize(m->stream), "probe sync");
-    *out = ProbeRun{p->out, p->n, m->dm.nv, m->dim, m->gamma, m->stream};
+    *out = ProbeRun{p->out, p->n, m->dim + 2, m->dim, m->gamma, m->stream};
   });
 }
 
@@ -1897,6 +1962,11 @@ fr_status fr::means_clear(::fr_mesh *m) {
   return guarded([&] {
     if (!m) fail(FR_E_ARG, "null mesh");
     hip_check(hipSetDevice(m->device), "hipSetDevice");
+    if (m->mixed()) {  // every order group keeps its own wall sums
+      for (auto &G : m->groups)
+        hip_check(hipMemsetAsync(G->a.fsum, 0, G->designs.size() * 8 * sizeof(double), m->stream), "clear sums");
+      return;
+    }
     hip_check(hipMemsetAsync(m->a.fsum, 0, m->designs.size() * 8 * sizeof(double), m->stream), "clear sums");
   });
 }

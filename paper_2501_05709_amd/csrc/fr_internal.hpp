@@ -126,8 +126,9 @@ struct MortarSrc {
 hipError_t launch_mortar_gather(int prec, int nv, int64_t r0, int64_t r1, const int *row_out, const int *row_off,
                                 const int *ent_grp, const int *ent_code, const double *ent_w, MortarSrc src,
                                 const void *compact, void *out, double sign, hipStream_t stream);
+// dst (may be null): output row of each point, else the point's own index
 hipError_t launch_probe(const LaunchCfg &c, const DevArrays &a, int64_t n, const int64_t *slot, const double *w,
-                        double *out);
+                        const int64_t *dst, double *out);
 
 // Message returned by fr_last_error() for the calling thread (fr_host.cpp).
 void set_last_error(const char *msg);

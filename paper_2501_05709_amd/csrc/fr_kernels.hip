@@ -1458,7 +1458,8 @@ __global__ void k_clear_flag(int *flag) {
 // Gauss-Legendre solution points at the point's reference coordinates
 template <typename T, int DIM, int ORDER>
 __global__ __launch_bounds__(256) void k_probe(KArgs<T> a, int64_t n, const int64_t *__restrict__ slot,
-                                               const double *__restrict__ w, double *__restrict__ out) {
+                                               const double *__restrict__ w, const int64_t *__restrict__ dst,
+                                               double *__restrict__ out) {
   using S = Shape<DIM, ORDER>;
   constexpr int N = S::N, NV = S::NV;
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1477,16 +1478,17 @@ __global__ __launch_bounds__(256) void k_probe(KArgs<T> a, int64_t n, const int6
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] += wt * double(a.U[at(blk, i, v, e, S::NUP, NV)]);
       }
+  const int64_t o = dst ? dst[p] : p;  // row of the output (points of several order groups)
 #pragma unroll
-  for (int v = 0; v < NV; ++v) out[p * NV + v] = acc[v];
+  for (int v = 0; v < NV; ++v) out[o * NV + v] = acc[v];
 }
 
 template <typename T, int DIM, int ORDER>
 static hipError_t probe_t(const LaunchCfg &c, const DevArrays &d, int64_t n, const int64_t *slot, const double *w,
-                          double *out) {
+                          const int64_t *dst, double *out) {
   KArgs<T> a = make_args<T>(c, d);
   hipLaunchKernelGGL((k_probe<T, DIM, ORDER>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, c.stream, a, n, slot,
-                     w, out);
+                     w, dst, out);
   return hipGetLastError();
 }
 
@@ -1675,8 +1677,8 @@ hipError_t launch_pack(const LaunchCfg &c, const DevArrays &a, bool to_dev, void
 }
 
 hipError_t launch_probe(const LaunchCfg &c, const DevArrays &a, int64_t n, const int64_t *slot, const double *w,
-                        double *out) {
-  FR_DISPATCH(probe_t, c, a, n, slot, w, out);
+                        const int64_t *dst, double *out) {
+  FR_DISPATCH(probe_t, c, a, n, slot, w, dst, out);
 }
 
 hipError_t launch_force_reduce(const LaunchCfg &c, const DevArrays &a) {

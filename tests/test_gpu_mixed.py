@@ -15,10 +15,11 @@ bit-identical to its solo run.
 import numpy as np
 import pytest
 
+from oracle import probe as oprobe
 from oracle.oracle import OracleMesh
 from paper_2501_05709_amd import _lib
 from paper_2501_05709_amd import workloads as W
-from paper_2501_05709_amd.solver import FRMesh, FRPool, Probe
+from paper_2501_05709_amd.solver import FRMesh, FRPool, FWH, Probe
 
 pytestmark = pytest.mark.gpu
 
@@ -190,6 +191,69 @@ def test_mixed_pool_request_bit_identical_to_solo():
     assert np.array_equal(u, g.get_state()) and np.array_equal(out, g.forces())
 
 
+def test_mixed_probe_matches_oracle():
+    """Sampling the P3-P0 O-grid at points spread over all four order rings."""
+    m = ogrid()
+    o = OracleMesh(m)
+    g = FRMesh(m, "fp64")
+    u = state(o, m)
+    g.set_state(u)
+    rng = np.random.default_rng(5)
+    r = rng.uniform(0.7, 19.0, 80)
+    th = rng.uniform(0, 2 * np.pi, 80)
+    pts = np.stack([0.5 + r * np.cos(th), r * np.sin(th), rng.uniform(0.01, 0.19, 80)], axis=1)
+    pr = Probe(g, pts)
+    elem, xi = pr.locate()
+    e_o, xi_o = oprobe.locate(m, pts)
+    assert np.array_equal(elem, e_o) and np.abs(xi - xi_o).max() < 1e-12
+    assert len(set(m["orders"][elem])) == 4
+    got = pr.sample()
+    want = oprobe.sample(u, m["orders"], e_o, xi_o, 3)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_mixed_sampled_pool_request_matches_hand_driven_pipeline():
+    """A served request on a variable-order mesh samples its data surface and feeds the
+    FW-H record on the device: bit-identical to FRMesh + Probe + FWH driven by hand."""
+    m = ogrid(seed=6, ni=16, nj=8, nk=1)
+    # panels in every order ring, at one chordwise station, heard from far along the span
+    # (so that the spread of arrival times stays below the record's length)
+    ys = np.array([0.45, 5.0, 10.0, 16.0])
+    surf_pts = np.array([(x, sg * y, 0.1) for x in (0.4, 0.6) for y in ys for sg in (1.0, -1.0)])
+    nrm = np.zeros_like(surf_pts)
+    nrm[:, 1] = np.sign(surf_pts[:, 1])
+    surf = dict(points=surf_pts, normals=nrm, areas=np.full(len(surf_pts), 0.16 * 0.2), n_copies=3,
+                copy_shift=(0.0, 0.0, 0.2))
+    warmup, every, n_samples = 5, 4, 120
+    g = FRMesh(m, "fp32")
+    fs = m["freestream"]
+    u0 = W.uniform_state(g.n_points, fs[0], fs[1:4], fs[4])
+    pool = FRPool(4 << 30)
+    slot = pool.admit_sampled(m, surf, warmup, every, n_samples, precision="fp32", u0=u0)
+    done = []
+    while not done:
+        done = pool.tick(9)
+    xo = np.array([0.5, 0.0, 500.0])
+    t0, p = pool.pressure(slot, xo, n_samples)
+    f = pool.result(slot)
+    pool.close()
+    g.set_state(u0)
+    g.step(warmup)
+    g.set_state(g.get_state())
+    pr = Probe(g, surf_pts)
+    c0 = np.sqrt(1.4 * fs[4] / fs[0])
+    rec = FWH(surf_pts, nrm, surf["areas"], fs[1:4] / c0, c0, fs[0], fs[4], every * m["dt"], n_samples,
+              n_copies=3, copy_shift=(0.0, 0.0, 0.2))
+    rec.append_probe(pr)
+    for _ in range(n_samples - 1):
+        g.step(every)
+        rec.append_probe(pr)
+    t_ref, p_ref = rec.pressure(xo)
+    assert len(set(m["orders"][pr.locate()[0]])) == 4
+    assert p.size > 5 and t0 == t_ref[0] and np.array_equal(p, p_ref)
+    assert np.array_equal(f, g.forces())
+
+
 def test_mixed_unsupported_calls_are_rejected():
     m = box(2, 1, 0.0, 1, 5, False)
     g = FRMesh(m, "fp64")
@@ -198,9 +262,6 @@ def test_mixed_unsupported_calls_are_rejected():
     assert e.value.code == _lib.FR_E_UNSUPPORTED
     with pytest.raises(_lib.FRError) as e:
         g.neighbours()
-    assert e.value.code == _lib.FR_E_UNSUPPORTED
-    with pytest.raises(_lib.FRError) as e:
-        Probe(g, np.array([[0.5, 0.5, 0.0]]))
     assert e.value.code == _lib.FR_E_UNSUPPORTED
     with pytest.raises(_lib.FRError) as e:
         FRMesh([m, m], "fp64")

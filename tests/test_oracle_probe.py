@@ -70,3 +70,34 @@ def test_solution_points_return_nodal_values(name):
     got = probe.sample(u, m["order"], elem, xi, m["dim"])
     assert np.array_equal(elem, np.repeat(es, o.nu))
     assert np.allclose(got, np.concatenate([u[e] for e in es]), rtol=0, atol=1e-10)
+
+
+def test_variable_order_state_is_exact():
+    """Per-element orders 0..4 on an affine box: a field that is a polynomial of degree
+    <= p_e in each coordinate inside element e (here: each element's own polynomial of
+    its order, discontinuous across elements) is reproduced exactly at any point."""
+    m = W.box_mesh(3, (3, 2, 2), (0.0, 0.0, 0.0), (1.2, 1.0, 0.8), q=1, order=4)
+    rng = np.random.default_rng(7)
+    E = len(m["elem_nodes"])
+    orders = rng.integers(0, 5, size=E).astype(np.int32)
+    mm = dict(m, orders=orders, gamma=1.4, prandtl=0.72, mu=0.0, freestream=np.array([1.0, 0, 0, 0, 1.0]), dt=1e-3)
+    o = OracleMesh(mm)
+    x = o.solution_points()
+    off = np.concatenate([[0], np.cumsum((orders + 1) ** 3)])
+    coefs = [rng.normal(size=(5, 3, int(p) + 1)) for p in orders]
+
+    def field(e, p):
+        out = np.zeros(p.shape[:-1] + (5,))
+        for v in range(5):
+            val = np.ones(p.shape[:-1])
+            for k in range(3):
+                val = val * np.polynomial.polynomial.polyval(p[..., k], coefs[e][v, k])
+            out[..., v] = val
+        return out
+
+    u = np.concatenate([field(e, x[off[e]:off[e + 1]]) for e in range(E)])
+    pts = np.array([1.2, 1.0, 0.8]) * rng.uniform(0.02, 0.98, size=(60, 3))
+    elem, xi = probe.locate(mm, pts)
+    got = probe.sample(u, orders, elem, xi, 3)
+    want = np.array([field(int(e), p) for e, p in zip(elem, pts)])
+    assert np.allclose(got, want, rtol=1e-11, atol=1e-11)
