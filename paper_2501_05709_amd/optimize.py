@@ -107,6 +107,9 @@ class Study:
     budget_bytes: int = 200 << 30
     chunk: int = 50              # steps per pool tick
     device: int = 0
+    # variable order (Section 3.1): ((first layer beyond the band, order), ...) from the
+    # wall outward, e.g. ((12, 3), (24, 2), (36, 1), (48, 0)); None: `order` everywhere
+    bands: tuple = None
 
     def observer(self):
         return np.array([1.0, -10.0, 0.5 * self.span])
@@ -116,6 +119,8 @@ class Study:
         mesh = W.naca_ogrid(m, pc, t, self.ni, self.nj, self.nk, span=self.span, radius=self.radius,
                             order=self.order)
         mesh.update(W.airfoil_flow(aoa_deg=aoa, span=self.span))
+        if self.bands is not None:
+            mesh["orders"] = W.ring_orders(self.ni, self.nj, self.nk, self.bands)
         mesh["dt"] = W.airfoil_dt(mesh, self.order) * self.dt_safety if dt is None else dt
         return mesh
 

@@ -146,6 +146,20 @@ def test_concurrent_designs_bit_identical_to_solo_runs():
     print(f"  one request holds {one / 2**20:.1f} MiB; OASPL {[round(r.oaspl, 3) for r in together]}", flush=True)
 
 
+def test_variable_order_designs_run_concurrently_as_alone():
+    """The paper's P-distribution (P3 at the wall down to P0 outside) in the evaluator:
+    designs run side by side give the outcomes each gives alone."""
+    st = tiny(n_samples=128, warmup=10, every=8, nj=8, bands=((2, 3), (4, 2), (6, 1), (8, 0)))
+    designs = [X, [0.0, 6.5, 12.0, 6.0]]
+    ev = O.PoolEvaluator(st, X)
+    together = ev(designs)
+    alone = [ev([d])[0] for d in designs]
+    ev.close()
+    assert ev.max_running == 2
+    for a, b in zip(together, alone):
+        assert a.ok and (a.oaspl, a.cl, a.cd) == (b.oaspl, b.cl, b.cd)
+
+
 def test_orthomads_over_the_pool_follows_algorithm_1():
     st = tiny(n_samples=128, warmup=10, every=8)
     x0 = np.array([0.0, 6.5, 12.0, 6.0])      # NACA 0012 at 6 degrees
