@@ -12,8 +12,11 @@
 //                 the panel's integrands at the window's observer times, as one 8-tap
 //                 stencil over its series (cubic interpolation in source time composed
 //                 with the fourth-order time derivative), weighted by the panel's
-//                 geometric factors; partial sums per panel chunk
-//   k_fwh_reduce  per observer time: the partial sums in fixed chunk order
+//                 geometric factors; the copies of a panel share its series, so their
+//                 stencils are first added into one filter per series; partial sums per
+//                 panel chunk
+//   k_fwh_reduce_groups, k_fwh_reduce
+//                 per observer time: the partial sums in fixed chunk order, in two levels
 // Because the surface and the observer are stationary and the observer times are spaced
 // by the sampling interval, each panel's fractional delay and hence its stencil weights
 // are the same for every observer time: the sum is a delay-and-sum over the series.
@@ -21,6 +24,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -174,78 +178,175 @@ struct Window {
   double t_end;  // end of the common window (the grid's last time is at most this)
 };
 
+// Stencil of copy c of panel j: the 8 weights per source series (cubic interpolation in
+// source time composed with the fourth-order derivative, times the geometric factors of
+// the thickness and loading integrands and the panel area, Appendix B) applied to the
+// samples from the returned index (relative to observer time 0) on.
+__device__ inline int64_t copy_stencil(const double *geo, int64_t j, int c, int ncopy, const Geo3 &g, const Stream &s,
+                                       const Window &w, double area, double *wt) {
+  const int64_t nv = w.nt - 4;  // samples with a time derivative
+  double y[3];
+  panel_position(geo, j, c, ncopy, g.shift, y);
+  const Radii r = radii(g.xo, y, s);
+  // position of observer time 0 among the panel's derivative-bearing samples; the clamp
+  // keeps every stencil inside the record (it only absorbs rounding)
+  const double pos0 = (w.t_start - w.tau0 - r.R / s.c0) / w.dt - 2.0;
+  int64_t i0 = int64_t(floor(pos0));
+  const int64_t i0max = nv - 3 - (w.n_out - 1);
+  i0 = i0 > i0max ? i0max : i0;
+  i0 = i0 < 1 ? 1 : i0;
+  if (wt) {
+    const double MR = s.mach[0] * r.gR[0] + s.mach[1] * r.gR[1] + s.mach[2] * r.gR[2];
+    const double MRs = s.mach[0] * r.gRs[0] + s.mach[1] * r.gRs[1] + s.mach[2] * r.gRs[2];
+    double a[NQ], b[NQ];
+    a[0] = area * (1.0 - MR) / r.Rs;            // x Qdot
+    b[0] = -area * s.c0 * MRs / (r.Rs * r.Rs);  // x Q
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      a[1 + i] = area * r.gR[i] / (s.c0 * r.Rs);   // x Ldot_i
+      b[1 + i] = area * r.gRs[i] / (r.Rs * r.Rs);  // x L_i
+    }
+    const double sf = pos0 - double(i0);
+    // cubic Lagrange weights (nodes -1..2) and their composition with the fourth-order
+    // derivative (1, -8, 0, 8, -1) / 12 dt: 8 taps from sample i0 - 1
+    const double l[4] = {-sf * (sf - 1.0) * (sf - 2.0) / 6.0, (sf + 1.0) * (sf - 1.0) * (sf - 2.0) / 2.0,
+                         -(sf + 1.0) * sf * (sf - 2.0) / 2.0, (sf + 1.0) * sf * (sf - 1.0) / 6.0};
+    double wv[8], wd[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) wv[d] = wd[d] = 0.0;
+    const double fd[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
+    const double idt = 1.0 / (12.0 * w.dt);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      wv[u + 2] += l[u];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) wd[u + v] += l[u] * fd[v] * idt;
+    }
+#pragma unroll
+    for (int x = 0; x < NQ; ++x)
+#pragma unroll
+      for (int d = 0; d < 8; ++d) wt[x * 8 + d] = a[x] * wd[d] + b[x] * wv[d];
+  }
+  return i0 - 1;
+}
+
 // Thickness and loading integrands of every copy and panel of one chunk at the observer
 // times of one time chunk, summed; partial sums per chunk: part[chunk][2][n_out].
-// Per panel of the chunk, its copies go in batches of SUM_PAIRS: one thread per copy
-// forms the copy's stencil weights into LDS; the workgroup stages the stretch of the
-// panel's four series that the batch's stencils touch over the time chunk (the copies'
-// delays shift it by up to the spread of the batch), and every thread applies each
-// copy's weights to its SUM_OUT consecutive observer times out of LDS.
+// All copies of a panel carry the same sample series, so their stencils add up to one
+// filter per series over the copies' delay spread: H[x][k] = sum over copies c and taps d
+// with b_c - b_min + d = k of the copy's weight (b_c its first sample).  Per panel the
+// workgroup (1) finds the copies' first samples, (2) forms H in LDS, the copies' weights
+// going through LDS in batches of SUM_PAIRS and each thread owning filter taps (summed
+// in copy order), (3) stages the stretch of the four series that the time chunk needs
+// and applies H to each thread's SUM_OUT consecutive observer times.  This does
+// (spread + 8) instead of 8 x copies multiply-adds per output; a panel whose copies'
+// delays spread over more than HMAX - 8 samples is summed copy by copy instead.
+constexpr int HMAX = 256 + 8;
+
 __global__ __launch_bounds__(SUM_WG) void k_fwh_sum(const double *__restrict__ src, const double *__restrict__ geo,
                                                     int64_t np, int64_t cap, int ncopy, Geo3 g, Stream s, Window w,
                                                     double *__restrict__ part) {
   __shared__ double Wt[SUM_PAIRS][NQ * 8];
   __shared__ int64_t Wb[SUM_PAIRS];
-  __shared__ double Xs[NQ][SUM_SPAN];
+  // one source series at a time; the combined-filter path stores sample e at
+  // (e % SUM_OUT) * XQ + e / SUM_OUT, so that the lanes of a wave, SUM_OUT samples apart,
+  // read consecutive words
+  constexpr int XQ = SUM_SPAN / SUM_OUT + 2;
+  __shared__ double Xs[1][SUM_OUT * XQ];
+  __shared__ double H[NQ][HMAX];
+  __shared__ int64_t red_lo[SUM_WG], red_hi[SUM_WG];
   __shared__ int64_t lo_s, hi_s;
   const int64_t chunk = blockIdx.y;
   const int tid = threadIdx.x;
   const int64_t mt0 = int64_t(blockIdx.x) * SUM_WG * SUM_OUT;  // first observer time of the chunk
   const int64_t m0 = mt0 + int64_t(tid) * SUM_OUT;
   const int64_t mlast = (mt0 + SUM_WG * SUM_OUT < w.n_out ? mt0 + SUM_WG * SUM_OUT : w.n_out) - 1;
-  const int64_t nv = w.nt - 4;  // samples with a time derivative
   double accT[SUM_OUT], accL[SUM_OUT];
 #pragma unroll
   for (int o = 0; o < SUM_OUT; ++o) accT[o] = accL[o] = 0.0;
   const int64_t j0 = chunk * SUM_PANELS, j1 = j0 + SUM_PANELS < np ? j0 + SUM_PANELS : np;
   for (int64_t j = j0; j < j1; ++j) {
     const double area = geo[j * 7 + 6];
+    // (1) first samples of all copies: their minimum and maximum
+    int64_t blo = INT64_MAX, bhi = INT64_MIN;
+    for (int c = tid; c < ncopy; c += SUM_WG) {
+      const int64_t b = copy_stencil(geo, j, c, ncopy, g, s, w, area, nullptr);
+      blo = b < blo ? b : blo;
+      bhi = b > bhi ? b : bhi;
+    }
+    red_lo[tid] = blo;
+    red_hi[tid] = bhi;
+    __syncthreads();
+    for (int h = SUM_WG / 2; h > 0; h >>= 1) {
+      if (tid < h) {
+        red_lo[tid] = red_lo[tid + h] < red_lo[tid] ? red_lo[tid + h] : red_lo[tid];
+        red_hi[tid] = red_hi[tid + h] > red_hi[tid] ? red_hi[tid + h] : red_hi[tid];
+      }
+      __syncthreads();
+    }
+    const int64_t bmin = red_lo[0], bmax = red_hi[0];
+    const int nh = int(bmax - bmin) + 8;  // taps of the combined filter
+    __syncthreads();
+    if (nh <= HMAX) {
+      // (2) combined filter
+      for (int t = tid; t < NQ * HMAX; t += SUM_WG) H[t / HMAX][t % HMAX] = 0.0;
+      for (int c0 = 0; c0 < ncopy; c0 += SUM_PAIRS) {
+        const int nb = ncopy - c0 < SUM_PAIRS ? ncopy - c0 : SUM_PAIRS;
+        if (tid < nb) Wb[tid] = copy_stencil(geo, j, c0 + tid, ncopy, g, s, w, area, Wt[tid]) - bmin;
+        __syncthreads();
+        for (int k = tid; k < nh; k += SUM_WG) {
+          double hx[NQ];
+#pragma unroll
+          for (int x = 0; x < NQ; ++x) hx[x] = H[x][k];
+          for (int p = 0; p < nb; ++p) {
+            const int64_t d = int64_t(k) - Wb[p];
+            if (d >= 0 && d < 8) {
+#pragma unroll
+              for (int x = 0; x < NQ; ++x) hx[x] += Wt[p][x * 8 + d];
+            }
+          }
+#pragma unroll
+          for (int x = 0; x < NQ; ++x) H[x][k] = hx[x];
+        }
+        __syncthreads();
+      }
+      // (3) each series over [bmin + mt0, bmax + mlast + 8) in turn, then the filter
+      const int64_t lo = bmin + mt0, span = int64_t(nh - 8) + (mlast - mt0) + 8;
+      for (int x = 0; x < NQ; ++x) {
+        for (int64_t k = tid; k < span; k += SUM_WG)
+          Xs[0][int(k % SUM_OUT) * XQ + int(k / SUM_OUT)] = src[(x * np + j) * cap + lo + k];
+        __syncthreads();
+        if (m0 <= mlast) {
+          // this thread's samples start at tid * SUM_OUT; its window holds SUM_OUT of them
+          double win[SUM_OUT], acc[SUM_OUT];
+#pragma unroll
+          for (int o = 0; o < SUM_OUT; ++o) {
+            win[o] = Xs[0][o * XQ + tid];
+            acc[o] = 0.0;
+          }
+          for (int k = 0; k < nh; ++k) {
+            const double hk = H[x][k];
+#pragma unroll
+            for (int o = 0; o < SUM_OUT; ++o) acc[o] += hk * win[o];
+#pragma unroll
+            for (int o = 0; o + 1 < SUM_OUT; ++o) win[o] = win[o + 1];
+            // sample tid * SUM_OUT + k + SUM_OUT
+            if (k + 1 < nh) win[SUM_OUT - 1] = Xs[0][(k % SUM_OUT) * XQ + tid + 1 + k / SUM_OUT];
+          }
+#pragma unroll
+          for (int o = 0; o < SUM_OUT; ++o) {
+            if (x == 0) accT[o] += acc[o];
+            else accL[o] += acc[o];
+          }
+        }
+        __syncthreads();
+      }
+      continue;
+    }
+    // copy by copy (delay spread beyond the combined filter)
     for (int c0 = 0; c0 < ncopy; c0 += SUM_PAIRS) {
       const int nb = ncopy - c0 < SUM_PAIRS ? ncopy - c0 : SUM_PAIRS;
-      if (tid < nb) {
-        double y[3];
-        panel_position(geo, j, c0 + tid, ncopy, g.shift, y);
-        const Radii r = radii(g.xo, y, s);
-        // geometric factors of the integrands (Appendix B), times the panel area
-        const double MR = s.mach[0] * r.gR[0] + s.mach[1] * r.gR[1] + s.mach[2] * r.gR[2];
-        const double MRs = s.mach[0] * r.gRs[0] + s.mach[1] * r.gRs[1] + s.mach[2] * r.gRs[2];
-        double a[NQ], b[NQ];
-        a[0] = area * (1.0 - MR) / r.Rs;            // x Qdot
-        b[0] = -area * s.c0 * MRs / (r.Rs * r.Rs);  // x Q
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          a[1 + i] = area * r.gR[i] / (s.c0 * r.Rs);   // x Ldot_i
-          b[1 + i] = area * r.gRs[i] / (r.Rs * r.Rs);  // x L_i
-        }
-        // position of observer time 0 among the panel's derivative-bearing samples; the
-        // clamp keeps every stencil inside the record (it only absorbs rounding)
-        const double pos0 = (w.t_start - w.tau0 - r.R / s.c0) / w.dt - 2.0;
-        int64_t i0 = int64_t(floor(pos0));
-        const int64_t i0max = nv - 3 - (w.n_out - 1);
-        i0 = i0 > i0max ? i0max : i0;
-        i0 = i0 < 1 ? 1 : i0;
-        const double sf = pos0 - double(i0);
-        // cubic Lagrange weights (nodes -1..2) and their composition with the
-        // fourth-order derivative (1, -8, 0, 8, -1) / 12 dt: 8 taps from sample i0 - 1
-        const double l[4] = {-sf * (sf - 1.0) * (sf - 2.0) / 6.0, (sf + 1.0) * (sf - 1.0) * (sf - 2.0) / 2.0,
-                             -(sf + 1.0) * sf * (sf - 2.0) / 2.0, (sf + 1.0) * sf * (sf - 1.0) / 6.0};
-        double wv[8], wd[8];
-#pragma unroll
-        for (int d = 0; d < 8; ++d) wv[d] = wd[d] = 0.0;
-        const double fd[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
-        const double idt = 1.0 / (12.0 * w.dt);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          wv[u + 2] += l[u];
-#pragma unroll
-          for (int v = 0; v < 5; ++v) wd[u + v] += l[u] * fd[v] * idt;
-        }
-#pragma unroll
-        for (int x = 0; x < NQ; ++x)
-#pragma unroll
-          for (int d = 0; d < 8; ++d) Wt[tid][x * 8 + d] = a[x] * wd[d] + b[x] * wv[d];
-        Wb[tid] = i0 - 1;
-      }
+      if (tid < nb) Wb[tid] = copy_stencil(geo, j, c0 + tid, ncopy, g, s, w, area, Wt[tid]);
       __syncthreads();
       // stretch of samples the batch touches over this time chunk
       if (tid == 0) {
@@ -261,24 +362,18 @@ __global__ __launch_bounds__(SUM_WG) void k_fwh_sum(const double *__restrict__ s
       const int64_t lo = lo_s, span = hi_s - lo_s;
       // copies whose stretch does not fit are applied straight from global memory
       const bool staged = span <= SUM_SPAN;
-      if (staged) {
-        for (int64_t t = tid; t < NQ * span; t += SUM_WG) {
-          const int x = int(t / span);
-          const int64_t k = t % span;
-          Xs[x][k] = src[(x * np + j) * cap + lo + k];
-        }
-      }
-      __syncthreads();
-      if (m0 < w.n_out) {
-        const bool full = m0 + SUM_OUT <= w.n_out;
-        for (int p = 0; p < nb; ++p) {
-          const int64_t base = Wb[p] + m0;  // sample of tap 0 for observer time m0
-#pragma unroll
-          for (int x = 0; x < NQ; ++x) {
+      for (int x = 0; x < NQ; ++x) {
+        if (staged)
+          for (int64_t k = tid; k < span; k += SUM_WG) Xs[0][k] = src[(x * np + j) * cap + lo + k];
+        __syncthreads();
+        if (m0 < w.n_out) {
+          const bool full = m0 + SUM_OUT <= w.n_out;
+          for (int p = 0; p < nb; ++p) {
+            const int64_t base = Wb[p] + m0;  // sample of tap 0 for observer time m0
             double xs[SUM_OUT + 7];
             const int nvalid = full ? SUM_OUT + 7 : int(w.n_out - m0) + 7;
             if (staged) {
-              const double *X = &Xs[x][base - lo];
+              const double *X = &Xs[0][base - lo];
 #pragma unroll
               for (int d = 0; d < SUM_OUT + 7; ++d) xs[d] = d < nvalid ? X[d] : 0.0;
             } else {
@@ -296,8 +391,8 @@ __global__ __launch_bounds__(SUM_WG) void k_fwh_sum(const double *__restrict__ s
             }
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
 #pragma unroll
@@ -307,6 +402,24 @@ __global__ __launch_bounds__(SUM_WG) void k_fwh_sum(const double *__restrict__ s
     part[(chunk * 2 + 0) * w.n_out + m] = accT[o];
     part[(chunk * 2 + 1) * w.n_out + m] = accL[o];
   }
+}
+
+// first level of the chunk reduction: group g of RED_GROUPS sums its contiguous range of
+// panel chunks, in chunk order, for every observer time: part2[g][2][n_out]
+constexpr int RED_GROUPS = 64;
+__global__ __launch_bounds__(256) void k_fwh_reduce_groups(const double *__restrict__ part, int64_t nchunk,
+                                                           int64_t n_out, double *__restrict__ part2) {
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t g = blockIdx.y;
+  if (m >= n_out) return;
+  const int64_t c0 = g * nchunk / RED_GROUPS, c1 = (g + 1) * nchunk / RED_GROUPS;
+  double t = 0.0, l = 0.0;
+  for (int64_t c = c0; c < c1; ++c) {
+    t += part[(c * 2 + 0) * n_out + m];
+    l += part[(c * 2 + 1) * n_out + m];
+  }
+  part2[(g * 2 + 0) * n_out + m] = t;
+  part2[(g * 2 + 1) * n_out + m] = l;
 }
 
 // p'_T, p'_L and p' at each observer time: partial sums in chunk order, over 4 pi
@@ -337,8 +450,9 @@ struct fr_fwh {
   int ncopy = 1;
   double shift[3] = {0, 0, 0}, dt = 0, tau0 = 0;
   Stream s{};
-  double *geo = nullptr, *src = nullptr, *stage = nullptr, *mm = nullptr, *part = nullptr, *out = nullptr;
-  size_t stage_bytes = 0, part_bytes = 0, out_bytes = 0;
+  double *geo = nullptr, *src = nullptr, *stage = nullptr, *mm = nullptr, *part = nullptr, *part2 = nullptr,
+         *out = nullptr;
+  size_t stage_bytes = 0, part_bytes = 0, part2_bytes = 0, out_bytes = 0;
   std::vector<void *> owned;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
@@ -539,6 +653,7 @@ void fwh_compute(fr_fwh *h, const double *observer, const Window &w, double *p, 
   const int64_t nchunk = (h->np + SUM_PANELS - 1) / SUM_PANELS;
   if (nchunk > 65535) fail(FR_E_UNSUPPORTED, "too many panels for one launch");
   h->grow(h->part, h->part_bytes, size_t(nchunk) * 2 * w.n_out * sizeof(double));
+  h->grow(h->part2, h->part2_bytes, size_t(RED_GROUPS) * 2 * w.n_out * sizeof(double));
   h->grow(h->out, h->out_bytes, size_t(3) * w.n_out * sizeof(double));
   Geo3 g;
   for (int i = 0; i < 3; ++i) {
@@ -551,8 +666,11 @@ void fwh_compute(fr_fwh *h, const double *observer, const Window &w, double *p, 
   hipLaunchKernelGGL(k_fwh_sum, grid, dim3(SUM_WG), 0, h->stream, h->src, h->geo, h->np, h->cap, h->ncopy, g, h->s, w,
                      h->part);
   hip_check(hipGetLastError(), "sum kernel");
-  hipLaunchKernelGGL(k_fwh_reduce, dim3(unsigned((w.n_out + 255) / 256)), dim3(256), 0, h->stream, h->part, nchunk,
-                     w.n_out, h->out);
+  hipLaunchKernelGGL(k_fwh_reduce_groups, dim3(unsigned((w.n_out + 255) / 256), RED_GROUPS), dim3(256), 0, h->stream,
+                     h->part, nchunk, w.n_out, h->part2);
+  hip_check(hipGetLastError(), "reduce kernel");
+  hipLaunchKernelGGL(k_fwh_reduce, dim3(unsigned((w.n_out + 255) / 256)), dim3(256), 0, h->stream, h->part2,
+                     int64_t(RED_GROUPS), w.n_out, h->out);
   hip_check(hipGetLastError(), "reduce kernel");
   hip_check(hipEventRecord(h->ev1, h->stream), "event");
   const size_t nb = size_t(w.n_out) * sizeof(double);
@@ -623,5 +741,6 @@ size_t fr::fwh_footprint(int64_t n_points, int64_t capacity) {
   const size_t nchunk = (np + SUM_PANELS - 1) / SUM_PANELS;
   // geometry, source series, one staged snapshot, delay extremes, and at most a
   // window of capacity observer times of partial sums and outputs
-  return (np * 7 + size_t(NQ) * np * cap + np * 5 + 2 * 64 + nchunk * 2 * cap + 3 * cap) * sizeof(double);
+  return (np * 7 + size_t(NQ) * np * cap + np * 5 + 2 * 64 + nchunk * 2 * cap + size_t(RED_GROUPS) * 2 * cap +
+          3 * cap) * sizeof(double);
 }

@@ -109,3 +109,25 @@ def test_full_size_copies_equal_shifted_observers():
         total += one.pressure_at(x - s, t[0], t.size)
     assert np.isfinite(p).all() and np.abs(p).max() > 0
     assert close(p, total)
+
+
+def test_copies_beyond_the_combined_filter_match_oracle():
+    """Copies whose arrival delays spread over more than 256 samples are summed copy by
+    copy; nearer ones through one combined filter per panel.  Both against the oracle:
+    a monopole sphere with 5 copies 200 apart heard from 20 away (spread about 280
+    samples), and with 5 copies 2.5 apart (spread of a few samples)."""
+    c = W.acoustic_case("monopole", (0.2, 0.0, 0.0), periods=9, n_polar=8, n_azimuth=12)
+    x = np.array([20.0, 3.0, 1.0])
+    for shift in (np.array([0.0, 0.0, 200.0]), np.array([0.0, 0.0, 2.5])):
+        g = FWH(c["points"], c["normals"], c["areas"], c["mach"], c["c0"], c["rho0"], c["p0"], c["dt"],
+                c["rho"].shape[0], n_copies=5, copy_shift=shift)
+        g.append(c["rho"], c["u"], c["p"])
+        t, p = g.pressure(x)
+        to, po, _, _ = fwh.observer_pressure(c["points"], c["normals"], c["areas"], c["rho"], c["u"], c["p"],
+                                             c["dt"], x, c["mach"], c["c0"], c["rho0"], c["p0"], n_copies=5,
+                                             shift=shift)
+        spread = np.ptp(fwh.radii(x[None], (c["points"][None] + fwh.copy_shifts(5, shift)[:, None]).reshape(-1, 3),
+                                  c["mach"])[1]) / c["c0"] / c["dt"]
+        print(f"copies {shift[2]:g} apart: delay spread {spread:.0f} samples, {t.size} observer times", flush=True)
+        assert t.size == to.size and t.size > 10
+        assert close(p, po)
