@@ -728,7 +728,10 @@ template <typename T, int DIM, int ORDER> struct TS {
 // strong-form divergence operator Dv = D - gR' l(+1)^T - gL' l(-1)^T (the
 // derivative of the flux polynomial minus its interpolated face corrections)
 template <typename T, int N> struct Basis {
+  static constexpr int COUNT = 2 * N * N + 4 * N;
   T D[N][N], lm[N], lp[N], gl[N], gr[N], Dv[N][N];
+  // entry t of the members taken in order, the order of the source array
+  __device__ inline void put(int t, T v) { reinterpret_cast<T *>(this)[t] = v; }
   __device__ inline void load(const T *src) {
     for (int t = threadIdx.x; t < 2 * N * N + 4 * N; t += blockDim.x) {
       if (t < N * N) D[t / N][t % N] = src[t];
@@ -738,6 +741,25 @@ template <typename T, int N> struct Basis {
       else if (t < N * N + 4 * N) gr[t - N * N - 3 * N] = src[t];
       else Dv[(t - N * N - 4 * N) / N][(t - N * N - 4 * N) % N] = src[t];
     }
+  }
+};
+
+// The basis of a WG-thread workgroup in registers: issued with the other prefetches
+// (no loop, so the wait before it goes to LDS counts only the loads issued before it)
+template <typename T, int N, int WG> struct BasisRegs {
+  static constexpr int C = Basis<T, N>::COUNT, R = (C + WG - 1) / WG;
+  T v[R];
+  __device__ inline void issue(const T *src, int tid) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[min(tid + r * WG, C - 1)];
+    // keep these loads ahead of every later one: the scheduler would otherwise sink
+    // them to their use, where the in-order wait for them drains all the others
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __device__ inline void store(Basis<T, N> &B, int tid) const {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (tid + r * WG < C) B.put(tid + r * WG, v[r]);
   }
 };
 
@@ -961,60 +983,64 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   if (e0 >= nvalid) return;
   const int tid = threadIdx.x;
 
-  // ---- prefetch in the order of first use: neighbour codes, stage state, normals,
-  // partner traces; the metrics of the solution points go last, so that they stay
-  // in flight through the flux-point pass and the gradient
+  // ---- prefetch in the order of first use: basis, neighbour codes, stage state,
+  // normals, partner traces (once the codes are back); the metrics of the solution
+  // points go last, so that they stay in flight through the flux-point pass and the
+  // gradient. Every load is unconditional, with indices clamped into the block (idle
+  // lanes and empty slots load values that are never used): the wait before a use
+  // then counts exactly the loads issued before it, instead of draining them all.
   constexpr int SI = (S::NU * NV * EW + WG - 1) / WG;
+  BasisRegs<T, N, WG> bas;
+  bas.issue(a.basis, tid);
   int nbv[FI];
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
-    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
-    nbv[it] = -BC_FARFIELD;
-    if (t < S::NF * EW && eg < nvalid) nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
+    const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
+    nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
   }
   T ust[SI];
   const T *Xb = X + size_t(blk) * S::NUP * NV * EB;
 #pragma unroll
   for (int r = 0; r < SI; ++r) {
-    const int t = tid + r * WG;
+    const int t = min(tid + r * WG, S::NU * NV * EW - 1);
     const int e = e0 + t % EW;
-    if (t < S::NU * NV * EW) ust[r] = Xb[(size_t(e / SB) * S::NUP * NV + t / EW) * SB + e % SB];
+    ust[r] = Xb[(size_t(e / SB) * S::NUP * NV + t / EW) * SB + e % SB];
   }
-  T nrm[FI][DIM], ur[FI][NV];
+  double nrd[FI][DIM];
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
-    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
-    if (t < S::NF * EW && eg < nvalid) {
+    const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) nrm[it][c] = T(a.FN[at(blk, q, c, eg, S::NFPAD, DIM)]);
-    }
+    for (int c = 0; c < DIM; ++c) nrd[it][c] = a.FN[at(blk, q, c, eg, S::NFPAD, DIM)];
   }
+  T ur[FI][NV];
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
-    if (nbv[it] >= 0) {
-      const size_t base = size_t(nbv[it] / SB) * NV * SB + (nbv[it] % SB);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) ur[it][v] = a.UF[base + v * SB];
-    } else if (MORTAR && ((-nbv[it]) & 3) == BC_MORTAR) {
+    const int nb = nbv[it];
+    if (MORTAR && nb < 0 && ((-nb) & 3) == BC_MORTAR) {
       // the other side's trace, brought to this point by the mortar gather
-      const size_t base = size_t((-nbv[it]) >> 3) * NV;
+      const size_t base = size_t((-nb) >> 3) * NV;
 #pragma unroll
       for (int v = 0; v < NV; ++v) ur[it][v] = a.MU[base + v];
+    } else {
+      // a boundary code loads slot 0 and never uses it
+      const int p = nb > 0 ? nb : 0;
+      const size_t base = size_t(p / SB) * NV * SB + (p % SB);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ur[it][v] = a.UF[base + v * SB];
     }
   }
   double Sm[PI][DIM][DIM], ijv[PI];
 #pragma unroll
   for (int it = 0; it < PI; ++it) {
-    const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
-    if (t < S::NU * EW && eg < nvalid) {
+    const int t = tid + it * WG, i = min(t / EW, S::NU - 1), eg = e0 + t % EW;
 #pragma unroll
-      for (int k = 0; k < DIM; ++k)
+    for (int k = 0; k < DIM; ++k)
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) Sm[it][k][c] = a.SM[at(blk, i, k * DIM + c, eg, S::NUP, DIM * DIM)];
-      ijv[it] = a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
-    }
+      for (int c = 0; c < DIM; ++c) Sm[it][k][c] = a.SM[at(blk, i, k * DIM + c, eg, S::NUP, DIM * DIM)];
+    ijv[it] = a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
   }
-  B.load(a.basis);
+  bas.store(B, tid);
 #pragma unroll
   for (int r = 0; r < SI; ++r) {
     const int t = tid + r * WG;
@@ -1024,7 +1050,11 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
 
   // ---- faces: own trace, common solution jump (LDS), Rusanov flux (registers)
-  T ufv[FI][NV], fiv[FI][NV];
+  T ufv[FI][NV], fiv[FI][NV], nrm[FI][DIM];
+#pragma unroll
+  for (int it = 0; it < FI; ++it)
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) nrm[it][c] = T(nrd[it][c]);
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
@@ -1238,59 +1268,63 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
   const int tid = threadIdx.x;
   const T dt = T(a.bdt[blk]);
 
-  // ---- prefetch in the order of first use: face inputs (codes first, so that the
-  // partner gather issues early), then the point inputs, which stay in flight
-  // through the flux pass
+  // ---- prefetch in the order of first use: basis, face inputs (codes first, so that
+  // the partner gather issues early), then the point inputs, which stay in flight
+  // through the flux pass. Loads are unconditional, indices clamped into the block, as
+  // in k_stage_a, so that no wait drains more than the loads it needs.
+  BasisRegs<T, N, WG> bas;
+  bas.issue(a.basis, tid);
   int nbv[FI];
   double Av[FI];
   T qv[FI][NV], pn[FI][NV];
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
-    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
-    nbv[it] = -BC_FARFIELD;
-    if (t < S::NF * EW && eg < nvalid) nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
+    const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
+    nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
   }
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
-    const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
-    Av[it] = 0.0;
-    if (t < S::NF * EW && eg < nvalid) {
-      Av[it] = a.FA[lay(blk, q, 0, eg, S::NFPAD, 1)];
+    const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
+    Av[it] = a.FA[lay(blk, q, 0, eg, S::NFPAD, 1)];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) qv[it][v] = a.FI[at(blk, q, v, eg, S::NFPAD, NV)];
-    }
+    for (int v = 0; v < NV; ++v) qv[it][v] = a.FI[at(blk, q, v, eg, S::NFPAD, NV)];
   }
+  // the face inputs, then the partner gather, then the point inputs, in this order:
+  // the flux pass then waits for the face loads only
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
-    if (nbv[it] >= 0) {
-      const size_t base = size_t(nbv[it] / SB) * NV * SB + (nbv[it] % SB);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[base + v * SB];
-    } else if (MORTAR && ((-nbv[it]) & 3) == BC_MORTAR) {
+    const int nb = nbv[it];
+    if (MORTAR && nb < 0 && ((-nb) & 3) == BC_MORTAR) {
       // higher-order side: the other side's half viscous flux; lower-order side: the
       // complete transformed common flux (projected from the higher-order side)
-      const size_t base = size_t((-nbv[it]) >> 3) * NV;
+      const size_t base = size_t((-nb) >> 3) * NV;
 #pragma unroll
       for (int v = 0; v < NV; ++v) pn[it][v] = a.MX[base + v];
+    } else {
+      // a boundary code loads slot 0 and never uses it
+      const int p = nb > 0 ? nb : 0;
+      const size_t base = size_t(p / SB) * NV * SB + (p % SB);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[base + v * SB];
     }
   }
+  __builtin_amdgcn_sched_barrier(0);
   T rv[PI][NV], un[PI][NV], ac[PI][NV];
   double ijv[PI];
 #pragma unroll
   for (int it = 0; it < PI; ++it) {
-    const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
-    if (t < S::NU * EW && eg < nvalid) {
-      ijv[it] = a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
+    const int t = tid + it * WG, i = min(t / EW, S::NU - 1), eg = e0 + t % EW;
+    ijv[it] = a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const size_t x = at(blk, i, v, eg, S::NUP, NV);
-        rv[it][v] = a.FT[x];
-        un[it][v] = mode == MODE_RESID ? T(0) : a.U[x];
-        ac[it][v] = (mode == MODE_RK1 || mode == MODE_RK2 || mode == MODE_RK3) ? a.ACC[x] : T(0);
-      }
+    for (int v = 0; v < NV; ++v) {
+      const size_t x = at(blk, i, v, eg, S::NUP, NV);
+      rv[it][v] = a.FT[x];
+      un[it][v] = mode == MODE_RESID ? T(0) : a.U[x];
+      ac[it][v] = (mode == MODE_RK1 || mode == MODE_RK2 || mode == MODE_RK3) ? a.ACC[x] : T(0);
     }
   }
-  B.load(a.basis);
+  bas.store(B, tid);
 
   // ---- transformed outward common flux A (Q + P_partner), boundary: A Q
 #pragma unroll
