@@ -1270,8 +1270,11 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
 
   // ---- prefetch in the order of first use: basis, face inputs (codes first, so that
   // the partner gather issues early), then the point inputs, which stay in flight
-  // through the flux pass. Loads are unconditional, indices clamped into the block, as
-  // in k_stage_a, so that no wait drains more than the loads it needs.
+  // through the flux pass. In FP32 the face loop has no idle lanes, and loads are
+  // unconditional with indices clamped into the block, as in k_stage_a. In FP64 half
+  // the waves are idle in the last face iteration; there the lanes that hold no flux
+  // point, and the slots past the last element, skip their loads (faster as measured).
+  constexpr bool SKIP = sizeof(T) == 8;
   BasisRegs<T, N, WG> bas;
   bas.issue(a.basis, tid);
   int nbv[FI];
@@ -1280,18 +1283,18 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
-    nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
+    nbv[it] = -BC_FARFIELD;
+    if (!SKIP || (t < S::NF * EW && eg < nvalid)) nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
   }
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
-    Av[it] = a.FA[lay(blk, q, 0, eg, S::NFPAD, 1)];
+    if (!SKIP || (t < S::NF * EW && eg < nvalid)) {
+      Av[it] = a.FA[lay(blk, q, 0, eg, S::NFPAD, 1)];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) qv[it][v] = a.FI[at(blk, q, v, eg, S::NFPAD, NV)];
+      for (int v = 0; v < NV; ++v) qv[it][v] = a.FI[at(blk, q, v, eg, S::NFPAD, NV)];
+    }
   }
-  // the face inputs, then the partner gather, then the point inputs, in this order:
-  // the flux pass then waits for the face loads only
-  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     const int nb = nbv[it];
@@ -1301,27 +1304,28 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
       const size_t base = size_t((-nb) >> 3) * NV;
 #pragma unroll
       for (int v = 0; v < NV; ++v) pn[it][v] = a.MX[base + v];
-    } else {
-      // a boundary code loads slot 0 and never uses it
+    } else if (!SKIP || nb >= 0) {
+      // unconditional form: a boundary code loads slot 0 and never uses it
       const int p = nb > 0 ? nb : 0;
       const size_t base = size_t(p / SB) * NV * SB + (p % SB);
 #pragma unroll
       for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[base + v * SB];
     }
   }
-  __builtin_amdgcn_sched_barrier(0);
   T rv[PI][NV], un[PI][NV], ac[PI][NV];
   double ijv[PI];
 #pragma unroll
   for (int it = 0; it < PI; ++it) {
     const int t = tid + it * WG, i = min(t / EW, S::NU - 1), eg = e0 + t % EW;
-    ijv[it] = a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
+    if (!SKIP || (t < S::NU * EW && eg < nvalid)) {
+      ijv[it] = a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const size_t x = at(blk, i, v, eg, S::NUP, NV);
-      rv[it][v] = a.FT[x];
-      un[it][v] = mode == MODE_RESID ? T(0) : a.U[x];
-      ac[it][v] = (mode == MODE_RK1 || mode == MODE_RK2 || mode == MODE_RK3) ? a.ACC[x] : T(0);
+      for (int v = 0; v < NV; ++v) {
+        const size_t x = at(blk, i, v, eg, S::NUP, NV);
+        rv[it][v] = a.FT[x];
+        un[it][v] = mode == MODE_RESID ? T(0) : a.U[x];
+        ac[it][v] = (mode == MODE_RK1 || mode == MODE_RK2 || mode == MODE_RK3) ? a.ACC[x] : T(0);
+      }
     }
   }
   bas.store(B, tid);
