@@ -56,7 +56,10 @@ def case(name):
         m.update(gamma=1.4, prandtl=0.72, mu=0.02, freestream=np.array([1.0, 0.3, -0.2, 0.0, 1.0]), dt=1e-3)
         return m
     if name.startswith("tgv"):
-        nel, order = {"tgv_p1": (6, 1), "tgv_p2": (5, 2), "tgv_p3": (4, 3), "tgv_p4": (3, 4)}[name]
+        # tgv_p3_one: a single periodic element, its own partner on every face, in a
+        # workgroup whose other slots are empty; tgv_p2_two: 8 elements, half a block
+        nel, order = {"tgv_p1": (6, 1), "tgv_p2": (5, 2), "tgv_p3": (4, 3), "tgv_p4": (3, 4),
+                      "tgv_p3_one": (1, 3), "tgv_p2_two": (2, 2)}[name]
         return W.config_tgv(nel=nel, order=order)
     if name == "airfoil_p3":
         return W.config_airfoil(1, ni=24, nj=5, nk=2)
@@ -65,7 +68,8 @@ def case(name):
     raise KeyError(name)
 
 
-CASES = ["vortex2d_p3", "box2d_curved_p2", "tgv_p1", "tgv_p2", "tgv_p3", "tgv_p4", "airfoil_p3", "airfoil_p2"]
+CASES = ["vortex2d_p3", "box2d_curved_p2", "tgv_p1", "tgv_p2", "tgv_p3", "tgv_p4", "tgv_p3_one", "tgv_p2_two",
+         "airfoil_p3", "airfoil_p2"]
 # kernel structures / operator back-ends: five launches per stage with dense
 # element-batched MFMA contractions or sum factorisation, or the fused
 # two-launch stage (sum factorised)
