@@ -334,8 +334,9 @@ def bench_fwh(args):
     npan = case["points"].shape[0]
     work = float(n) * npan * t.size                      # (copy, panel, observer time) triples
     k_ms = float(np.mean(ms))
-    # the kernel sums each panel's copies through one filter of (delay spread + 8) taps per
-    # source series: its flops are 2 x 4 series x taps per (panel, observer time)
+    # each panel's copies are summed through one filter of (delay spread + 8) taps per source
+    # series: 2 x 4 series x taps flops per (panel, observer time), priced against the time
+    # of the whole evaluation (forming the filters, applying them, the chunk reductions)
     taps = combined_filter_taps(case, x, t[0])
     flops = 8.0 * float(taps.sum()) * t.size
     # oracle on a bounded sample: one copy of one spanwise row of panels, all samples
@@ -372,7 +373,7 @@ def bench_fwh(args):
         "wall_ms_per_step": round(wall * 1e3, 3), "append_s": round(t_app, 3),
         "roofline": {"bound": "alu", "achieved": round(flops / (k_ms * 1e-3) / 1e12, 2), "peak": PEAK["fp64"],
                      "unit": "TFLOP/s", "frac": round(flops / (k_ms * 1e-3) / 1e12 / PEAK["fp64"], 4),
-                     "kernel": "k_fwh_sum", "traffic": None,
+                     "kernel": "one evaluation: k_fwh_filter + k_fwh_sum + reductions", "traffic": None,
                      "flops": "8 x (copies' delay spread + 8) per panel and observer time",
                      "mean_taps_per_panel": round(float(taps.mean()), 1),
                      "copy_by_copy_equivalent_tflops": round(64.0 * work / (k_ms * 1e-3) / 1e12, 2)},

@@ -359,7 +359,8 @@ fr_status fr_fwh_pressure_at(fr_fwh *h, const double *observer, double t_start, 
                              double *p_thickness, double *p_loading);
 
 /* Device time (ms) of the last fr_fwh_pressure or fr_fwh_pressure_at (HIP
- * events on its stream around the summation kernels). */
+ * events on its stream around the per-panel filter, summation and reduction
+ * kernels). */
 fr_status fr_fwh_time_ms(const fr_fwh *h, double *ms);
 
 /* ---- Served requests with a data surface -------------------------------

@@ -8,13 +8,13 @@
 // contiguous.  For one observer:
 //   k_fwh_delay   per (copy, panel): arrival delay R / c0; per-block min and max
 //   (host)        the common observer-time window from the extreme delays
-//   k_fwh_sum     per (panel chunk, time chunk): for every copy and panel of the chunk,
-//                 the panel's integrands at the window's observer times, as one 8-tap
-//                 stencil over its series (cubic interpolation in source time composed
-//                 with the fourth-order time derivative), weighted by the panel's
-//                 geometric factors; the copies of a panel share its series, so their
-//                 stencils are first added into one filter per series; partial sums per
-//                 panel chunk
+//   k_fwh_filter  per panel: every copy's integrands at the window's observer times are
+//                 one 8-tap stencil over the panel's series (cubic interpolation in source
+//                 time composed with the fourth-order time derivative), weighted by the
+//                 panel's geometric factors; the copies share the panel's series, so their
+//                 stencils add up to one filter per series, formed once per evaluation
+//   k_fwh_sum     per (panel chunk, time chunk): each panel's filters applied to its
+//                 series at the chunk's observer times; partial sums per panel chunk
 //   k_fwh_reduce_groups, k_fwh_reduce
 //                 per observer time: the partial sums in fixed chunk order, in two levels
 // Because the surface and the observer are stationary and the observer times are spaced
@@ -230,31 +230,99 @@ __device__ inline int64_t copy_stencil(const double *geo, int64_t j, int c, int 
   return i0 - 1;
 }
 
-// Thickness and loading integrands of every copy and panel of one chunk at the observer
-// times of one time chunk, summed; partial sums per chunk: part[chunk][2][n_out].
 // All copies of a panel carry the same sample series, so their stencils add up to one
 // filter per series over the copies' delay spread: H[x][k] = sum over copies c and taps d
-// with b_c - b_min + d = k of the copy's weight (b_c its first sample).  Per panel the
-// workgroup (1) finds the copies' first samples, (2) forms H in LDS, the copies' weights
-// going through LDS in batches of SUM_PAIRS and each thread owning filter taps (summed
-// in copy order), (3) stages the stretch of the four series that the time chunk needs
-// and applies H to each thread's SUM_OUT consecutive observer times.  This does
-// (spread + 8) instead of 8 x copies multiply-adds per output; a panel whose copies'
-// delays spread over more than HMAX - 8 samples is summed copy by copy instead.
+// with b_c - b_min + d = k of the copy's weight (b_c its first sample).  k_fwh_filter forms
+// H once per panel and evaluation: (1) the copies' first samples and their extremes,
+// (2) H in LDS, the copies' weights going through LDS in batches of SUM_PAIRS and each
+// thread owning filter taps (summed in copy order).  k_fwh_sum then, per panel of its
+// chunk, (3) stages the stretch of the four series that its time chunk needs and applies
+// H to each thread's SUM_OUT consecutive observer times.  This does (spread + 8) instead
+// of 8 x copies multiply-adds per output; a panel whose copies' delays spread over more
+// than HMAX - 8 samples is summed copy by copy instead.
 constexpr int HMAX = 256 + 8;
+// filter rows padded to whole blocks of 4 taps (the taps past nh stay zero)
+constexpr int HROW = (HMAX + 3) / 4 * 4 + 4;
+static_assert(SUM_OUT == 4, "the filter loop below takes taps in blocks of SUM_OUT = 4");
 
+// Per panel, once per evaluation (the same for every time chunk): the first sample of
+// each copy, their minimum b_min, and the combined filter of the copies, filt[j][x][k]
+// for x < NQ, k < HROW (zero past nh); meta[j] = {b_min, nh}, nh = -1 when the copies'
+// delays spread over more than HMAX - 8 samples (that panel is summed copy by copy).
+__global__ __launch_bounds__(SUM_WG) void k_fwh_filter(const double *__restrict__ geo, int64_t np, int ncopy, Geo3 g,
+                                                       Stream s, Window w, double *__restrict__ filt,
+                                                       int64_t *__restrict__ meta) {
+  __shared__ double Wt[SUM_PAIRS][NQ * 8];
+  __shared__ int64_t Wb[SUM_PAIRS];
+  __shared__ double H[NQ][HROW];
+  __shared__ int64_t red_lo[SUM_WG], red_hi[SUM_WG];
+  const int64_t j = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double area = geo[j * 7 + 6];
+  // (1) first samples of all copies: their minimum and maximum
+  int64_t blo = INT64_MAX, bhi = INT64_MIN;
+  for (int c = tid; c < ncopy; c += SUM_WG) {
+    const int64_t b = copy_stencil(geo, j, c, ncopy, g, s, w, area, nullptr);
+    blo = b < blo ? b : blo;
+    bhi = b > bhi ? b : bhi;
+  }
+  red_lo[tid] = blo;
+  red_hi[tid] = bhi;
+  __syncthreads();
+  for (int h = SUM_WG / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      red_lo[tid] = red_lo[tid + h] < red_lo[tid] ? red_lo[tid + h] : red_lo[tid];
+      red_hi[tid] = red_hi[tid + h] > red_hi[tid] ? red_hi[tid + h] : red_hi[tid];
+    }
+    __syncthreads();
+  }
+  const int64_t bmin = red_lo[0], bmax = red_hi[0];
+  const int nh = int(bmax - bmin) + 8;  // taps of the combined filter
+  if (tid == 0) {
+    meta[2 * j] = bmin;
+    meta[2 * j + 1] = nh <= HMAX ? nh : -1;
+  }
+  if (nh > HMAX) return;
+  // (2) combined filter, copies in batches of SUM_PAIRS, each thread owning taps
+  for (int t = tid; t < NQ * HROW; t += SUM_WG) H[t / HROW][t % HROW] = 0.0;
+  for (int c0 = 0; c0 < ncopy; c0 += SUM_PAIRS) {
+    const int nb = ncopy - c0 < SUM_PAIRS ? ncopy - c0 : SUM_PAIRS;
+    if (tid < nb) Wb[tid] = copy_stencil(geo, j, c0 + tid, ncopy, g, s, w, area, Wt[tid]) - bmin;
+    __syncthreads();
+    for (int k = tid; k < nh; k += SUM_WG) {
+      double hx[NQ];
+#pragma unroll
+      for (int x = 0; x < NQ; ++x) hx[x] = H[x][k];
+      for (int p = 0; p < nb; ++p) {
+        const int64_t d = int64_t(k) - Wb[p];
+        if (d >= 0 && d < 8) {
+#pragma unroll
+          for (int x = 0; x < NQ; ++x) hx[x] += Wt[p][x * 8 + d];
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < NQ; ++x) H[x][k] = hx[x];
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < NQ * HROW; t += SUM_WG) filt[j * NQ * HROW + t] = H[t / HROW][t % HROW];
+}
+
+// Thickness and loading integrands of the panels of one chunk at the observer times of
+// one time chunk, summed; partial sums per chunk: part[chunk][2][n_out].
 __global__ __launch_bounds__(SUM_WG) void k_fwh_sum(const double *__restrict__ src, const double *__restrict__ geo,
                                                     int64_t np, int64_t cap, int ncopy, Geo3 g, Stream s, Window w,
+                                                    const double *__restrict__ filt, const int64_t *__restrict__ meta,
                                                     double *__restrict__ part) {
   __shared__ double Wt[SUM_PAIRS][NQ * 8];
   __shared__ int64_t Wb[SUM_PAIRS];
   // one source series at a time; the combined-filter path stores sample e at
   // (e % SUM_OUT) * XQ + e / SUM_OUT, so that the lanes of a wave, SUM_OUT samples apart,
-  // read consecutive words
-  constexpr int XQ = SUM_SPAN / SUM_OUT + 2;
+  // read consecutive words; 8 zero samples past the staged stretch (the filter loop runs
+  // whole blocks of 4 taps)
+  constexpr int XQ = SUM_SPAN / SUM_OUT + 4;
   __shared__ double Xs[1][SUM_OUT * XQ];
-  __shared__ double H[NQ][HMAX];
-  __shared__ int64_t red_lo[SUM_WG], red_hi[SUM_WG];
+  __shared__ double H[NQ][HROW];
   __shared__ int64_t lo_s, hi_s;
   const int64_t chunk = blockIdx.y;
   const int tid = threadIdx.x;
@@ -267,71 +335,42 @@ __global__ __launch_bounds__(SUM_WG) void k_fwh_sum(const double *__restrict__ s
   const int64_t j0 = chunk * SUM_PANELS, j1 = j0 + SUM_PANELS < np ? j0 + SUM_PANELS : np;
   for (int64_t j = j0; j < j1; ++j) {
     const double area = geo[j * 7 + 6];
-    // (1) first samples of all copies: their minimum and maximum
-    int64_t blo = INT64_MAX, bhi = INT64_MIN;
-    for (int c = tid; c < ncopy; c += SUM_WG) {
-      const int64_t b = copy_stencil(geo, j, c, ncopy, g, s, w, area, nullptr);
-      blo = b < blo ? b : blo;
-      bhi = b > bhi ? b : bhi;
-    }
-    red_lo[tid] = blo;
-    red_hi[tid] = bhi;
-    __syncthreads();
-    for (int h = SUM_WG / 2; h > 0; h >>= 1) {
-      if (tid < h) {
-        red_lo[tid] = red_lo[tid + h] < red_lo[tid] ? red_lo[tid + h] : red_lo[tid];
-        red_hi[tid] = red_hi[tid + h] > red_hi[tid] ? red_hi[tid + h] : red_hi[tid];
-      }
-      __syncthreads();
-    }
-    const int64_t bmin = red_lo[0], bmax = red_hi[0];
-    const int nh = int(bmax - bmin) + 8;  // taps of the combined filter
-    __syncthreads();
-    if (nh <= HMAX) {
-      // (2) combined filter
-      for (int t = tid; t < NQ * HMAX; t += SUM_WG) H[t / HMAX][t % HMAX] = 0.0;
-      for (int c0 = 0; c0 < ncopy; c0 += SUM_PAIRS) {
-        const int nb = ncopy - c0 < SUM_PAIRS ? ncopy - c0 : SUM_PAIRS;
-        if (tid < nb) Wb[tid] = copy_stencil(geo, j, c0 + tid, ncopy, g, s, w, area, Wt[tid]) - bmin;
-        __syncthreads();
-        for (int k = tid; k < nh; k += SUM_WG) {
-          double hx[NQ];
-#pragma unroll
-          for (int x = 0; x < NQ; ++x) hx[x] = H[x][k];
-          for (int p = 0; p < nb; ++p) {
-            const int64_t d = int64_t(k) - Wb[p];
-            if (d >= 0 && d < 8) {
-#pragma unroll
-              for (int x = 0; x < NQ; ++x) hx[x] += Wt[p][x * 8 + d];
-            }
-          }
-#pragma unroll
-          for (int x = 0; x < NQ; ++x) H[x][k] = hx[x];
-        }
-        __syncthreads();
-      }
+    const int64_t bmin = meta[2 * j];
+    const int nh = int(meta[2 * j + 1]);
+    if (nh > 0) {
+      // the panel's combined filter (the previous panel's last barrier has passed)
+      for (int t = tid; t < NQ * HROW; t += SUM_WG) H[t / HROW][t % HROW] = filt[j * NQ * HROW + t];
       // (3) each series over [bmin + mt0, bmax + mlast + 8) in turn, then the filter
       const int64_t lo = bmin + mt0, span = int64_t(nh - 8) + (mlast - mt0) + 8;
       for (int x = 0; x < NQ; ++x) {
-        for (int64_t k = tid; k < span; k += SUM_WG)
-          Xs[0][int(k % SUM_OUT) * XQ + int(k / SUM_OUT)] = src[(x * np + j) * cap + lo + k];
+        for (int64_t k = tid; k < span + 8; k += SUM_WG)
+          Xs[0][int(k % SUM_OUT) * XQ + int(k / SUM_OUT)] = k < span ? src[(x * np + j) * cap + lo + k] : 0.0;
         __syncthreads();
         if (m0 <= mlast) {
-          // this thread's samples start at tid * SUM_OUT; its window holds SUM_OUT of them
-          double win[SUM_OUT], acc[SUM_OUT];
+          // this thread's samples start at tid * SUM_OUT. Taps go in blocks of 4 over a
+          // window of 8 samples, w[r] = sample tid * 4 + 4 b + r, in tap order for each
+          // output (the zero taps past nh add nothing): 16 multiply-adds per 4 samples
+          // read, the taps read as a broadcast
+          const double *X0 = &Xs[0][tid];
+          double w[8], acc[SUM_OUT];
 #pragma unroll
-          for (int o = 0; o < SUM_OUT; ++o) {
-            win[o] = Xs[0][o * XQ + tid];
-            acc[o] = 0.0;
+          for (int r = 0; r < 4; ++r) {
+            w[r] = X0[r * XQ];
+            acc[r] = 0.0;
           }
-          for (int k = 0; k < nh; ++k) {
-            const double hk = H[x][k];
+          const int nblk = (nh + 3) / 4;
+#pragma unroll 2
+          for (int b = 0; b < nblk; ++b) {
 #pragma unroll
-            for (int o = 0; o < SUM_OUT; ++o) acc[o] += hk * win[o];
+            for (int r = 0; r < 4; ++r) w[4 + r] = X0[r * XQ + b + 1];
 #pragma unroll
-            for (int o = 0; o + 1 < SUM_OUT; ++o) win[o] = win[o + 1];
-            // sample tid * SUM_OUT + k + SUM_OUT
-            if (k + 1 < nh) win[SUM_OUT - 1] = Xs[0][(k % SUM_OUT) * XQ + tid + 1 + k / SUM_OUT];
+            for (int kk = 0; kk < 4; ++kk) {
+              const double hk = H[x][4 * b + kk];
+#pragma unroll
+              for (int o = 0; o < SUM_OUT; ++o) acc[o] += hk * w[o + kk];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w[r] = w[4 + r];
           }
 #pragma unroll
           for (int o = 0; o < SUM_OUT; ++o) {
@@ -451,8 +490,8 @@ struct fr_fwh {
   double shift[3] = {0, 0, 0}, dt = 0, tau0 = 0;
   Stream s{};
   double *geo = nullptr, *src = nullptr, *stage = nullptr, *mm = nullptr, *part = nullptr, *part2 = nullptr,
-         *out = nullptr;
-  size_t stage_bytes = 0, part_bytes = 0, part2_bytes = 0, out_bytes = 0;
+         *out = nullptr, *filt = nullptr, *meta = nullptr;
+  size_t stage_bytes = 0, part_bytes = 0, part2_bytes = 0, out_bytes = 0, filt_bytes = 0, meta_bytes = 0;
   std::vector<void *> owned;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
@@ -655,6 +694,8 @@ void fwh_compute(fr_fwh *h, const double *observer, const Window &w, double *p, 
   h->grow(h->part, h->part_bytes, size_t(nchunk) * 2 * w.n_out * sizeof(double));
   h->grow(h->part2, h->part2_bytes, size_t(RED_GROUPS) * 2 * w.n_out * sizeof(double));
   h->grow(h->out, h->out_bytes, size_t(3) * w.n_out * sizeof(double));
+  h->grow(h->filt, h->filt_bytes, size_t(h->np) * NQ * HROW * sizeof(double));
+  h->grow(h->meta, h->meta_bytes, size_t(h->np) * 2 * sizeof(int64_t));
   Geo3 g;
   for (int i = 0; i < 3; ++i) {
     g.shift[i] = h->shift[i];
@@ -663,8 +704,11 @@ void fwh_compute(fr_fwh *h, const double *observer, const Window &w, double *p, 
   const int64_t per_block = int64_t(SUM_WG) * SUM_OUT;
   const dim3 grid(unsigned((w.n_out + per_block - 1) / per_block), unsigned(nchunk));
   hip_check(hipEventRecord(h->ev0, h->stream), "event");
+  hipLaunchKernelGGL(k_fwh_filter, dim3(unsigned(h->np)), dim3(SUM_WG), 0, h->stream, h->geo, h->np, h->ncopy, g, h->s,
+                     w, h->filt, reinterpret_cast<int64_t *>(h->meta));
+  hip_check(hipGetLastError(), "filter kernel");
   hipLaunchKernelGGL(k_fwh_sum, grid, dim3(SUM_WG), 0, h->stream, h->src, h->geo, h->np, h->cap, h->ncopy, g, h->s, w,
-                     h->part);
+                     h->filt, reinterpret_cast<const int64_t *>(h->meta), h->part);
   hip_check(hipGetLastError(), "sum kernel");
   hipLaunchKernelGGL(k_fwh_reduce_groups, dim3(unsigned((w.n_out + 255) / 256), RED_GROUPS), dim3(256), 0, h->stream,
                      h->part, nchunk, w.n_out, h->part2);
@@ -739,8 +783,9 @@ fr_status fr::fwh_append_probe_async(::fr_fwh *h, ::fr_probe *p) {
 size_t fr::fwh_footprint(int64_t n_points, int64_t capacity) {
   const size_t np = size_t(n_points), cap = size_t(capacity);
   const size_t nchunk = (np + SUM_PANELS - 1) / SUM_PANELS;
-  // geometry, source series, one staged snapshot, delay extremes, and at most a
-  // window of capacity observer times of partial sums and outputs
-  return (np * 7 + size_t(NQ) * np * cap + np * 5 + 2 * 64 + nchunk * 2 * cap + size_t(RED_GROUPS) * 2 * cap +
-          3 * cap) * sizeof(double);
+  // geometry, source series, one staged snapshot, delay extremes, the panels' combined
+  // filters and their first samples, and at most a window of capacity observer times of
+  // partial sums and outputs
+  return (np * 7 + size_t(NQ) * np * cap + np * 5 + 2 * 64 + np * (size_t(NQ) * HROW + 2) + nchunk * 2 * cap +
+          size_t(RED_GROUPS) * 2 * cap + 3 * cap) * sizeof(double);
 }
