@@ -955,11 +955,16 @@ template <typename T, int DIM, int ORDER> struct FS {
   // stage a: max(state + jumps, gradient + transformed flux) per element (aliased)
   static constexpr int LDS_A_ELEM = (S::NU * S::NV + S::NF * S::NV) > 2 * S::NU * S::NG
                                         ? (S::NU * S::NV + S::NF * S::NV) : 2 * S::NU * S::NG;
-  static constexpr int EW_A = ew(LDS_A_ELEM * int(sizeof(T)), 40960);
-  static constexpr int WG_A = S::NU * EW_A >= 256 ? 256 : (S::NU * EW_A + 63) / 64 * 64;
+  // threads per element: one per solution point from p = 3 up; below, the flux points
+  // outnumber the solution points (P1: 24 against 8) and one thread per flux point
+  // gives the low orders' small grids more waves to hide latency with
+  static constexpr int TPE = ORDER >= 3 ? S::NU : (S::NF > S::NU ? S::NF : S::NU);
+  static constexpr int ewt(int e) { return ORDER >= 3 || TPE * e <= 256 || e == 1 ? e : ewt(e / 2); }
+  static constexpr int EW_A = ewt(ew(LDS_A_ELEM * int(sizeof(T)), 40960));
+  static constexpr int WG_A = TPE * EW_A >= 256 ? 256 : (TPE * EW_A + 63) / 64 * 64;
   // stage b: common flux at faces and the new state
-  static constexpr int EW_B = ew((S::NF * S::NV + S::NU * S::NV) * int(sizeof(T)), 32768);
-  static constexpr int WG_B = S::NU * EW_B >= 256 ? 256 : (S::NU * EW_B + 63) / 64 * 64;
+  static constexpr int EW_B = ewt(ew((S::NF * S::NV + S::NU * S::NV) * int(sizeof(T)), 32768));
+  static constexpr int WG_B = TPE * EW_B >= 256 ? 256 : (TPE * EW_B + 63) / 64 * 64;
 };
 
 // MORTAR: the mesh is one order group of a variable-order mesh, whose neighbour codes
