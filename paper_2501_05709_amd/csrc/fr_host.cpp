@@ -577,11 +577,10 @@ struct fr_mesh {
   std::vector<int64_t> uoff;            // [E + 1] first solution point of the element
   int64_t n_mortar = 0;                 // mortar points
   // gather rows: [0, rA) higher-order points (partner = lower order, interpolation);
-  // [rA, rB) lower-order points (partner = higher order, projection); then, per
-  // group g, rows [rC[g], rC[g + 1]) of lower-order points whose higher-order side is
-  // g, reading the higher side's transformed flux MT (projection, sign -1)
+  // [rA, rB) lower-order points (partner = higher order, projection). The projection of
+  // the higher side's transformed common flux MT onto the lower side is formed inside
+  // the lower group's second launch, from the per-point tables DevArrays::PO/PC/PW
   int64_t rA = 0, rB = 0;
-  std::vector<int64_t> rC;
   int *row_out = nullptr, *row_off = nullptr, *ent_grp = nullptr, *ent_code = nullptr;
   double *ent_w = nullptr;
   bool mixed() const { return !groups.empty(); }
@@ -1033,7 +1032,7 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
   };
   std::vector<int> row_out, row_off{0}, ent_grp, ent_code;
   std::vector<double> ent_w;
-  struct LowRow { int g; int out; std::vector<int> code; std::vector<double> w; };
+  struct LowRow { int out; std::vector<int> code; std::vector<double> w; };
   std::vector<LowRow> low;
   std::vector<std::vector<int>> rowsB_code(0);
   // face geometry helpers on each side
@@ -1083,7 +1082,7 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
       }
       for (int i = 0; i < nfpL; ++i) {
         row_out.push_back(int(mf.baseL + i));
-        LowRow lr{gH, int(mf.baseL + i), {}, {}};
+        LowRow lr{int(mf.baseL + i), {}, {}};
         for (int j = 0; j < nfpH; ++j) {
           ent_grp.push_back(gH);
           ent_code.push_back(code_of(mf.eH, mf.fH, j));
@@ -1098,22 +1097,24 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
     if (pass == 0) M->rA = int64_t(row_out.size());
   }
   M->rB = int64_t(row_out.size());
-  std::stable_sort(low.begin(), low.end(), [](const LowRow &a, const LowRow &b) { return a.g < b.g; });
-  M->rC.assign(present.size() + 1, M->rB);
-  for (size_t g = 0; g < present.size(); ++g) {
-    M->rC[g] = int64_t(row_out.size());
-    for (const auto &lr : low) {
-      if (lr.g != int(g)) continue;
-      row_out.push_back(lr.out);
-      for (size_t j = 0; j < lr.code.size(); ++j) {
-        ent_grp.push_back(-1);
-        ent_code.push_back(lr.code[j]);
-        ent_w.push_back(lr.w[j]);
+  // projection onto the lower-order sides, per mortar point: MT points and weights
+  std::vector<int> po(size_t(std::max<int64_t>(np, 1)) + 1, 0), pc;
+  std::vector<double> pw;
+  {
+    std::vector<const LowRow *> at_point(size_t(std::max<int64_t>(np, 1)), nullptr);
+    for (const auto &lr : low) at_point[size_t(lr.out)] = &lr;
+    for (size_t q = 0; q < at_point.size(); ++q) {
+      if (at_point[q]) {
+        pc.insert(pc.end(), at_point[q]->code.begin(), at_point[q]->code.end());
+        pw.insert(pw.end(), at_point[q]->w.begin(), at_point[q]->w.end());
       }
-      row_off.push_back(int(ent_w.size()));
+      po[q + 1] = int(pw.size());
     }
   }
-  M->rC[present.size()] = int64_t(row_out.size());
+  if (pw.empty()) {  // keep the tables valid
+    pc.push_back(0);
+    pw.push_back(0.0);
+  }
   if (ent_w.empty()) {  // no mortar face: keep the tables valid
     ent_grp.push_back(0);
     ent_code.push_back(0);
@@ -1126,6 +1127,9 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
   M->ent_grp = M->upload(ent_grp);
   M->ent_code = M->upload(ent_code);
   M->ent_w = M->upload(ent_w);
+  M->a.PO = M->upload(po);
+  M->a.PC = M->upload(pc);
+  M->a.PW = M->upload(pw);
   const size_t mb = size_t(std::max<int64_t>(np, 1)) * (dim + 2) * M->real_size();
   M->a.MU = M->dalloc(mb);
   M->a.MX = M->dalloc(mb);
@@ -1134,6 +1138,9 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
     G->a.MU = M->a.MU;
     G->a.MX = M->a.MX;
     G->a.MT = M->a.MT;
+    G->a.PO = M->a.PO;
+    G->a.PC = M->a.PC;
+    G->a.PW = M->a.PW;
   }
   M->a.flag = (int *)M->dalloc(sizeof(int));
   M->cfg = M->groups[0]->cfg;
@@ -1142,7 +1149,7 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
 }
 
 // gather rows [r0, r1) from the groups' array `which` (0: traces UF, 1: half viscous
-// fluxes PV) or, for rows of the C range, from MT
+// fluxes PV)
 void gather(fr_mesh *M, int64_t r0, int64_t r1, int which, void *out, double sign) {
   MortarSrc src{};
   for (size_t g = 0; g < M->groups.size() && g < 8; ++g)
@@ -1167,8 +1174,9 @@ void lk(fr_mesh *M, int kernel, int stage, int mode, bool forces) {
 // one RK4 stage (or the residual, mode MODE_RESID) of a variable-order mesh: the
 // other sides' traces at every mortar point, the first fused launch of every group,
 // the lower-order sides' half viscous fluxes at the higher-order points, then the
-// second launch group by group from the highest order down, each followed by the
-// projection of its transformed mortar fluxes onto the lower-order points
+// second launch group by group from the highest order down; each projects the
+// transformed mortar fluxes that the higher groups wrote before it onto its
+// lower-order points
 void enqueue_stage_mixed(fr_mesh *M, int stage, int mode, bool forces) {
   gather(M, 0, M->rB, 0, M->a.MU, 1.0);
   for (auto &G : M->groups) {
@@ -1179,7 +1187,6 @@ void enqueue_stage_mixed(fr_mesh *M, int stage, int mode, bool forces) {
   gather(M, 0, M->rA, 1, M->a.MX, 1.0);
   for (size_t g = M->groups.size(); g-- > 0;) {
     lk(M->groups[g].get(), K_STAGE_B, stage, mode, false);
-    gather(M, M->rC[g], M->rC[g + 1], 2, M->a.MX, -1.0);
   }
 }
 

@@ -79,6 +79,11 @@ struct DevArrays {
   // viscous normal flux (higher-order side) or the complete transformed common flux
   // (lower-order side); MT the transformed common flux of the higher-order side
   void *MU = nullptr, *MX = nullptr, *MT = nullptr;
+  // the L2 projection onto a lower-order side, per mortar point (CSR): entries
+  // [PO[s], PO[s + 1]) of mortar point s are MT points PC[] with weights PW[]; empty for
+  // higher-order points
+  const int *PO = nullptr, *PC = nullptr;
+  const double *PW = nullptr;
 };
 
 struct LaunchCfg {

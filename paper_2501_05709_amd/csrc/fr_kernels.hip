@@ -79,6 +79,8 @@ template <typename T> struct KArgs {
   int *flag;
   const T *MU, *MX;
   T *MT;
+  const int *PO, *PC;
+  const double *PW;
   int64_t nblk, n_canon;
   int ndesign;
   T gam, mu, kappa;
@@ -1304,11 +1306,27 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
   for (int it = 0; it < FI; ++it) {
     const int nb = nbv[it];
     if (MORTAR && nb < 0 && ((-nb) & 3) == BC_MORTAR) {
-      // higher-order side: the other side's half viscous flux; lower-order side: the
-      // complete transformed common flux (projected from the higher-order side)
-      const size_t base = size_t((-nb) >> 3) * NV;
+      const int64_t pt = (-nb) >> 3;
+      if (((-nb) >> 2) & 1) {
+        // lower-order side: the complete transformed common flux, the L2 projection of
+        // the higher-order side's (MT, written by that group's second launch, which runs
+        // before this one), with the outward sign of this side; FP64 sums in entry order
+        double acc[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) pn[it][v] = a.MX[base + v];
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+        for (int j = a.PO[pt]; j < a.PO[pt + 1]; ++j) {
+          const double wj = a.PW[j];
+          const size_t src = size_t(a.PC[j]) * NV;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[v] += wj * double(a.MT[src + v]);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) pn[it][v] = T(-1.0 * acc[v]);
+      } else {
+        // higher-order side: the other side's half viscous flux
+#pragma unroll
+        for (int v = 0; v < NV; ++v) pn[it][v] = a.MX[size_t(pt) * NV + v];
+      }
     } else if (!SKIP || nb >= 0) {
       // unconditional form: a boundary code loads slot 0 and never uses it
       const int p = nb > 0 ? nb : 0;
@@ -1550,6 +1568,7 @@ template <typename T> static KArgs<T> make_args(const LaunchCfg &c, const DevArr
   a.NB = d.NB; a.bcount = d.bcount; a.bdesign = d.bdesign; a.bcanon = d.bcanon; a.wall_first = d.wall_first;
   a.flag = d.flag;
   a.MU = (const T *)d.MU; a.MX = (const T *)d.MX; a.MT = (T *)d.MT;
+  a.PO = d.PO; a.PC = d.PC; a.PW = d.PW;
   a.nblk = c.nblk; a.n_canon = c.n_canon; a.ndesign = c.ndesign;
   a.gam = T(c.gamma); a.mu = T(c.mu); a.kappa = T(c.mu * c.gamma / c.prandtl);
   return a;
