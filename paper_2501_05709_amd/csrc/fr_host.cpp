@@ -569,20 +569,14 @@ struct fr_mesh {
   hipGraphExec_t graph_first = nullptr, graph_rest = nullptr;
 
   // variable order: one uniform-order solver per order present (ascending order),
-  // all on this handle's stream and sharing its mortar buffers (DevArrays MU, MX, MT)
+  // all on this handle's stream and sharing its mortar tables (DevArrays MO.., MT, PO..)
   std::vector<std::unique_ptr<fr_mesh>> groups;
   std::vector<int> eorder;              // [E] element order
   std::vector<int> egroup;              // [E] group of the element
   std::vector<int64_t> elocal;          // [E] index of the element within its group
   std::vector<int64_t> uoff;            // [E + 1] first solution point of the element
   int64_t n_mortar = 0;                 // mortar points
-  // gather rows: [0, rA) higher-order points (partner = lower order, interpolation);
-  // [rA, rB) lower-order points (partner = higher order, projection). The projection of
-  // the higher side's transformed common flux MT onto the lower side is formed inside
-  // the lower group's second launch, from the per-point tables DevArrays::PO/PC/PW
-  int64_t rA = 0, rB = 0;
-  int *row_out = nullptr, *row_off = nullptr, *ent_grp = nullptr, *ent_code = nullptr;
-  double *ent_w = nullptr;
+  std::vector<const void *> group_uf, group_pv;  // the groups' UF and PV arrays
   bool mixed() const { return !groups.empty(); }
 
   size_t real_size() const { return prec == FR_FP32 ? 4 : 8; }
@@ -1094,9 +1088,7 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
         low.push_back(std::move(lr));
       }
     }
-    if (pass == 0) M->rA = int64_t(row_out.size());
   }
-  M->rB = int64_t(row_out.size());
   // projection onto the lower-order sides, per mortar point: MT points and weights
   std::vector<int> po(size_t(std::max<int64_t>(np, 1)) + 1, 0), pc;
   std::vector<double> pw;
@@ -1115,28 +1107,52 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
     pc.push_back(0);
     pw.push_back(0.0);
   }
-  if (ent_w.empty()) {  // no mortar face: keep the tables valid
-    ent_grp.push_back(0);
-    ent_code.push_back(0);
-    ent_w.push_back(0.0);
-    row_out.push_back(0);
-    row_off.push_back(1);
+  // the rows again, per mortar point: each point is the output of exactly one row
+  std::vector<int> mo(size_t(std::max<int64_t>(np, 1)) + 1, 0), mg, mc;
+  std::vector<double> mw;
+  {
+    std::vector<int64_t> row_of(size_t(std::max<int64_t>(np, 1)), -1);
+    for (size_t r = 0; r < row_out.size(); ++r) row_of[size_t(row_out[r])] = int64_t(r);
+    for (size_t q = 0; q < row_of.size(); ++q) {
+      const int64_t r = row_of[q];
+      if (r >= 0)
+        for (int j = row_off[size_t(r)]; j < row_off[size_t(r) + 1]; ++j) {
+          mg.push_back(ent_grp[size_t(j)]);
+          mc.push_back(ent_code[size_t(j)]);
+          mw.push_back(ent_w[size_t(j)]);
+        }
+      mo[q + 1] = int(mw.size());
+    }
   }
-  M->row_out = M->upload(row_out);
-  M->row_off = M->upload(row_off);
-  M->ent_grp = M->upload(ent_grp);
-  M->ent_code = M->upload(ent_code);
-  M->ent_w = M->upload(ent_w);
+  if (mw.empty()) {  // no mortar face: keep the tables valid
+    mg.push_back(0);
+    mc.push_back(0);
+    mw.push_back(0.0);
+  }
+  M->a.MO = M->upload(mo);
+  M->a.MG = M->upload(mg);
+  M->a.MC = M->upload(mc);
+  M->a.MW = M->upload(mw);
+  for (auto &G : M->groups) {
+    M->group_uf.push_back(G->a.UF);
+    M->group_pv.push_back(G->a.PV);
+  }
+  M->a.GUF = M->upload(M->group_uf);
+  M->a.GPV = M->upload(M->group_pv);
   M->a.PO = M->upload(po);
   M->a.PC = M->upload(pc);
   M->a.PW = M->upload(pw);
-  const size_t mb = size_t(std::max<int64_t>(np, 1)) * (dim + 2) * M->real_size();
-  M->a.MU = M->dalloc(mb);
-  M->a.MX = M->dalloc(mb);
-  M->a.MT = M->dalloc(mb);
+  M->a.MT = M->dalloc(size_t(std::max<int64_t>(np, 1)) * (dim + 2) * M->real_size());
+  // the groups run the mortar build of the fused kernels (DevArrays::MO set) only when
+  // the mesh has mortar points; with one order present they run the one-order build
+  if (np == 0) M->a.MO = nullptr;
   for (auto &G : M->groups) {
-    G->a.MU = M->a.MU;
-    G->a.MX = M->a.MX;
+    G->a.MO = M->a.MO;
+    G->a.MG = M->a.MG;
+    G->a.MC = M->a.MC;
+    G->a.MW = M->a.MW;
+    G->a.GUF = M->a.GUF;
+    G->a.GPV = M->a.GPV;
     G->a.MT = M->a.MT;
     G->a.PO = M->a.PO;
     G->a.PC = M->a.PC;
@@ -1148,16 +1164,6 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
   hip_check(hipStreamSynchronize(M->stream), "mesh upload");
 }
 
-// gather rows [r0, r1) from the groups' array `which` (0: traces UF, 1: half viscous
-// fluxes PV)
-void gather(fr_mesh *M, int64_t r0, int64_t r1, int which, void *out, double sign) {
-  MortarSrc src{};
-  for (size_t g = 0; g < M->groups.size() && g < 8; ++g)
-    src.g[g] = which == 0 ? M->groups[g]->a.UF : M->groups[g]->a.PV;
-  hip_check(launch_mortar_gather(M->prec, M->dim + 2, r0, r1, M->row_out, M->row_off, M->ent_grp, M->ent_code,
-                                 M->ent_w, src, M->a.MT, out, sign, M->stream),
-            "mortar gather");
-}
 
 void profile_steps(fr_mesh *m, int64_t steps, double *ms, int64_t *launches);
 
@@ -1172,22 +1178,19 @@ void lk(fr_mesh *M, int kernel, int stage, int mode, bool forces) {
 }
 
 // one RK4 stage (or the residual, mode MODE_RESID) of a variable-order mesh: the
-// other sides' traces at every mortar point, the first fused launch of every group,
-// the lower-order sides' half viscous fluxes at the higher-order points, then the
-// second launch group by group from the highest order down; each projects the
-// transformed mortar fluxes that the higher groups wrote before it onto its
-// lower-order points
+// first fused launch of every group (each forms the other sides' traces at its mortar
+// points from the groups' traces), then the second launch group by group from the
+// highest order down. A higher-order side interpolates the lower side's half viscous
+// fluxes (written by the first launches) to its mortar points and writes its
+// transformed common flux there; a lower-order side projects that flux, written by the
+// higher group's second launch before its own, onto its points.
 void enqueue_stage_mixed(fr_mesh *M, int stage, int mode, bool forces) {
-  gather(M, 0, M->rB, 0, M->a.MU, 1.0);
   for (auto &G : M->groups) {
     const bool f = forces && G->nwall > 0;
     lk(G.get(), K_STAGE_A, stage, 0, f);
     if (f) hip_check(launch_force_reduce(G->cfg, G->a), "force reduce");
   }
-  gather(M, 0, M->rA, 1, M->a.MX, 1.0);
-  for (size_t g = M->groups.size(); g-- > 0;) {
-    lk(M->groups[g].get(), K_STAGE_B, stage, mode, false);
-  }
+  for (size_t g = M->groups.size(); g-- > 0;) lk(M->groups[g].get(), K_STAGE_B, stage, mode, false);
 }
 
 // one RK4 step; force terms of the step's input state are reduced if `forces`
@@ -1249,7 +1252,6 @@ void step_async(fr_mesh *M, int64_t n, bool clear_flag = true) {
     for (int64_t s = 0; s < n; ++s)
       hip_check(hipGraphLaunch(s == 0 ? M->graph_first : M->graph_rest, M->stream), "graph launch");
     if (M->nwall > 0) {  // wall force of the final state
-      gather(M, 0, M->rB, 0, M->a.MU, 1.0);
       for (auto &G : M->groups)
         if (G->nwall > 0) {
           lk(G.get(), K_STAGE_A, 0, 0, true);

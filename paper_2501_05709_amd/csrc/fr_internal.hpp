@@ -74,14 +74,19 @@ struct DevArrays {
   double *fsum = nullptr;  // [design][8]: sum Fx,Fy,Fz, count, last Fx,Fy,Fz, spare
   int *flag = nullptr;     // non-finite flag
   double *stage64 = nullptr;  // canonical FP64 staging [E][nu][nv]
-  // mortar buffers of a variable-order mesh, [mortar point][nv] (real), shared by its
-  // order groups: MU the other side's trace at the point; MX the other side's half
-  // viscous normal flux (higher-order side) or the complete transformed common flux
-  // (lower-order side); MT the transformed common flux of the higher-order side
-  void *MU = nullptr, *MX = nullptr, *MT = nullptr;
-  // the L2 projection onto a lower-order side, per mortar point (CSR): entries
-  // [PO[s], PO[s + 1]) of mortar point s are MT points PC[] with weights PW[]; empty for
-  // higher-order points
+  // mortar data of a variable-order mesh, shared by its order groups. Per mortar point s
+  // (a flux point on a face shared with an element of another order), entries
+  // [MO[s], MO[s + 1]) read partner code MC[] of order group MG[] with weight MW[]: the
+  // other side's face points interpolated to s (higher-order side) or projected onto
+  // it (lower-order side). The first launch applies them to the groups' traces GUF[g]
+  // (the other side's trace at s), the second launch of a higher-order side to their
+  // half viscous fluxes GPV[g]. MT, [mortar point][nv] (real): the transformed common
+  // flux of a higher-order side, projected onto the lower-order points by entries
+  // [PO[s], PO[s + 1]) (MT points PC[], weights PW[]; empty for higher-order points).
+  const int *MO = nullptr, *MG = nullptr, *MC = nullptr;
+  const double *MW = nullptr;
+  const void *const *GUF = nullptr, *const *GPV = nullptr;  // device arrays of group pointers
+  void *MT = nullptr;
   const int *PO = nullptr, *PC = nullptr;
   const double *PW = nullptr;
 };
@@ -121,16 +126,6 @@ hipError_t launch_pack(const LaunchCfg &c, const DevArrays &a, bool to_device_la
 hipError_t launch_force_reduce(const LaunchCfg &c, const DevArrays &a);
 hipError_t launch_clear_flag(const LaunchCfg &c, const DevArrays &a);
 
-// Mortar gather: for rows r in [r0, r1), out[row_out[r]][v] = sign * sum over the row's
-// entries j in [row_off[r], row_off[r+1]) of w[j] * source value, the source being
-// group ent_grp[j]'s face array (a partner code ent_code[j], as in the neighbour table)
-// or, for ent_grp[j] < 0, the compact array `compact` at point ent_code[j].
-struct MortarSrc {
-  const void *g[8];
-};
-hipError_t launch_mortar_gather(int prec, int nv, int64_t r0, int64_t r1, const int *row_out, const int *row_off,
-                                const int *ent_grp, const int *ent_code, const double *ent_w, MortarSrc src,
-                                const void *compact, void *out, double sign, hipStream_t stream);
 // dst (may be null): output row of each point, else the point's own index
 hipError_t launch_probe(const LaunchCfg &c, const DevArrays &a, int64_t n, const int64_t *slot, const double *w,
                         const int64_t *dst, double *out);

@@ -77,7 +77,9 @@ template <typename T> struct KArgs {
   const int *NB, *bcount, *bdesign;
   const int64_t *bcanon, *wall_first;
   int *flag;
-  const T *MU, *MX;
+  const int *MO, *MG, *MC;
+  const double *MW;
+  const T *const *GUF, *const *GPV;
   T *MT;
   const int *PO, *PC;
   const double *PW;
@@ -930,6 +932,25 @@ __global__ __launch_bounds__(256) void t_divrk(KArgs<T> a, int mode) {
   if (bad) atomicOr(a.flag, 1);
 }
 
+// the other side's face data at mortar point pt: sum over its entries of weight x the
+// value of group MG[j] at partner code MC[j] in the face layout, in FP64, entry order
+template <typename T, int NV>
+__device__ inline void mortar_sum(const KArgs<T> &a, const T *const *grp, int64_t pt, T out[NV]) {
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int j = a.MO[pt]; j < a.MO[pt + 1]; ++j) {
+    const T *src = grp[a.MG[j]];
+    const int c = a.MC[j];
+    const double wj = a.MW[j];
+    const size_t base = size_t(c / SB) * NV * SB + (c % SB);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += wj * double(src[base + v * SB]);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = T(acc[v]);
+}
+
 // ---------------------------------------------------------------------------
 // fused stage: two launches per RK stage, sum-factorised, LDS-staged
 //
@@ -1025,10 +1046,9 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   for (int it = 0; it < FI; ++it) {
     const int nb = nbv[it];
     if (MORTAR && nb < 0 && ((-nb) & 3) == BC_MORTAR) {
-      // the other side's trace, brought to this point by the mortar gather
-      const size_t base = size_t((-nb) >> 3) * NV;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) ur[it][v] = a.MU[base + v];
+      // the other side's trace at this point: its face points' traces interpolated
+      // (higher-order side) or projected (lower-order side)
+      mortar_sum<T, NV>(a, a.GUF, (-nb) >> 3, ur[it]);
     } else {
       // a boundary code loads slot 0 and never uses it
       const int p = nb > 0 ? nb : 0;
@@ -1323,9 +1343,9 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) pn[it][v] = T(-1.0 * acc[v]);
       } else {
-        // higher-order side: the other side's half viscous flux
-#pragma unroll
-        for (int v = 0; v < NV; ++v) pn[it][v] = a.MX[size_t(pt) * NV + v];
+        // higher-order side: the other side's half viscous flux, interpolated to this
+        // point (that group's first launch wrote it)
+        mortar_sum<T, NV>(a, a.GPV, pt, pn[it]);
       }
     } else if (!SKIP || nb >= 0) {
       // unconditional form: a boundary code loads slot 0 and never uses it
@@ -1567,7 +1587,8 @@ template <typename T> static KArgs<T> make_args(const LaunchCfg &c, const DevArr
   a.FC = d.FC; a.fsum = d.fsum; a.stage64 = d.stage64;
   a.NB = d.NB; a.bcount = d.bcount; a.bdesign = d.bdesign; a.bcanon = d.bcanon; a.wall_first = d.wall_first;
   a.flag = d.flag;
-  a.MU = (const T *)d.MU; a.MX = (const T *)d.MX; a.MT = (T *)d.MT;
+  a.MO = d.MO; a.MG = d.MG; a.MC = d.MC; a.MW = d.MW;
+  a.GUF = (const T *const *)d.GUF; a.GPV = (const T *const *)d.GPV; a.MT = (T *)d.MT;
   a.PO = d.PO; a.PC = d.PC; a.PW = d.PW;
   a.nblk = c.nblk; a.n_canon = c.n_canon; a.ndesign = c.ndesign;
   a.gam = T(c.gamma); a.mu = T(c.mu); a.kappa = T(c.mu * c.gamma / c.prandtl);
@@ -1626,7 +1647,7 @@ static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, i
       break;
     case K_STAGE_A: {
       const dim3 grid(c.nblk * (EB / FS<T, DIM, ORDER>::EW_A)), wgs(FS<T, DIM, ORDER>::WG_A);
-      if (d.MU)
+      if (d.MO)
         hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER, true>), grid, wgs, 0, c.stream, a, X, int(forces));
       else
         hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER, false>), grid, wgs, 0, c.stream, a, X, int(forces));
@@ -1634,7 +1655,7 @@ static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, i
     }
     case K_STAGE_B: {
       const dim3 grid(c.nblk * (EB / FS<T, DIM, ORDER>::EW_B)), wgs(FS<T, DIM, ORDER>::WG_B);
-      if (d.MU) return launch_stage_b<T, DIM, ORDER, true>(mode, grid, wgs, c.stream, a);
+      if (d.MO) return launch_stage_b<T, DIM, ORDER, true>(mode, grid, wgs, c.stream, a);
       return launch_stage_b<T, DIM, ORDER, false>(mode, grid, wgs, c.stream, a);
     }
     case K_DIVRK:
@@ -1663,41 +1684,6 @@ static hipError_t pack_t(const LaunchCfg &c, const DevArrays &d, bool to_dev, vo
 // mortar gather (faces between elements of different orders): one thread per
 // (row, variable), a short FP64 dot product over the other side's face points
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_mortar_gather(int64_t r0, int64_t r1, int nv, const int *__restrict__ row_out,
-                                                       const int *__restrict__ row_off, const int *__restrict__ ent_grp,
-                                                       const int *__restrict__ ent_code, const double *__restrict__ ent_w,
-                                                       MortarSrc src, const T *__restrict__ compact, T *__restrict__ out,
-                                                       double sign) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t r = r0 + t / nv;
-  const int v = int(t % nv);
-  if (r >= r1) return;
-  double acc = 0.0;
-  for (int j = row_off[r]; j < row_off[r + 1]; ++j) {
-    const int g = ent_grp[j], c = ent_code[j];
-    const T x = g >= 0 ? ((const T *)src.g[g])[size_t(c / SB) * nv * SB + (c % SB) + size_t(v) * SB]
-                       : compact[size_t(c) * nv + v];
-    acc += ent_w[j] * double(x);
-  }
-  out[size_t(row_out[r]) * nv + v] = T(sign * acc);
-}
-
-hipError_t launch_mortar_gather(int prec, int nv, int64_t r0, int64_t r1, const int *row_out, const int *row_off,
-                                const int *ent_grp, const int *ent_code, const double *ent_w, MortarSrc src,
-                                const void *compact, void *out, double sign, hipStream_t stream) {
-  if (r1 <= r0) return hipSuccess;
-  const int64_t thr = (r1 - r0) * nv;
-  const dim3 grid(unsigned((thr + 255) / 256));
-  if (prec == 1)
-    hipLaunchKernelGGL(k_mortar_gather<float>, grid, dim3(256), 0, stream, r0, r1, nv, row_out, row_off, ent_grp,
-                       ent_code, ent_w, src, (const float *)compact, (float *)out, sign);
-  else
-    hipLaunchKernelGGL(k_mortar_gather<double>, grid, dim3(256), 0, stream, r0, r1, nv, row_out, row_off, ent_grp,
-                       ent_code, ent_w, src, (const double *)compact, (double *)out, sign);
-  return hipGetLastError();
-}
-
 #define FR_DISPATCH(FN, ...)                                                              \
   do {                                                                                    \
     const int key = c.prec * 100 + c.dim * 10 + c.order;                                  \

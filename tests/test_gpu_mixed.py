@@ -160,6 +160,10 @@ def test_mixed_fp32_form_matches_oracle(name):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_equal_orders_bit_identical_to_one_order(precision):
+    """Every element at one order: no mortar faces, so the variable-order driver (order
+    groups, split state, captured stage sequence) runs the one-order build of the fused
+    kernels and must reproduce the uniform mesh bit for bit. (The mortar build, used
+    when orders differ, may round a few boundary values differently in the last bit.)"""
     m = W.config_airfoil(3, ni=24, nj=5, nk=2)
     mm = dict(m, orders=np.full(len(m["elem_nodes"]), 3, dtype=np.int32))
     g1, g2 = FRMesh(m, precision), FRMesh(mm, precision)
