@@ -434,8 +434,8 @@ def bench_pmix(args):
     t3 = timed_run(g3, u3, args.steps, args.warmup)
     dof3 = g3.E * g3.nu * g3.nv
     # step roofline: algorithmic bytes of both fused launches of every order group, four
-    # stages, plus the mortar gathers (each mortar point: its weights, codes and partner
-    # values in, one value out), over the measured step time
+    # stages, over the measured step time (the mortar points' table entries and partner
+    # values, read inside those launches, are not counted)
     orders, counts = np.unique(m["orders"], return_counts=True)
     step_bytes = 0.0
     for p, c in zip(orders, counts):

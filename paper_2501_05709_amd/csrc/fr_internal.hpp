@@ -33,7 +33,7 @@ constexpr int BC_WALL = 1;
 constexpr int BC_FARFIELD = 2;
 // A flux point on a face shared with an element of another order: index =
 // (mortar point << 1) | side, side 1 on the lower-order element.  Its partner data
-// come from the mortar buffers (DevArrays::MU, MX), filled by k_mortar_gather.
+// are formed in the fused kernels from the mortar tables (DevArrays::MO, MG, MC, MW).
 constexpr int BC_MORTAR = 3;
 
 enum Kernel {

@@ -1680,10 +1680,6 @@ static hipError_t pack_t(const LaunchCfg &c, const DevArrays &d, bool to_dev, vo
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// mortar gather (faces between elements of different orders): one thread per
-// (row, variable), a short FP64 dot product over the other side's face points
-// ---------------------------------------------------------------------------
 #define FR_DISPATCH(FN, ...)                                                              \
   do {                                                                                    \
     const int key = c.prec * 100 + c.dim * 10 + c.order;                                  \
