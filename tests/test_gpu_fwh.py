@@ -131,3 +131,34 @@ def test_copies_beyond_the_combined_filter_match_oracle():
         print(f"copies {shift[2]:g} apart: delay spread {spread:.0f} samples, {t.size} observer times", flush=True)
         assert t.size == to.size and t.size > 10
         assert close(p, po)
+
+
+def test_panels_of_both_summation_paths_in_one_chunk_match_oracle():
+    """Panels that need the copy-by-copy path and panels that take the combined filter,
+    interleaved so that every chunk of the summation holds both: a monopole sphere 20 from
+    the observer (5 copies 200 apart: delays spread about 285 samples) and the same samples
+    on a sphere moved 80 further away (spread about 233 samples).  Against the oracle."""
+    c = W.acoustic_case("monopole", (0.2, 0.0, 0.0), periods=12, n_polar=7, n_azimuth=11)
+    x = np.array([20.0, 3.0, 1.0])
+    shift = np.array([0.0, 0.0, 200.0])
+    n = c["points"].shape[0]
+    order = np.ravel(np.column_stack([np.arange(n), n + np.arange(n)]))   # A0, B0, A1, B1, ...
+    pts = np.concatenate([c["points"], c["points"] + np.array([-80.0, 0.0, 0.0])])[order]
+    nrm = np.concatenate([c["normals"], c["normals"]])[order]
+    area = np.concatenate([c["areas"], c["areas"]])[order]
+    rho = np.concatenate([c["rho"], c["rho"]], axis=1)[:, order]
+    u = np.concatenate([c["u"], c["u"]], axis=1)[:, order]
+    p = np.concatenate([c["p"], c["p"]], axis=1)[:, order]
+    R = fwh.radii(x[None], (pts[None] + fwh.copy_shifts(5, shift)[:, None]).reshape(-1, 3), c["mach"])[1]
+    spread = np.ptp(R.reshape(5, -1), axis=0) / c["c0"] / c["dt"]
+    assert spread[0::2].min() > 256 >= spread[1::2].max()   # both paths present, alternating
+    g = FWH(pts, nrm, area, c["mach"], c["c0"], c["rho0"], c["p0"], c["dt"], rho.shape[0], n_copies=5,
+            copy_shift=shift)
+    g.append(rho, u, p)
+    t, pr = g.pressure(x)
+    to, po, _, _ = fwh.observer_pressure(pts, nrm, area, rho, u, p, c["dt"], x, c["mach"], c["c0"], c["rho0"],
+                                         c["p0"], n_copies=5, shift=shift)
+    print(f"{len(pts)} panels, spreads {spread[1::2].max():.0f} and {spread[0::2].min():.0f} samples, "
+          f"{t.size} observer times", flush=True)
+    assert t.size == to.size and t.size > 100
+    assert close(pr, po)
