@@ -61,8 +61,8 @@ extern "C" {
 fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
   if (!d || !bytes || d->n_elems <= 0 || (d->dim != 2 && d->dim != 3)) return FR_E_ARG;
   if (d->elem_order) {
-    // variable order: the order groups' footprints, plus the mortar buffers and
-    // gather tables for at most every face point of every element
+    // variable order: the order groups' footprints, plus the mortar data for at most
+    // every face point of every element
     size_t total = 0;
     std::vector<int64_t> en_count(8, 0);
     for (int64_t e = 0; e < d->n_elems; ++e) {
@@ -90,7 +90,10 @@ fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
     const size_t rs = d->precision == FR_FP32 ? 4 : 8;
     const size_t pts = size_t(d->n_elems) * D.nf;
     total += size_t(nwall) * D.nfp * 3 * 8;
-    total += pts * D.nv * rs * 3 + pts * (2 * 4) + pts * D.nfp * (4 + 4 + 8);
+    // MT, the two per-point offset tables, the other side's entries (group, code,
+    // weight) and the projection entries (code, weight), up to nfp per point, and the
+    // groups' pointer arrays
+    total += pts * D.nv * rs + (pts + 2) * (2 * 4) + pts * D.nfp * ((4 + 4 + 8) + (4 + 8)) + 2 * 256;
     *bytes = total;
     return FR_OK;
   }

@@ -274,3 +274,54 @@ def test_mixed_unsupported_calls_are_rejected():
     with pytest.raises(_lib.FRError) as e:
         FRMesh(bad, "fp64")
     assert e.value.code == _lib.FR_E_UNSUPPORTED
+
+
+class _CountingAllocator:
+    """The binding's torch allocator bridge, counting the live and peak device bytes."""
+
+    def __init__(self, device):
+        import torch
+        self.live = self.peak = 0
+        self.sizes = {}
+
+        def _alloc(nbytes, ctx, stream):
+            ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+            self.sizes[ptr] = int(nbytes)
+            self.live += int(nbytes)
+            self.peak = max(self.peak, self.live)
+            return ptr
+
+        def _free(ptr, ctx, stream):
+            self.live -= self.sizes.pop(ptr, 0)
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc = _lib.ALLOC_FN(_alloc)
+        self.free = _lib.FREE_FN(_free)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("kind", ["uniform", "rings"])
+def test_footprint_bounds_the_device_memory_held(monkeypatch, precision, kind):
+    """fr_footprint, which the pool admits requests by, is at least the peak of what a
+    solver allocates through its allocator while it is built, set and stepped."""
+    from paper_2501_05709_amd import solver as S
+    m = ogrid(seed=2, ni=16, nj=8, nk=2)
+    if kind == "uniform":
+        m = {k: v for k, v in m.items() if k != "orders"}
+    counters = []
+
+    def make(device):
+        counters.append(_CountingAllocator(device))
+        return counters[-1]
+
+    monkeypatch.setattr(S, "_TorchAllocator", make)
+    g = FRMesh(m, precision)
+    fs = m["freestream"]
+    g.set_state(W.uniform_state(g.n_points, fs[0], fs[1:4], fs[4]).reshape(g.shape))
+    g.step(3)
+    g.forces()
+    peak = counters[0].peak
+    g.close()
+    bound = S.footprint(m, precision)
+    print(f"{kind} {precision}: peak {peak} B, footprint {bound} B", flush=True)
+    assert 0 < peak <= bound
