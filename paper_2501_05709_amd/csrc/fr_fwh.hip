@@ -36,7 +36,7 @@ namespace {
 
 constexpr int NQ = 4;          // Q, L1, L2, L3
 constexpr int SUM_WG = 256;    // threads of k_fwh_sum
-constexpr int SUM_OUT = 4;     // consecutive observer times per thread
+constexpr int SUM_OUT = 8;     // consecutive observer times per thread
 constexpr int SUM_PANELS = 8;  // panels per chunk
 constexpr int SUM_PAIRS = 64;  // copies of one panel whose weights share the LDS
 constexpr int SUM_SPAN = SUM_WG * SUM_OUT + 7 + 256;  // staged samples per series (delay spread up to 256)
@@ -241,9 +241,8 @@ __device__ inline int64_t copy_stencil(const double *geo, int64_t j, int c, int 
 // of 8 x copies multiply-adds per output; a panel whose copies' delays spread over more
 // than HMAX - 8 samples is summed copy by copy instead.
 constexpr int HMAX = 256 + 8;
-// filter rows padded to whole blocks of 4 taps (the taps past nh stay zero)
-constexpr int HROW = (HMAX + 3) / 4 * 4 + 4;
-static_assert(SUM_OUT == 4, "the filter loop below takes taps in blocks of SUM_OUT = 4");
+// filter rows padded to whole blocks of SUM_OUT taps (the taps past nh stay zero)
+constexpr int HROW = (HMAX + SUM_OUT - 1) / SUM_OUT * SUM_OUT + 4;
 
 // Per panel, once per evaluation (the same for every time chunk): the first sample of
 // each copy, their minimum b_min, and the combined filter of the copies, filt[j][x][k]
@@ -318,8 +317,8 @@ __global__ __launch_bounds__(SUM_WG) void k_fwh_sum(const double *__restrict__ s
   __shared__ int64_t Wb[SUM_PAIRS];
   // one source series at a time; the combined-filter path stores sample e at
   // (e % SUM_OUT) * XQ + e / SUM_OUT, so that the lanes of a wave, SUM_OUT samples apart,
-  // read consecutive words; 8 zero samples past the staged stretch (the filter loop runs
-  // whole blocks of 4 taps)
+  // read consecutive words; 2 SUM_OUT zero samples past the staged stretch (the filter
+  // loop runs whole blocks of SUM_OUT taps)
   constexpr int XQ = SUM_SPAN / SUM_OUT + 4;
   __shared__ double Xs[1][SUM_OUT * XQ];
   __shared__ double H[NQ][HROW];
@@ -343,34 +342,33 @@ __global__ __launch_bounds__(SUM_WG) void k_fwh_sum(const double *__restrict__ s
       // (3) each series over [bmin + mt0, bmax + mlast + 8) in turn, then the filter
       const int64_t lo = bmin + mt0, span = int64_t(nh - 8) + (mlast - mt0) + 8;
       for (int x = 0; x < NQ; ++x) {
-        for (int64_t k = tid; k < span + 8; k += SUM_WG)
+        for (int64_t k = tid; k < span + 2 * SUM_OUT; k += SUM_WG)
           Xs[0][int(k % SUM_OUT) * XQ + int(k / SUM_OUT)] = k < span ? src[(x * np + j) * cap + lo + k] : 0.0;
         __syncthreads();
         if (m0 <= mlast) {
-          // this thread's samples start at tid * SUM_OUT. Taps go in blocks of 4 over a
-          // window of 8 samples, w[r] = sample tid * 4 + 4 b + r, in tap order for each
-          // output (the zero taps past nh add nothing): 16 multiply-adds per 4 samples
-          // read, the taps read as a broadcast
+          // this thread's samples start at tid * SUM_OUT. Taps go in blocks of SUM_OUT
+          // over a window of 2 SUM_OUT samples, w[r] = sample tid * SUM_OUT + SUM_OUT b + r,
+          // in tap order for each output (the zero taps past nh add nothing):
+          // SUM_OUT^2 multiply-adds per SUM_OUT samples read, the taps read as a broadcast
           const double *X0 = &Xs[0][tid];
-          double w[8], acc[SUM_OUT];
+          double w[2 * SUM_OUT], acc[SUM_OUT];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
+          for (int r = 0; r < SUM_OUT; ++r) {
             w[r] = X0[r * XQ];
             acc[r] = 0.0;
           }
-          const int nblk = (nh + 3) / 4;
-#pragma unroll 2
+          const int nblk = (nh + SUM_OUT - 1) / SUM_OUT;
           for (int b = 0; b < nblk; ++b) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) w[4 + r] = X0[r * XQ + b + 1];
+            for (int r = 0; r < SUM_OUT; ++r) w[SUM_OUT + r] = X0[r * XQ + b + 1];
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-              const double hk = H[x][4 * b + kk];
+            for (int kk = 0; kk < SUM_OUT; ++kk) {
+              const double hk = H[x][SUM_OUT * b + kk];
 #pragma unroll
               for (int o = 0; o < SUM_OUT; ++o) acc[o] += hk * w[o + kk];
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) w[r] = w[4 + r];
+            for (int r = 0; r < SUM_OUT; ++r) w[r] = w[SUM_OUT + r];
           }
 #pragma unroll
           for (int o = 0; o < SUM_OUT; ++o) {
