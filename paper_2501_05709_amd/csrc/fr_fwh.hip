@@ -688,7 +688,7 @@ namespace {
 void fwh_compute(fr_fwh *h, const double *observer, const Window &w, double *p, double *p_thickness,
                  double *p_loading) {
   const int64_t nchunk = (h->np + SUM_PANELS - 1) / SUM_PANELS;
-  if (nchunk > 65535) fail(FR_E_UNSUPPORTED, "too many panels for one launch");
+  if (nchunk > 65535) fail(FR_E_UNSUPPORTED, "too many panels for one launch");  // also bounds the filter grid
   h->grow(h->part, h->part_bytes, size_t(nchunk) * 2 * w.n_out * sizeof(double));
   h->grow(h->part2, h->part2_bytes, size_t(RED_GROUPS) * 2 * w.n_out * sizeof(double));
   h->grow(h->out, h->out_bytes, size_t(3) * w.n_out * sizeof(double));
