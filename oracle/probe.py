@@ -70,15 +70,20 @@ def locate(mesh, points, tol=1e-10):
             X = nodes[conn[e]]
             r = np.zeros(dim)
             ok = False
+            prev = np.inf
             for _ in range(50):
                 x, J = geometry(X, q, dim, r)
                 dr = np.linalg.solve(J, p - x)
                 r = r + dr
-                if np.abs(dr).max() < 1e-14:
+                step = np.abs(dr).max()
+                # converged: below 1e-14, or at the round-off floor (below 1e-10 and no
+                # longer shrinking), which thin curved elements put above 1e-14
+                if step < 1e-14 or (step < 1e-10 and step >= prev):
                     ok = True
                     break
                 if np.abs(r).max() > 3.0:
                     break
+                prev = step
             if ok and np.abs(r).max() <= 1.0 + tol:
                 elem[i] = e
                 xi[i, :dim] = r

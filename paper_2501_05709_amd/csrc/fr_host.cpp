@@ -1723,10 +1723,13 @@ struct fr_probe {
 namespace {
 
 // x(r) = p by Newton's method from the element centre; true with r when the
-// iteration converges inside the reference cube (tolerance 1e-10)
+// iteration converges inside the reference cube (tolerance 1e-10). Converged: a step
+// below 1e-14, or below 1e-10 and no smaller than the one before (the round-off floor,
+// which in thin curved elements lies above 1e-14)
 bool locate_in(const fr_mesh_desc &d, int64_t e, const double *p, std::array<double, 3> &r) {
   const int dim = d.dim;
   r = {0.0, 0.0, 0.0};
+  double prev = INFINITY;
   for (int it = 0; it < 50; ++it) {
     double x[3], a[3][3];
     geom_map(d, e, r, x, a);
@@ -1753,12 +1756,13 @@ bool locate_in(const fr_mesh_desc &d, int64_t e, const double *p, std::array<dou
       step = std::max(step, std::fabs(dr[k]));
       big = std::max(big, std::fabs(r[k]));
     }
-    if (step < 1e-14) {
+    if (step < 1e-14 || (step < 1e-10 && step >= prev)) {
       for (int k = 0; k < dim; ++k)
         if (std::fabs(r[k]) > 1.0 + 1e-10) return false;
       return true;
     }
     if (big > 3.0) return false;
+    prev = step;
   }
   return false;
 }

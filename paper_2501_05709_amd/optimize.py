@@ -28,13 +28,14 @@ Set-up (non-dimensional: chord, free-stream density and speed are 1):
 from __future__ import annotations
 
 import math
+import time
 from dataclasses import dataclass
 
 import numpy as np
 
 from . import mads
 from . import workloads as W
-from ._lib import FRError
+from ._lib import FR_E_MESH, FRError
 from .solver import FRPool
 
 # sea-level air at Mach 0.2 fixes the dimensional dynamic pressure that turns 20 uPa
@@ -138,14 +139,18 @@ class Outcome:
 
 
 class PoolEvaluator:
-    """Runs candidate designs (unscaled vectors) as concurrent pool requests."""
+    """Runs candidate designs (unscaled vectors) as concurrent pool requests.
 
-    def __init__(self, study: Study, x_baseline):
+    progress: optional callable taking a message, called at most every `every_s` seconds
+    while requests run."""
+
+    def __init__(self, study: Study, x_baseline, progress=None, every_s=30.0):
         self.study = study
         self.dt = study.mesh(x_baseline)["dt"]
         self.pool = FRPool(study.budget_bytes, study.device)
         self.pref = p_ref()
         self.max_running = 0
+        self.progress, self.every_s = progress, every_s
 
     def close(self):
         self.pool.close()
@@ -155,13 +160,18 @@ class PoolEvaluator:
         out = [None] * len(designs)
         pending = list(range(len(designs)))
         running = {}
+        last = time.perf_counter()
         while pending or running:
             while pending:
                 i = pending[0]
                 try:
                     slot = self.pool.admit_sampled(s.mesh(designs[i], self.dt), s.surface(designs[i]), s.warmup,
                                                    s.every, s.n_samples, precision=s.precision)
-                except (FRError, ValueError):
+                except (FRError, ValueError) as e:
+                    if isinstance(e, FRError) and e.code != FR_E_MESH:
+                        # the mesh is valid but the request is not (e.g. a surface point
+                        # outside the grid): a set-up error, not an infeasible design
+                        raise RuntimeError(f"design {list(designs[i])}: {e}") from e
                     out[i] = Outcome(math.inf, math.nan, math.nan, ok=False)  # no valid mesh: infeasible
                     pending.pop(0)
                     continue
@@ -174,6 +184,10 @@ class PoolEvaluator:
             self.max_running = max(self.max_running, len(running))
             if not running:
                 break
+            if self.progress is not None and time.perf_counter() - last >= self.every_s:
+                last = time.perf_counter()
+                self.progress(f"{len(running)} designs running, {sum(o is not None for o in out)} of "
+                              f"{len(designs)} done, {len(pending)} waiting")
             for slot in self.pool.tick(s.chunk):
                 i = running.pop(slot)
                 p = err = None
@@ -195,7 +209,7 @@ class PoolEvaluator:
 def optimise(study: Study, x0, l0=2, max_iter=100, mesh_tol=1e-6, move_tol=0.01, log=None):
     """OrthoMADS from the unscaled baseline x0.  Returns (mads.Result with the scaled
     incumbent, baseline Outcome, {design tuple: Outcome} of every solved design)."""
-    ev = PoolEvaluator(study, x0)
+    ev = PoolEvaluator(study, x0, progress=log)
     seen = {}
     try:
         base = ev([np.asarray(x0, dtype=np.float64)])[0]
@@ -221,3 +235,53 @@ def optimise(study: Study, x0, l0=2, max_iter=100, mesh_tol=1e-6, move_tol=0.01,
         return res, base, seen
     finally:
         ev.close()
+
+
+def main(argv=None):
+    """Run Algorithm 1 from the baseline of Section 3.4 (NACA 0012 at 6 degrees) over the
+    served pool; print one line per poll and a JSON summary.
+
+        python -m paper_2501_05709_amd.optimize [--max-iter K] [--bands] [sizes ...]
+    """
+    import argparse
+    import json
+    import time
+    ap = argparse.ArgumentParser(description=main.__doc__.split("\n")[0])
+    ap.add_argument("--max-iter", type=int, default=100)
+    ap.add_argument("--l0", type=int, default=2, help="initial mesh index (mesh size 4^-l0)")
+    ap.add_argument("--ni", type=int, default=160)
+    ap.add_argument("--nj", type=int, default=48)
+    ap.add_argument("--nk", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--every", type=int, default=4)
+    ap.add_argument("--n-samples", type=int, default=1024)
+    ap.add_argument("--spacing", type=float, default=0.01)
+    ap.add_argument("--lz", type=float, default=25.0, help="spanwise extent of the copied data surface")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--bands", action="store_true",
+                    help="P3 in the 12 wall layers, then P2, P1, P0 in bands of 12 (Section 3.1)")
+    args = ap.parse_args(argv)
+    bands = ((12, 3), (24, 2), (36, 1), (args.nj, 0)) if args.bands else None
+    st = Study(ni=args.ni, nj=args.nj, nk=args.nk, warmup=args.warmup, every=args.every,
+               n_samples=args.n_samples, spacing=args.spacing, lz=args.lz, precision=args.precision, bands=bands)
+    x0 = np.array([0.0, 6.5, 12.0, 6.0])
+    t0 = time.perf_counter()
+
+    def log(msg):
+        print(f"[{time.perf_counter() - t0:8.1f} s] {msg}", flush=True)
+
+    log(f"baseline {list(x0)}: {st.ni}x{st.nj}x{st.nk} O-grid, {st.warmup} + {st.n_samples - 1} x "
+        f"{st.every} steps per design, data surface spacing {st.spacing}, copies over {st.lz} chords")
+    res, base, seen = optimise(st, x0, l0=args.l0, max_iter=args.max_iter, log=log)
+    wall = time.perf_counter() - t0
+    for k, dm, f, x in res.history:
+        log(f"iteration {k}: mesh size {dm:.3g}, incumbent {f:.4f} at {[round(v, 3) for v in mads.unscale(x)]}")
+    print(json.dumps({
+        "iterations": res.iterations, "evaluations": res.evaluations, "designs_solved": len(seen),
+        "wall_s": round(wall, 1), "baseline": {"oaspl_db": base.oaspl, "cl": base.cl, "cd": base.cd},
+        "best": {"design": [float(v) for v in mads.unscale(res.x)], "objective": res.f},
+    }))
+
+
+if __name__ == "__main__":
+    main()

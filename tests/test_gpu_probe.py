@@ -116,3 +116,24 @@ def test_sampled_run_to_far_field_matches_oracle():
     err = np.abs(p - po).max() / np.abs(po).max()
     print(f"sampled run -> far field: {t.size} observer times, max rel err {err:.2e}", flush=True)
     assert err <= 1e-10
+
+
+def test_full_size_data_surface_located_like_oracle():
+    """The paper-scale set-up: the 24,000-panel data surface of Section 3.1 in the
+    160 x 48 x 8 O-grid of the baseline design (thin, curved wall-normal elements, where
+    Newton's step can stall at its round-off floor above 1e-14).  Every point is located,
+    and the first 128 (point 12 among them stalls that way) exactly as by the oracle."""
+    from paper_2501_05709_amd import optimize as O
+    st = O.Study(lz=1.0)
+    x0 = np.array([0.0, 6.5, 12.0, 6.0])
+    m, s = st.mesh(x0), st.surface(x0)
+    pts = s["points"]
+    g = FRMesh(m, "fp32")
+    pr = Probe(g, pts)
+    e, xi = pr.locate()
+    assert e.shape == (len(pts),) and np.all(e >= 0) and np.abs(xi).max() <= 1.0 + 1e-10
+    e_ref, xi_ref = probe.locate(m, pts[:128])
+    assert np.array_equal(e[:128], e_ref)
+    assert np.abs(xi[:128] - xi_ref).max() <= 1e-12
+    pr.close()
+    g.close()

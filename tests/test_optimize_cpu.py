@@ -65,8 +65,9 @@ class FakePool:
     """Stand-in for FRPool: admits while fewer than `cap` run, finishes a request after
     ceil(steps / k) ticks; its results are functions of the design's free stream."""
 
-    def __init__(self, budget_bytes, device=0, cap=3, fail_aoa=(), nonfinite_aoa=(), short_aoa=()):
+    def __init__(self, budget_bytes, device=0, cap=3, fail_aoa=(), nonfinite_aoa=(), short_aoa=(), outside_aoa=()):
         self.cap, self.fail_aoa, self.nonfinite_aoa, self.short_aoa = cap, fail_aoa, nonfinite_aoa, short_aoa
+        self.outside_aoa = outside_aoa
         self.run, self.done, self.next = {}, {}, 0
         self.admitted = []
 
@@ -77,6 +78,8 @@ class FakePool:
         aoa = round(math.degrees(math.atan2(mesh["freestream"][2], mesh["freestream"][1])), 9)
         if aoa in self.fail_aoa:
             raise _lib.FRError(_lib.FR_E_MESH, "non-positive Jacobian")
+        if aoa in self.outside_aoa:
+            raise _lib.FRError(_lib.FR_E_ARG, "point 12 lies in no element")
         if len(self.run) >= self.cap:
             return None
         slot = self.next
@@ -152,4 +155,14 @@ def test_pool_evaluator_does_not_hide_a_too_short_record(monkeypatch):
     st = O.Study(ni=8, nj=3, nk=1, radius=8.0, spacing=0.5, lz=1.0, warmup=4, every=2, n_samples=16, chunk=8)
     ev = O.PoolEvaluator(st, [0.0, 6.5, 12.0, 3.0])
     with pytest.raises(RuntimeError, match="too short"):
+        ev([[0.0, 6.5, 12.0, 1.0], [0.0, 6.5, 12.0, 2.0]])
+
+
+def test_pool_evaluator_does_not_hide_a_surface_outside_the_grid(monkeypatch):
+    """A valid mesh whose request the library rejects for another reason (a data-surface
+    point in no element) is a set-up error: it raises instead of counting as infeasible."""
+    monkeypatch.setattr(O, "FRPool", lambda budget, device=0: FakePool(budget, device, outside_aoa=(2.0,)))
+    st = O.Study(ni=8, nj=3, nk=1, radius=8.0, spacing=0.5, lz=1.0, warmup=4, every=2, n_samples=16, chunk=8)
+    ev = O.PoolEvaluator(st, [0.0, 6.5, 12.0, 3.0])
+    with pytest.raises(RuntimeError, match="lies in no element"):
         ev([[0.0, 6.5, 12.0, 1.0], [0.0, 6.5, 12.0, 2.0]])
