@@ -308,6 +308,41 @@ def combined_filter_taps(case, x, t_start):
     return first.max(axis=0) - first.min(axis=0) + 8.0
 
 
+def measured_ceilings():
+    """Streaming and matrix ceilings measured on this GPU, reported beside the published
+    peaks the rooflines use: a 1 GiB device-to-device copy (read + write bytes over time)
+    and FP32 / FP64 library GEMMs (2 n^3 flops over time), each the mean of 10 after 3
+    warm-up runs, timed with events on torch's stream."""
+    import torch
+
+    def timed(fn, reps=10):
+        for _ in range(3):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps * 1e-3
+    n = 2 ** 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    t_copy = timed(lambda: dst.copy_(src))
+    del src, dst
+    out = {"copy_gbs": round(2 * n * 4 / t_copy / 1e9, 1)}
+    for name, dt, k in (("sgemm_tflops", torch.float32, 8192), ("dgemm_tflops", torch.float64, 4096)):
+        a = torch.rand(k, k, dtype=dt, device="cuda")
+        b = torch.rand(k, k, dtype=dt, device="cuda")
+        t = timed(lambda: torch.matmul(a, b))
+        out[name] = round(2.0 * k ** 3 / t / 1e12, 1)
+        del a, b
+    torch.cuda.empty_cache()
+    out["note"] = ("measured beside the published peaks (HBM 8 TB/s, FP32 157.3 and FP64 78.6 TFLOP/s), "
+                   "which the rooflines use")
+    return out
+
+
 def bench_fwh(args):
     """Far-field pressure at the paper's observer from its airfoil data surface (24,000
     panels, 4,332 samples, 125 spanwise copies filling 25 chords)."""
@@ -644,6 +679,7 @@ def main():
                             "fp64_value": round(dof * args.steps / t64_dense, 1)},
         "kernels": kernels,
         "roofline": roof,
+        "measured_ceilings": measured_ceilings(),
         "dense_mfma_kernels_fp32": dense_kernels,
         "cpu_baseline": cpu,
     }
