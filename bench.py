@@ -308,6 +308,20 @@ def combined_filter_taps(case, x, t_start):
     return first.max(axis=0) - first.min(axis=0) + 8.0
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs"
+
+
 def measured_ceilings():
     """Streaming and matrix ceilings measured on this GPU, reported beside the published
     peaks the rooflines use: a 1 GiB device-to-device copy (read + write bytes over time)
@@ -556,7 +570,7 @@ def main():
         ref_sample = o.rk4(u0, m["dt"], n_sample)
         tc = time.perf_counter() - t0
         cpu = {"value": dof * n_sample / tc, "unit": "DOF-updates/s", "cores": num_threads(),
-               "kind": "oracle",
+               "kind": "oracle", "host": host_cpu(),
                "sample": f"{n_sample} RK4 steps of the full {desc['workload']} mesh, FP64, "
                          f"OpenMP over elements, {tc:.1f} s"}
 
