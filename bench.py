@@ -308,6 +308,27 @@ def combined_filter_taps(case, x, t_start):
     return first.max(axis=0) - first.min(axis=0) + 8.0
 
 
+def oracle_one_thread(workload, steps=1):
+    """The oracle's DOF-updates/s on one host thread: a child process (no GPU use) with
+    OMP_NUM_THREADS=1 runs `steps` RK4 steps of the workload's mesh."""
+    import subprocess
+    code = ("import sys, time, json; sys.path.insert(0, %r); import bench; "
+            "from oracle.oracle import OracleMesh, num_threads; import numpy as np; "
+            "m, desc = bench.build_workload(%r); o = OracleMesh(m); "
+            "u0 = np.ascontiguousarray(m['init'](o.solution_points().reshape(-1, 3)).reshape(o.shape)); "
+            "t0 = time.perf_counter(); o.rk4(u0, m['dt'], %d); t = time.perf_counter() - t0; "
+            "print(json.dumps({'value': o.E * o.nu * o.nv * %d / t, 'threads': num_threads(), 's': t}))"
+            % (ROOT, workload, steps, steps))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+        return {"value": d["value"], "cores": d["threads"],
+                "sample": f"{steps} RK4 step of the full mesh on one thread, {d['s']:.1f} s"}
+    except Exception as e:  # reported, not fatal: the GPU figures stand on their own
+        return {"value": None, "error": str(e)[:200]}
+
+
 def host_cpu():
     """Model name and logical CPU count of the host the oracle runs on."""
     model = "unknown"
@@ -570,7 +591,7 @@ def main():
         ref_sample = o.rk4(u0, m["dt"], n_sample)
         tc = time.perf_counter() - t0
         cpu = {"value": dof * n_sample / tc, "unit": "DOF-updates/s", "cores": num_threads(),
-               "kind": "oracle", "host": host_cpu(),
+               "kind": "oracle", "host": host_cpu(), "one_thread": oracle_one_thread(args.workload),
                "sample": f"{n_sample} RK4 steps of the full {desc['workload']} mesh, FP64, "
                          f"OpenMP over elements, {tc:.1f} s"}
 
