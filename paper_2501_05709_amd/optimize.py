@@ -167,10 +167,11 @@ class PoolEvaluator:
                 try:
                     slot = self.pool.admit_sampled(s.mesh(designs[i], self.dt), s.surface(designs[i]), s.warmup,
                                                    s.every, s.n_samples, precision=s.precision)
-                except (FRError, ValueError) as e:
-                    if isinstance(e, FRError) and e.code != FR_E_MESH:
+                except FRError as e:
+                    if e.code != FR_E_MESH:
                         # the mesh is valid but the request is not (e.g. a surface point
-                        # outside the grid): a set-up error, not an infeasible design
+                        # outside the grid): a set-up error, not an infeasible design; so is
+                        # any other exception, which is not caught here
                         raise RuntimeError(f"design {list(designs[i])}: {e}") from e
                     out[i] = Outcome(math.inf, math.nan, math.nan, ok=False)  # no valid mesh: infeasible
                     pending.pop(0)
