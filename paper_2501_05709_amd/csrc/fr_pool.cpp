@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <set>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -88,12 +89,53 @@ fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
       if (d->bfaces[3 * i + 2] == FR_BC_WALL) ++nwall;
     const fr::Dims D(d->dim, int(maxp));
     const size_t rs = d->precision == FR_FP32 ? 4 : 8;
-    const size_t pts = size_t(d->n_elems) * D.nf;
     total += size_t(nwall) * D.nfp * 3 * 8;
-    // MT, the two per-point offset tables, the other side's entries (group, code,
-    // weight) and the projection entries (code, weight), up to nfp per point, and the
-    // groups' pointer arrays
-    total += pts * D.nv * rs + (pts + 2) * (2 * 4) + pts * D.nfp * ((4 + 4 + 8) + (4 + 8)) + 2 * 256;
+    // mortar data. Faces are matched by their corner node ids; a face shared by elements
+    // of two orders carries nfp_H + nfp_L mortar points, nfp_H nfp_L interpolation entries
+    // and, for its lower-order points, nfp_L nfp_H trace and nfp_L nfp_H projection
+    // entries. A face matched by no other element and not a listed boundary face (a
+    // periodic face, paired by translation) is counted as a mortar face at the highest
+    // order on both sides, an upper bound.
+    const int dim = d->dim, q = d->geom_order, na = q + 1, nfe = 2 * dim, nc = dim == 2 ? 2 : 4;
+    const int nn = dim == 2 ? na * na : na * na * na;
+    if (q < 1 || !d->nodes || !d->elem_nodes) return FR_E_ARG;
+    auto nfp_of = [&](int64_t p) { return size_t(dim == 2 ? p + 1 : (p + 1) * (p + 1)); };
+    std::set<std::pair<int64_t, int>> listed;
+    for (int64_t i = 0; i < d->n_bfaces; ++i) listed.insert({d->bfaces[3 * i], int(d->bfaces[3 * i + 1])});
+    std::map<std::array<int64_t, 4>, std::pair<int64_t, int>> seen;  // corner ids -> (element, face)
+    size_t mpts = 0, ment = 0, pent = 0;
+    auto add = [&](size_t hi, size_t lo) {
+      mpts += hi + lo;
+      ment += 2 * hi * lo;
+      pent += hi * lo;
+    };
+    for (int64_t e = 0; e < d->n_elems; ++e)
+      for (int f = 0; f < nfe; ++f) {
+        const int k = f / 2;
+        std::array<int64_t, 4> key{-1, -1, -1, -1};
+        for (int c = 0; c < nc; ++c) {
+          int a[3] = {0, 0, 0}, o = 0;
+          a[k] = (f & 1) * q;
+          for (int j = 0; j < dim; ++j)
+            if (j != k) a[j] = ((c >> o++) & 1) * q;
+          key[size_t(c)] = d->elem_nodes[e * nn + a[0] + na * a[1] + na * na * a[2]];
+        }
+        std::sort(key.begin(), key.begin() + nc);
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+          seen.emplace(key, std::make_pair(e, f));
+          continue;
+        }
+        const int64_t pa = d->elem_order[it->second.first], pb = d->elem_order[e];
+        if (pa != pb) add(nfp_of(std::max(pa, pb)), nfp_of(std::min(pa, pb)));
+        seen.erase(it);
+      }
+    for (const auto &kv : seen)
+      if (!listed.count(kv.second)) add(D.nfp, D.nfp);
+    // MT, the two per-point offset tables, the trace / half-flux entries (group, code,
+    // weight) and the projection entries (code, weight), and the groups' pointer arrays
+    total += std::max<size_t>(mpts, 1) * D.nv * rs + (mpts + 2) * (2 * 4) + ment * (4 + 4 + 8) +
+             pent * (4 + 8) + 4 * 256;
     *bytes = total;
     return FR_OK;
   }
