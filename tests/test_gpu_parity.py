@@ -51,6 +51,10 @@ def perturbed(o, mesh, amp=0.1, seed=0):
 def case(name):
     if name == "vortex2d_p3":
         return W.config_vortex(0)
+    if name == "vortex2d_p1":
+        return W.config_vortex(3, nel=9, order=1)
+    if name == "vortex2d_p4":
+        return W.config_vortex(4, nel=5, order=4)
     if name == "box2d_curved_p2":
         m = W.box_mesh(2, (5, 4), (0, 0), (1, 1), q=2, warp=0.05, order=2)
         m.update(gamma=1.4, prandtl=0.72, mu=0.02, freestream=np.array([1.0, 0.3, -0.2, 0.0, 1.0]), dt=1e-3)
@@ -68,7 +72,7 @@ def case(name):
     raise KeyError(name)
 
 
-CASES = ["vortex2d_p3", "box2d_curved_p2", "tgv_p1", "tgv_p2", "tgv_p3", "tgv_p4", "tgv_p3_one", "tgv_p2_two",
+CASES = ["vortex2d_p3", "vortex2d_p1", "vortex2d_p4", "box2d_curved_p2", "tgv_p1", "tgv_p2", "tgv_p3", "tgv_p4", "tgv_p3_one", "tgv_p2_two",
          "airfoil_p3", "airfoil_p2"]
 # kernel structures / operator back-ends: five launches per stage with dense
 # element-batched MFMA contractions or sum factorisation, or the fused
