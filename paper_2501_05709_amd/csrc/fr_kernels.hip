@@ -1004,6 +1004,10 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   T *Us = L, *Ds = L + S::NU * NV * EW;
   T *Gs = L, *Fs = L + S::NU * NG * EW;
   __shared__ Basis<T, N> B;
+  // FP32: the Rusanov fluxes of the face pass wait in LDS through the gradient and flux
+  // passes (each lane reads back only what it wrote); held in registers they spill
+  constexpr bool FQL = sizeof(T) == 4;
+  __shared__ T Lq[FQL ? S::NF * NV * EW : 1];
   const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t blk = wg / NS;
   const int e0 = int(wg % NS) * EW;
@@ -1120,6 +1124,10 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
         ub[DIM + 1] = ufv[it][DIM + 1];
       }
       gas.rusanov(ufv[it], ub, nrm[it], fiv[it]);
+      if constexpr (FQL) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Lq[(q * NV + v) * EW + e] = fiv[it][v];
+      }
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) du[v] = 0;
@@ -1215,7 +1223,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       for (int v = 0; v < NV; ++v) {
         const T pv = T(0.5) * fn[v];
         a.PV[at(blk, q, v, eg, S::NFPAD, NV)] = pv;
-        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = fiv[it][v] - pv;
+        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = (FQL ? Lq[(q * NV + v) * EW + e] : fiv[it][v]) - pv;
       }
     } else {
       const int code = -nb;
@@ -1228,7 +1236,8 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
         gas.flux_vis_n(ub, gf, nrm[it], fn, true);
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = fiv[it][v] - fn[v];
+      for (int v = 0; v < NV; ++v)
+        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = (FQL ? Lq[(q * NV + v) * EW + e] : fiv[it][v]) - fn[v];
       if (forces && (code & 3) == BC_WALL) {
         // traction of the fluid on the body: W A (p n - tau . n), interior trace
         T Fw[DIM][NV];
