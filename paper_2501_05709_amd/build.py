@@ -8,7 +8,9 @@ instructions are disabled for all device code.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import json
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -37,18 +39,45 @@ def common_flags():
             "-I", os.path.join(ROOT, "include")]
 
 
+_RESOURCE_KEYS = {"VGPRs": "vgpr", "AGPRs": "agpr", "SGPRs Spill": "sgpr_spill", "VGPRs Spill": "vgpr_spill",
+                  "ScratchSize [bytes/lane]": "scratch", "Occupancy [waves/SIMD]": "occupancy",
+                  "LDS Size [bytes/block]": "lds"}
+
+
+def parse_resource_usage(text):
+    """Per-kernel resource usage from the compiler's kernel-resource-usage remarks:
+    {mangled name: {vgpr, agpr, sgpr_spill, vgpr_spill, scratch, occupancy, lds}}."""
+    out, cur = {}, None
+    for line in text.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = out.setdefault(m.group(1), {})
+            continue
+        m = re.search(r"remark:\s+([A-Za-z /\[\]]+?):\s+(-?\d+)\s", line + " ")
+        if cur is not None and m and m.group(1).strip() in _RESOURCE_KEYS:
+            cur[_RESOURCE_KEYS[m.group(1).strip()]] = int(m.group(2))
+    return out
+
+
 def _compile(src, verbose):
     os.makedirs(OBJ, exist_ok=True)
     out = os.path.join(OBJ, os.path.basename(src) + ".o")
-    lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [hipcc()] + common_flags() + lang + ["-c", os.path.join(CSRC, src), "-o", out]
+    device = src.endswith(".hip")
+    lang = ["-x", "hip"] if device else []
+    # device sources also report each kernel's registers, spills, occupancy and LDS
+    remarks = ["-Rpass-analysis=kernel-resource-usage"] if device else []
+    cmd = [hipcc()] + common_flags() + lang + remarks + ["-c", os.path.join(CSRC, src), "-o", out]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {src}\n{r.stdout}\n{r.stderr}")
-    if verbose and r.stderr.strip():
-        print(r.stderr, flush=True)
+    if device:
+        with open(os.path.join(OBJ, os.path.basename(src) + ".resources.json"), "w") as f:
+            json.dump(parse_resource_usage(r.stderr), f, indent=0, sort_keys=True)
+    warnings = "\n".join(l for l in r.stderr.splitlines() if "warning:" in l)
+    if verbose and warnings:
+        print(warnings, flush=True)
     return out
 
 
