@@ -484,7 +484,7 @@ def bench_pmix(args):
         tc = time.perf_counter() - t0
         cpu = {"value": dof * n_sample / tc, "unit": "DOF-updates/s", "cores": num_threads(), "kind": "oracle",
                "sample": f"{n_sample} RK4 steps of the full {desc['workload']} mesh, FP64, OpenMP over elements, "
-                         f"{tc:.1f} s"}
+                         f"{tc:.1f} s wall on {num_threads()} threads ({tc * num_threads():.0f} thread-s)"}
     g64 = FRMesh(m, "fp64")
     if ref is not None:
         for g in (g64, g32):
@@ -593,7 +593,8 @@ def main():
         cpu = {"value": dof * n_sample / tc, "unit": "DOF-updates/s", "cores": num_threads(),
                "kind": "oracle", "host": host_cpu(), "one_thread": oracle_one_thread(args.workload),
                "sample": f"{n_sample} RK4 steps of the full {desc['workload']} mesh, FP64, "
-                         f"OpenMP over elements, {tc:.1f} s"}
+                         f"OpenMP over elements, {tc:.1f} s wall on {num_threads()} threads "
+                         f"({tc * num_threads():.0f} thread-s)"}
 
     # --- autotune the operator back-end of every kernel (dense MFMA vs sum factorised)
     g32.set_state(u0)
