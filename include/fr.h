@@ -120,7 +120,10 @@ typedef struct {
 /* Build a solver for one mesh: connectivity (faces matched by node ids,
  * periodic faces by the listed translations, flux points by position),
  * FP64 metrics, operators, device arrays.  FR_E_MESH if a face is neither
- * matched nor listed as a boundary, or a Jacobian is not positive. */
+ * matched nor listed as a boundary, or a Jacobian is not positive.
+ * Follows Algorithm 1 (each candidate design gets its own mesh before its
+ * flow solve) and the set-up of Section 3.1 (spanwise-periodic airfoil grid,
+ * curved elements); the FR discretisation is the one named in Section 1. */
 fr_status fr_mesh_create(const fr_mesh_desc *desc, fr_mesh **out);
 
 /* Several meshes (candidate designs) advanced together by every kernel
@@ -141,7 +144,8 @@ fr_status fr_mesh_info(const fr_mesh *m, int64_t *info);
 /* Elements of design d and their offset in the concatenated arrays. */
 fr_status fr_design_range(const fr_mesh *m, int32_t design, int64_t *first, int64_t *count);
 
-/* Physical coordinates of the solution points, [elements][n_u][3] (z = 0 in 2D). */
+/* Physical coordinates of the solution points, [elements][n_u][3] (z = 0 in 2D),
+ * into caller-owned host memory: where initial conditions are evaluated. */
 fr_status fr_solution_points(const fr_mesh *m, double *xyz);
 
 /* Partner of every flux point, [elements][n_f]: e' * n_f + q' for an
@@ -159,28 +163,45 @@ fr_status fr_mesh_points(const fr_mesh *m, int64_t *n_points);
  * solution points [n_elems][n_u][3]. */
 fr_status fr_connectivity(const fr_mesh_desc *desc, int64_t *nbr, double *xyz);
 
-/* Set / get the conserved state (host, FP64, canonical layout).  Setting
- * the state also clears the running lift and drag means. */
+/* Set / get the conserved state (host, FP64, canonical layout): the
+ * variables of Eq. (2) of Section 2.1, rho, rho u_i, rho E, at every
+ * solution point.  Setting the state also clears the running lift and drag
+ * means (Section 3.4 averages them over the solve).  u is read (set) or
+ * written (get) during the call only.  FR_E_STATE from fr_get_state before
+ * any state was set. */
 fr_status fr_set_state(fr_mesh *m, const double *u);
 fr_status fr_get_state(const fr_mesh *m, double *u);
 
-/* Advance n RK4 steps of dt on the device and wait for them.  After each
- * step the wall force of the new state is added to the running means.
- * FR_E_NONFINITE if any step produced a non-finite value. */
+/* Advance n RK4 steps of dt on the device and wait for them: the time
+ * integration of Eq. (1) of Section 2.1, du/dt = -div F, with classic
+ * four-stage Runge-Kutta and a fixed step in place of the paper's
+ * second-order scheme with adaptive steps (Section 3.1, whose coefficients
+ * are not given).  After each step the wall force of the new state is added
+ * to the running means.  FR_E_NONFINITE if any step produced a non-finite
+ * value (the state is left as computed); FR_E_STATE if no state was set;
+ * FR_E_ARG for n < 0. */
 fr_status fr_step(fr_mesh *m, int64_t n);
 
-/* Enqueue n steps without waiting (the state stays in device memory). */
+/* Enqueue n steps (as fr_step) without waiting; the state stays in device
+ * memory.  This is what lets the poll designs of Algorithm 1 run side by
+ * side on one device. */
 fr_status fr_step_async(fr_mesh *m, int64_t n);
 /* Wait for enqueued work; reports FR_E_NONFINITE like fr_step. */
 fr_status fr_sync(fr_mesh *m);
 
 /* out[0..7] = C_L, C_D, F_x, F_y, F_z of the last step; mean C_L, mean C_D
  * over the steps since the state was set; number of steps averaged.
- * Lift and drag come from the wall traction integral of (p n - tau . n). */
+ * Lift and drag come from the wall traction integral of (p n - tau . n),
+ * with p and the stress tau of Eqs. (5)-(6) of Section 2.1; the means are
+ * the time-averaged lift and drag coefficients of the objective of Section
+ * 3.4 (summed in FP64).  out is host memory of 8 doubles; FR_E_ARG for a
+ * design index outside the batch. */
 fr_status fr_forces(const fr_mesh *m, int32_t design, double *out);
 
-/* Test hook: R(u) = dU/dt of the semi-discretisation, host FP64 canonical
- * arrays in and out.  Leaves the current state untouched. */
+/* Test hook: R(u) = du/dt of the semi-discretisation, i.e. -div F of Eq. (1)
+ * of Section 2.1 with F = F_inv - F_vis of Eqs. (3)-(4), host FP64 canonical
+ * arrays in and out ([points][variables], caller-owned).  Leaves the current
+ * state untouched. */
 fr_status fr_residual(fr_mesh *m, const double *u, double *r);
 
 /* Device pointer and layout of the state, for callers that keep data on

@@ -7,11 +7,12 @@ density, momentum vector and total energy; FP64 residual and state 1e-12; FP32 f
 
   * Taylor-Green 24^3 hexes, p = 3 (4.4 M DOF): FP64 residual; 200 RK4 steps of the
     FP32 form and the FP64 path against the oracle, and the kinetic-energy decay
-    E_k(t) = <rho |v|^2 / 2> sampled every 20 steps.
-  * NACA O-grid 160x48x8 quadratic hexes, p = 3 (19.7 M DOF): FP64 residual; 3 steps
-    of both forms from a perturbed state, with the wall force of every step.
+    E_k(t) = <rho |v|^2 / 2> over every 20-step interval (FP64 1e-10, FP32 1e-3).
+  * NACA O-grid 160x48x8 quadratic hexes, p = 3 (19.7 M DOF): FP64 residual; 100
+    steps of both forms from a perturbed state, with the wall force means.
   * Sixteen uneven O-grids in one batch (917,407 hexes): the smallest design and one
-    drawn at random, bit for bit against solo runs; the smallest against the oracle.
+    drawn at random, bit for bit against solo runs and against the oracle after 100
+    steps.
   * Edge cases: a single periodic element that is its own neighbour on every face
     (2D and 3D), zero steps, a ragged last block.
 """
@@ -91,12 +92,11 @@ def test_tgv_full_200_steps_and_kinetic_energy(tgv):
         ref.append(o.rk4(ref[-1], dt, chunk))
         ek_ref.append(kinetic_energy(ref[-1], 3))
     ek_ref = np.array(ek_ref)
-    # E_k is a weighted mean of a quadratic in the state, so a state error below tol
-    # bounds its error by about 2 tol E_k; the decay between samples is a difference
-    # of two such values
-    dek = np.abs(np.diff(ek_ref)).min()
-    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
-        ek_tol = 2.0 * 2.0 * tol * ek_ref[0] / dek
+    # decay of E_k over each 20-step interval against the oracle's, relative to the
+    # oracle's: FP64 1e-10, FP32 1e-3.  The state bars do not imply these: a state
+    # within 1e-5 bounds E_k within about 2e-5 E_k, i.e. the decay of an interval
+    # (about 8e-5 E_k) only to within half of itself
+    for prec, tol, dtol in (("fp64", 1e-12, 1e-10), ("fp32", 1e-5, 1e-3)):
         g = tuned(m, prec, u0)
         g.set_state(u0)
         ek = [kinetic_energy(u0, 3)]
@@ -108,15 +108,13 @@ def test_tgv_full_200_steps_and_kinetic_energy(tgv):
                 err100 = rel_err(u, ref[5])
         ek = np.array(ek)
         err = rel_err(u, ref[-1])
-        # decay between samples, relative to the oracle's
-        rate_err = np.abs(np.diff(ek) - np.diff(ek_ref)).max() / np.abs(np.diff(ek_ref)).max()
+        decay_err = np.abs(np.diff(ek) - np.diff(ek_ref)) / np.abs(np.diff(ek_ref))
         print(f"tgv 24^3 {prec}: rel L2 after 100 steps {err100:.3e}, after 200 {err:.3e}; "
-              f"E_k {ek[0]:.9f} -> {ek[-1]:.9f} (oracle {ek_ref[-1]:.9f}), decay rel err {rate_err:.2e} "
-              f"(bound {ek_tol:.1e})",
-              flush=True)
+              f"E_k {ek[0]:.9f} -> {ek[-1]:.9f} (oracle {ek_ref[-1]:.9f}), decay rel err per "
+              f"{chunk} steps max {decay_err.max():.2e} (bar {dtol:.0e})", flush=True)
         assert err100 <= tol and err <= tol
         assert np.abs(ek - ek_ref).max() <= 2.0 * tol * ek_ref[0]
-        assert rate_err <= ek_tol
+        assert decay_err.max() <= dtol
         g.close()
 
 
@@ -135,10 +133,11 @@ def test_airfoil_full_fp64_residual(airfoil):
     assert err <= 1e-12
 
 
-@pytest.mark.timeout(300)
-def test_airfoil_full_steps_and_forces(airfoil):
+@pytest.mark.timeout(600)
+def test_airfoil_full_100_steps_and_forces(airfoil):
     m, o, u = airfoil
-    n = 3
+    n = 100
+    print(f"airfoil 160x48x8: oracle, {n} steps", flush=True)
     ref, hist = o.rk4(u, m["dt"], n, forces=True)
     qref = 0.5 * m["ref_area"]
     scale = np.abs(hist).max()
@@ -149,37 +148,39 @@ def test_airfoil_full_steps_and_forces(airfoil):
         err = rel_err(g.get_state(), ref)
         f = g.forces()
         ferr = np.abs(f[2:5] - hist[-1]).max() / scale
-        mean_err = abs(f[5] - hist.mean(axis=0) @ m["lift_dir"] / qref) / (scale / qref)
+        mean_err = max(abs(f[5] - hist.mean(axis=0) @ m["lift_dir"] / qref),
+                       abs(f[6] - hist.mean(axis=0) @ m["drag_dir"] / qref)) / (scale / qref)
         print(f"airfoil 160x48x8 {prec} {n} steps: rel L2 {err:.3e}, force rel err {ferr:.2e}, "
-              f"mean C_L err {mean_err:.2e}", flush=True)
+              f"mean C_L/C_D err {mean_err:.2e}", flush=True)
         assert err <= tol
         assert f[7] == n and ferr <= ftol and mean_err <= ftol
         g.close()
 
 
-@pytest.mark.timeout(400)
+@pytest.mark.timeout(900)
 def test_full_batch_members_match_solo_and_oracle():
     meshes = W.config_batch(0)
     sizes = [len(m["elem_nodes"]) for m in meshes]
     small = int(np.argmin(sizes))
     other = int(np.random.default_rng(7).choice([i for i in range(len(meshes)) if i != small]))
-    states = []
-    o_small = OracleMesh(meshes[small])
+    states, oracles = [], {}
     for i, m in enumerate(meshes):
-        if i == small:
-            states.append(perturbed(o_small, m, amp=0.05, seed=i))
+        if i in (small, other):
+            oracles[i] = OracleMesh(m)
+            states.append(perturbed(oracles[i], m, amp=0.05, seed=i))
         else:
             fs = m["freestream"]
             states.append(W.uniform_state(sizes[i] * 64, fs[0], fs[1:4], fs[4]).reshape(sizes[i], 64, 5))
     u0 = np.concatenate(states)
+    print(f"batch: {len(meshes)} designs, {sum(sizes)} elements; building", flush=True)
     b = FRMesh(meshes, "fp32")
     b.set_state(u0)
     mask = b.autotune(2)
     b.set_state(u0)
-    n = 2
+    n = 100
     b.step(n)
     ub = b.get_state()
-    print(f"batch of {len(meshes)} designs, {b.E} elements, mask {mask}", flush=True)
+    print(f"batch of {len(meshes)} designs, {b.E} elements, mask {mask}: {n} steps done", flush=True)
     for i in (small, other):
         g = FRMesh(meshes[i], "fp32")
         g.select_kernels(mask)
@@ -189,11 +190,14 @@ def test_full_batch_members_match_solo_and_oracle():
         assert np.array_equal(ub[e0:e0 + ne], g.get_state()), i
         assert np.array_equal(b.forces(i), g.forces()), i
         g.close()
-    e0, ne = b.design_range(small)
-    ref = o_small.rk4(states[small], meshes[small]["dt"], n)
-    err = rel_err(ub[e0:e0 + ne], ref)
-    print(f"smallest design ({sizes[small]} elements) fp32 batched vs oracle, {n} steps: {err:.3e}", flush=True)
-    assert err <= 1e-5
+        print(f"design {i}: batched bit-identical to solo", flush=True)
+    for i in (small, other):
+        e0, ne = b.design_range(i)
+        print(f"design {i} ({sizes[i]} elements): oracle, {n} steps", flush=True)
+        ref = oracles[i].rk4(states[i], meshes[i]["dt"], n)
+        err = rel_err(ub[e0:e0 + ne], ref)
+        print(f"design {i} ({sizes[i]} elements) fp32 batched vs oracle, {n} steps: {err:.3e}", flush=True)
+        assert err <= 1e-5
     b.close()
 
 

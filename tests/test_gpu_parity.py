@@ -69,11 +69,14 @@ def case(name):
         return W.config_airfoil(1, ni=24, nj=5, nk=2)
     if name == "airfoil_p2":
         return W.config_airfoil(2, ni=16, nj=4, nk=3, order=2)
+    if name == "airfoil_p4":
+        # the served workload's highest order on a curved O-grid: wall and far field
+        return W.config_airfoil(6, ni=16, nj=4, nk=2, order=4)
     raise KeyError(name)
 
 
 CASES = ["vortex2d_p3", "vortex2d_p1", "vortex2d_p4", "box2d_curved_p2", "tgv_p1", "tgv_p2", "tgv_p3", "tgv_p4", "tgv_p3_one", "tgv_p2_two",
-         "airfoil_p3", "airfoil_p2"]
+         "airfoil_p3", "airfoil_p2", "airfoil_p4"]
 # kernel structures / operator back-ends: five launches per stage with dense
 # element-batched MFMA contractions or sum factorisation, or the fused
 # two-launch stage (sum factorised)
@@ -185,6 +188,32 @@ def test_airfoil_state_and_forces(variant):
     assert abs(f[5] - mean @ m["lift_dir"] / qref) <= 1e-10 * scale
     assert abs(f[6] - mean @ m["drag_dir"] / qref) <= 1e-10 * scale
     assert np.allclose(f[2:5], hist[-1], rtol=0, atol=1e-10 * np.abs(hist).max())
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_airfoil_p4_state_after_100_steps(variant):
+    """Uniform p = 4 on a curved O-grid with wall and far-field faces: both forms after
+    100 RK4 steps from a perturbed state, and the wall force means (FP64)."""
+    m = case("airfoil_p4")
+    o = OracleMesh(m)
+    u0 = perturbed(o, m, amp=0.05)
+    n = 100
+    ref, hist = o.rk4(u0, m["dt"], n, forces=True)
+    qref = 0.5 * m["ref_area"]
+    scale = np.abs(hist).max() / qref
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        g = FRMesh(m, prec)
+        g.select_kernels(VARIANTS[variant])
+        g.set_state(u0)
+        g.step(n)
+        err = rel_err(g.get_state(), ref)
+        f = g.forces()
+        mean_err = max(abs(f[5] - hist.mean(axis=0) @ m["lift_dir"] / qref),
+                       abs(f[6] - hist.mean(axis=0) @ m["drag_dir"] / qref)) / scale
+        print(f"airfoil p4 {variant} {prec} {n} steps: rel L2 {err:.3e}, mean C_L/C_D err {mean_err:.2e}")
+        assert err <= tol and f[7] == n
+        assert mean_err <= (1e-10 if prec == "fp64" else 1e-5)
+        g.close()
 
 
 def test_set_get_roundtrip_and_resume_bit_identical():
