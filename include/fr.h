@@ -379,6 +379,24 @@ fr_status fr_fwh_pressure(fr_fwh *h, const double *observer, int64_t capacity, d
 fr_status fr_fwh_pressure_at(fr_fwh *h, const double *observer, double t_start, int64_t n, double *p,
                              double *p_thickness, double *p_loading);
 
+/* Allocation-free variant of fr_fwh_pressure_at, for callers that cannot
+ * allocate device memory while they run: work under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Same arguments, kernels and
+ * results (bit for bit) as fr_fwh_pressure_at; the evaluation's intermediate
+ * arrays (per-panel combined filters and first samples, partial sums, outputs)
+ * live in one static device array of 64 MiB instead of buffers the record
+ * grows, and the call allocates nothing.  The library holds that array on every
+ * GPU it runs on until the process ends.  Limit: n_points panels at n observer
+ * times need, in bytes, each term rounded up to 256,
+ *   8576 n_points + 16 n_points + 16 n ceil(n_points / 8) + 1024 n + 24 n
+ * (e.g. 3,000 panels at 4,000 observer times); a larger request returns
+ * FR_E_ARG before anything runs.  Every call on one GPU uses the same array and
+ * leaves its contents behind (each evaluation writes every element it reads
+ * first): calls that overlap on one GPU, from different threads or streams,
+ * race, and the caller must serialise them. */
+fr_status fr_fwh_pressure_at_noalloc(fr_fwh *h, const double *observer, double t_start, int64_t n, double *p,
+                                     double *p_thickness, double *p_loading);
+
 /* Device time (ms) of the last fr_fwh_pressure or fr_fwh_pressure_at (HIP
  * events on its stream around the per-panel filter, summation and reduction
  * kernels). */

@@ -109,6 +109,8 @@ SIGNATURES = {
     "fr_fwh_window": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _i64p]),
     "fr_fwh_pressure": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int64, _dp, _i64p, _dp, _dp, _dp]),
     "fr_fwh_pressure_at": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp]),
+    "fr_fwh_pressure_at_noalloc": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.c_int64, _dp, _dp,
+                                                  _dp]),
     "fr_fwh_time_ms": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "fr_last_error": (ctypes.c_char_p, []),
 }

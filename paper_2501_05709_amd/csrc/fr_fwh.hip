@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -551,11 +552,11 @@ struct fr_fwh {
       g.shift[i] = shift[i];
       g.xo[i] = xo[i];
     }
-    const int blocks = 64;
+    constexpr int blocks = 64;
     hipLaunchKernelGGL(k_fwh_delay, dim3(blocks), dim3(256), 0, stream, geo, np, ncopy, g, s, mm);
     hip_check(hipGetLastError(), "delay kernel");
-    std::vector<double> h(2 * blocks);
-    hip_check(hipMemcpyAsync(h.data(), mm, h.size() * sizeof(double), hipMemcpyDeviceToHost, stream), "delay copy");
+    double h[2 * blocks];
+    hip_check(hipMemcpyAsync(h, mm, sizeof(h), hipMemcpyDeviceToHost, stream), "delay copy");
     hip_check(hipStreamSynchronize(stream), "delay sync");
     double dmin = INFINITY, dmax = -INFINITY;
     for (int b = 0; b < blocks; ++b) {
@@ -683,17 +684,26 @@ fr_status fr_fwh_window(fr_fwh *h, const double *observer, double *t_start, int6
 
 }  // extern "C"
 
+// Allocation-free evaluation (fr_fwh_pressure_at_noalloc): the evaluation's
+// intermediate arrays live in one static device array per GPU instead of buffers the
+// record grows.  In host code `scratch` names a host-side stand-in; its device address
+// on the current GPU comes from hipGetSymbolAddress and is the only way host code
+// refers to it.
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
 namespace {
-// p' on the grid w (inside the common window) into host p, p_thickness, p_loading
-void fwh_compute(fr_fwh *h, const double *observer, const Window &w, double *p, double *p_thickness,
-                 double *p_loading) {
+// device buffers of one pressure evaluation
+struct Scratch {
+  double *part, *part2, *out, *filt;
+  int64_t *meta;
+};
+
+// p' on the grid w (inside the common window) into host p, p_thickness, p_loading, with
+// the evaluation's intermediate arrays in sc
+void fwh_launch(fr_fwh *h, const double *observer, const Window &w, const Scratch &sc, double *p,
+                double *p_thickness, double *p_loading) {
   const int64_t nchunk = (h->np + SUM_PANELS - 1) / SUM_PANELS;
-  if (nchunk > 65535) fail(FR_E_UNSUPPORTED, "too many panels for one launch");  // also bounds the filter grid
-  h->grow(h->part, h->part_bytes, size_t(nchunk) * 2 * w.n_out * sizeof(double));
-  h->grow(h->part2, h->part2_bytes, size_t(RED_GROUPS) * 2 * w.n_out * sizeof(double));
-  h->grow(h->out, h->out_bytes, size_t(3) * w.n_out * sizeof(double));
-  h->grow(h->filt, h->filt_bytes, size_t(h->np) * NQ * HROW * sizeof(double));
-  h->grow(h->meta, h->meta_bytes, size_t(h->np) * 2 * sizeof(int64_t));
   Geo3 g;
   for (int i = 0; i < 3; ++i) {
     g.shift[i] = h->shift[i];
@@ -703,28 +713,83 @@ void fwh_compute(fr_fwh *h, const double *observer, const Window &w, double *p, 
   const dim3 grid(unsigned((w.n_out + per_block - 1) / per_block), unsigned(nchunk));
   hip_check(hipEventRecord(h->ev0, h->stream), "event");
   hipLaunchKernelGGL(k_fwh_filter, dim3(unsigned(h->np)), dim3(SUM_WG), 0, h->stream, h->geo, h->np, h->ncopy, g, h->s,
-                     w, h->filt, reinterpret_cast<int64_t *>(h->meta));
+                     w, sc.filt, sc.meta);
   hip_check(hipGetLastError(), "filter kernel");
   hipLaunchKernelGGL(k_fwh_sum, grid, dim3(SUM_WG), 0, h->stream, h->src, h->geo, h->np, h->cap, h->ncopy, g, h->s, w,
-                     h->filt, reinterpret_cast<const int64_t *>(h->meta), h->part);
+                     sc.filt, static_cast<const int64_t *>(sc.meta), sc.part);
   hip_check(hipGetLastError(), "sum kernel");
   hipLaunchKernelGGL(k_fwh_reduce_groups, dim3(unsigned((w.n_out + 255) / 256), RED_GROUPS), dim3(256), 0, h->stream,
-                     h->part, nchunk, w.n_out, h->part2);
+                     sc.part, nchunk, w.n_out, sc.part2);
   hip_check(hipGetLastError(), "reduce kernel");
-  hipLaunchKernelGGL(k_fwh_reduce, dim3(unsigned((w.n_out + 255) / 256)), dim3(256), 0, h->stream, h->part2,
-                     int64_t(RED_GROUPS), w.n_out, h->out);
+  hipLaunchKernelGGL(k_fwh_reduce, dim3(unsigned((w.n_out + 255) / 256)), dim3(256), 0, h->stream, sc.part2,
+                     int64_t(RED_GROUPS), w.n_out, sc.out);
   hip_check(hipGetLastError(), "reduce kernel");
   hip_check(hipEventRecord(h->ev1, h->stream), "event");
   const size_t nb = size_t(w.n_out) * sizeof(double);
-  hip_check(hipMemcpyAsync(p, h->out, nb, hipMemcpyDeviceToHost, h->stream), "copy p");
+  hip_check(hipMemcpyAsync(p, sc.out, nb, hipMemcpyDeviceToHost, h->stream), "copy p");
   if (p_thickness)
-    hip_check(hipMemcpyAsync(p_thickness, h->out + w.n_out, nb, hipMemcpyDeviceToHost, h->stream), "copy pT");
+    hip_check(hipMemcpyAsync(p_thickness, sc.out + w.n_out, nb, hipMemcpyDeviceToHost, h->stream), "copy pT");
   if (p_loading)
-    hip_check(hipMemcpyAsync(p_loading, h->out + 2 * w.n_out, nb, hipMemcpyDeviceToHost, h->stream), "copy pL");
+    hip_check(hipMemcpyAsync(p_loading, sc.out + 2 * w.n_out, nb, hipMemcpyDeviceToHost, h->stream), "copy pL");
   hip_check(hipStreamSynchronize(h->stream), "pressure sync");
   float ms = 0.f;
   hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1), "elapsed");
   h->last_ms = ms;
+}
+
+void check_chunks(int64_t np) {
+  if ((np + SUM_PANELS - 1) / SUM_PANELS > 65535)
+    fail(FR_E_UNSUPPORTED, "too many panels for one launch");  // also bounds the filter grid
+}
+
+// the record's own buffers, grown on demand
+void fwh_compute(fr_fwh *h, const double *observer, const Window &w, double *p, double *p_thickness,
+                 double *p_loading) {
+  check_chunks(h->np);
+  const int64_t nchunk = (h->np + SUM_PANELS - 1) / SUM_PANELS;
+  Scratch sc;
+  sc.part = h->grow(h->part, h->part_bytes, size_t(nchunk) * 2 * w.n_out * sizeof(double));
+  sc.part2 = h->grow(h->part2, h->part2_bytes, size_t(RED_GROUPS) * 2 * w.n_out * sizeof(double));
+  sc.out = h->grow(h->out, h->out_bytes, size_t(3) * w.n_out * sizeof(double));
+  sc.filt = h->grow(h->filt, h->filt_bytes, size_t(h->np) * NQ * HROW * sizeof(double));
+  sc.meta = reinterpret_cast<int64_t *>(h->grow(h->meta, h->meta_bytes, size_t(h->np) * 2 * sizeof(int64_t)));
+  fwh_launch(h, observer, w, sc, p, p_thickness, p_loading);
+}
+
+// bytes of each intermediate array of an evaluation of np panels at n_out observer
+// times, each rounded up to 256; the total is what the static array must hold
+struct NoallocLayout {
+  size_t filt, meta, part, part2, out, total;
+};
+size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+NoallocLayout noalloc_layout(int64_t np, int64_t n_out) {
+  NoallocLayout L;
+  const size_t nchunk = size_t((np + SUM_PANELS - 1) / SUM_PANELS);
+  L.filt = up256(size_t(np) * NQ * HROW * sizeof(double));
+  L.meta = up256(size_t(np) * 2 * sizeof(int64_t));
+  L.part = up256(nchunk * 2 * size_t(n_out) * sizeof(double));
+  L.part2 = up256(size_t(RED_GROUPS) * 2 * size_t(n_out) * sizeof(double));
+  L.out = up256(size_t(3) * size_t(n_out) * sizeof(double));
+  L.total = L.filt + L.meta + L.part + L.part2 + L.out;
+  return L;
+}
+
+// device address of `scratch` on each GPU, looked up once per device with that device
+// current (each GPU holds its own copy of the array)
+constexpr int NOALLOC_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[NOALLOC_DEVICES] = {};
+
+unsigned char *scratch_on(int device) {
+  if (device < 0 || device >= NOALLOC_DEVICES) fail(FR_E_ARG, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "static scratch address");
+    if (!ptr) fail(FR_E_DEVICE, "static scratch has no device address");
+    g_scratch_ptr[device] = static_cast<unsigned char *>(ptr);
+  }
+  return g_scratch_ptr[device];
 }
 }  // namespace
 
@@ -755,6 +820,41 @@ fr_status fr_fwh_pressure_at(fr_fwh *h, const double *observer, double t_start, 
     w.t_start = t_start;
     w.n_out = n;
     fwh_compute(h, observer, w, p, p_thickness, p_loading);
+  });
+}
+
+fr_status fr_fwh_pressure_at_noalloc(fr_fwh *h, const double *observer, double t_start, int64_t n, double *p,
+                                     double *p_thickness, double *p_loading) {
+  return guarded([&] {
+    if (!h || !observer || !p || n <= 0) fail(FR_E_ARG, "bad argument");
+    check_chunks(h->np);
+    // sizes first: a request beyond the static array launches nothing
+    const NoallocLayout L = noalloc_layout(h->np, n);
+    if (L.total > NOALLOC_BYTES)
+      fail(FR_E_ARG, "panels x observer times need " + std::to_string(L.total) + " bytes of scratch, more than the " +
+                         std::to_string(NOALLOC_BYTES) + " of the allocation-free path");
+    hip_check(hipSetDevice(h->device), "hipSetDevice");
+    unsigned char *base = scratch_on(h->device);
+    Window w = h->window(observer);
+    const double tol = 1e-9 * w.dt;
+    if (t_start < w.t_start - tol || t_start + double(n - 1) * w.dt > w.t_end + tol)
+      fail(FR_E_ARG, "observer times outside the common window");
+    w.t_start = t_start;
+    w.n_out = n;
+    // every element of these arrays that a kernel reads is written earlier in the same
+    // evaluation, so the previous call's contents need no clearing
+    Scratch sc;
+    size_t off = 0;
+    sc.filt = reinterpret_cast<double *>(base + off);
+    off += L.filt;
+    sc.meta = reinterpret_cast<int64_t *>(base + off);
+    off += L.meta;
+    sc.part = reinterpret_cast<double *>(base + off);
+    off += L.part;
+    sc.part2 = reinterpret_cast<double *>(base + off);
+    off += L.part2;
+    sc.out = reinterpret_cast<double *>(base + off);
+    fwh_launch(h, observer, w, sc, p, p_thickness, p_loading);
   });
 }
 

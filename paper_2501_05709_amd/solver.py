@@ -429,6 +429,16 @@ class FWH:
                                              pl.ctypes.data_as(_lib._dp)), "fr_fwh_pressure_at")
         return (p, pt, pl) if parts else p
 
+    def pressure_at_noalloc(self, observer, t_start, n, parts=False):
+        """As pressure_at, through the entry point that allocates no device memory (its
+        intermediate arrays live in the library's static device scratch)."""
+        x = np.ascontiguousarray(observer, dtype=np.float64)
+        p, pt, pl = np.zeros(n), np.zeros(n), np.zeros(n)
+        check(_lib.load().fr_fwh_pressure_at_noalloc(self.h, x.ctypes.data_as(_lib._dp), float(t_start), int(n),
+                                                     p.ctypes.data_as(_lib._dp), pt.ctypes.data_as(_lib._dp),
+                                                     pl.ctypes.data_as(_lib._dp)), "fr_fwh_pressure_at_noalloc")
+        return (p, pt, pl) if parts else p
+
     def pressure(self, observer, parts=False):
         """(t, p') at the observer, plus (p'_T, p'_L) when parts is set."""
         x = np.ascontiguousarray(observer, dtype=np.float64)
