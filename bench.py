@@ -48,10 +48,20 @@ KERNEL_NAMES = {1: "k_face", 2: "k_grad", 3: "k_visc", 4: "k_divrk", 5: "k_inter
                 7: "k_stage_b"}
 
 
-def per_element_cost(dim, order, real_bytes):
+def metric_source(mask):
+    """Where the fused stage takes its FP64 metrics from, by variant mask: 'stored' (S,
+    1/|J|, normals and areas per point), 'extruded' (2D columns of z-extruded elements)
+    or 'node' (the 27 geometry nodes of each element)."""
+    if mask & (1 << 8):
+        return "extruded"
+    return "stored" if mask & (1 << 6) else "node"
+
+
+def per_element_cost(dim, order, real_bytes, metrics="stored"):
     """Dense-MFMA flops and implementation bytes of each kernel, per element and launch:
-    what each kernel of this library reads and writes (its own data layout, metrics
-    stored per point), not the method's minimum (``algorithmic_bytes_per_element_stage``).
+    what each kernel of this library reads and writes (its own data layout and metric
+    source, see ``metric_source``), not the method's minimum
+    (``algorithmic_bytes_per_element_stage``).
 
     Operator sizes are the unpadded FR matrices (n_u solution points, n_f flux
     points); metric terms are FP64 (8 bytes), neighbour indices 4 bytes.
@@ -61,6 +71,13 @@ def per_element_cost(dim, order, real_bytes):
     nf = 2 * dim * n ** (dim - 1)
     nv = dim + 2
     s = real_bytes
+    # metric bytes of the fused stage's first launch and its second (areas only when stored)
+    if dim == 3 and metrics == "extruded":
+        met_a, area_b = (4 * n * n + n + 2 * (4 * n + n * n)) * 8, 0
+    elif dim == 3 and metrics == "node":
+        met_a, area_b = 27 * 3 * 8, 0
+    else:
+        met_a, area_b = nf * dim * 8 + nu * (dim * dim + 1) * 8, nf * 8
     cost = {
         1: dict(flops=0, bytes=(2 * nf * nv * s + nf * dim * 8 + nf * 4) + 2 * nf * nv * s),
         2: dict(flops=2 * nv * (dim * nu * nu + dim * nu * nf),
@@ -71,14 +88,14 @@ def per_element_cost(dim, order, real_bytes):
                 bytes=nu * dim * nv * s + 3 * nf * nv * s + nf * 8 + nf * 4 + nu * 8 + 2 * nu * nv * s
                 + 2 * nu * nv * s),
         5: dict(flops=2 * nv * nf * nu, bytes=nu * nv * s + nf * nv * s),
-        # fused stage a: stage state, partner traces, normals, neighbour codes, S and 1/|J|
+        # fused stage a: stage state, partner traces, neighbour codes and the metric source
         # in; Q, P and the volume divergence out
-        6: dict(flops=0, bytes=nu * nv * s + nf * nv * s + nf * dim * 8 + nf * 4 + nu * (dim * dim + 1) * 8
-                + 2 * nf * nv * s + nu * nv * s),
-        # fused stage b: Q, partner P, codes, areas, divergence, 1/|J|, u_n and acc in; acc,
-        # next stage state and its trace out; the first stage reads no acc and the last
-        # writes none, so acc counts 3/4 each way (mean over the four RK stages)
-        7: dict(flops=0, bytes=2 * nf * nv * s + nf * 4 + nf * 8 + nu * nv * s + nu * 8
+        6: dict(flops=0, bytes=nu * nv * s + nf * nv * s + nf * 4 + met_a + 2 * nf * nv * s + nu * nv * s),
+        # fused stage b: Q, partner P, codes, areas (stored metrics only), divergence, 1/|J|,
+        # u_n and acc in; acc, next stage state and its trace out; the first stage reads no
+        # acc and the last writes none, so acc counts 3/4 each way (mean over the four RK
+        # stages)
+        7: dict(flops=0, bytes=2 * nf * nv * s + nf * 4 + area_b + nu * nv * s + nu * 8
                 + 1.75 * nu * nv * s + 1.75 * nu * nv * s + nf * nv * s),
     }
     return cost, nu * nv
@@ -182,6 +199,11 @@ def gpu_telemetry():
     return out
 
 
+def progress(msg):
+    """One line per finished phase on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def windows(mesh, steps, n_windows=5):
     """Time `steps` steps as n_windows consecutive windows (host clock around each
     synchronising fr_step); returns the per-window seconds and steps per window."""
@@ -216,7 +238,8 @@ def stage_roofline(mesh, dim, order, real_bytes, curved, workload, steps=5):
     t_a, t_b = ms[6] / nl[6] * 1e-3, ms[7] / nl[7] * 1e-3
     alg = algorithmic_bytes_per_element_stage(dim, order, real_bytes, curved) * mesh.E
     achieved = alg / (t_a + t_b) / 1e9
-    cost, _ = per_element_cost(dim, order, real_bytes)
+    metrics = metric_source(mesh.selected_kernels())
+    cost, _ = per_element_cost(dim, order, real_bytes, metrics)
     impl = (cost[6]["bytes"] + cost[7]["bytes"]) * mesh.E
     ta, tb = counters_traffic(workload, "k_stage_a"), counters_traffic(workload, "k_stage_b")
     traffic = ta + tb if ta is not None and tb is not None else None
@@ -229,7 +252,7 @@ def stage_roofline(mesh, dim, order, real_bytes, curved, workload, steps=5):
             "k_stage_b_us": round(t_b * 1e6, 2),
             "algorithmic_bytes_per_stage": int(alg),
             "algorithmic_bytes_per_dof_update": round(alg / dof_updates_per_stage, 1),
-            "implementation_bytes_per_stage": int(impl),
+            "implementation_bytes_per_stage": int(impl), "metric_source": metrics,
             "traffic_over_algorithmic": round(traffic / alg, 3) if traffic else None}
     return roof, ms, nl
 
@@ -296,6 +319,7 @@ def bench_batch(args):
     b64.set_state(u0)
     mask64 = b64.autotune(2)
     t_setup = time.perf_counter() - t_setup
+    progress(f"batch built and autotuned in {t_setup:.0f} s (fp32 mask {mask32}, fp64 mask {mask64})")
 
     # --- parity on sampled designs and the CPU baseline (the oracle on the smallest design)
     parity, cpu = {}, None
@@ -322,6 +346,7 @@ def bench_batch(args):
                 # the change from the initial state is the sharper measure
                 entry[f"{prec}_rel_l2_of_change_vs_oracle"] = rel_l2(x - ui, d_ref)
             parity[f"design_{i}"] = entry
+            progress(f"oracle on design {i} ({ne} elements, {n_sample} steps): {tc:.0f} s")
             if i == small:
                 cpu = {"value": ne * nu * nv * n_sample / tc, "unit": "DOF-updates/s", "cores": num_threads(),
                        "kind": "oracle", "host": host_cpu(),
@@ -341,6 +366,7 @@ def bench_batch(args):
         ts = windows(g, args.steps)
         rate, med = median_rate(dof, ts)
         total = sum(t for t, _ in ts)
+        progress(f"{prec}: {rate:.4g} DOF-updates/s")
         res[prec] = {"value": rate, "ms_per_step": med * 1e3, "window_ms_per_step": [round(t / k * 1e3, 4)
                                                                                   for t, k in ts],
                      "value_whole_window": dof * args.steps / total}
@@ -350,7 +376,7 @@ def bench_batch(args):
     # --- per-kernel events and the whole-stage roofline (FP32 form)
     b32.set_state(u0)
     roof, ms, nl = stage_roofline(b32, 3, 3, 4, True, "batch")
-    cost, _ = per_element_cost(3, 3, 4)
+    cost, _ = per_element_cost(3, 3, 4, metric_source(mask32))
     kernels = {}
     for k in range(1, 8):
         if not nl[k]:
@@ -368,6 +394,7 @@ def bench_batch(args):
         b32.step(args.solve_steps)
         [b32.forces(i) for i in range(len(meshes))]
         lat.append(time.perf_counter() - t0)
+    progress(f"{len(lat)} batched solves done")
     tel["after_solves"] = gpu_telemetry()
     lat = np.array(lat) if lat else None
     cl = [round(float(b32.forces(i)[5]), 6) for i in range(len(meshes))]
@@ -380,6 +407,7 @@ def bench_batch(args):
     if not args.no_extras:
         for name in ("tgv", "airfoil"):
             extras[name] = bench_single_quick(name, 50)
+            progress(f"extra workload {name} done")
 
     out = {
         "metric": "FR DOF-updates/s FP64 vs FP32 at stated L2 err; p50/p99 batched solve latency",
@@ -751,14 +779,13 @@ def bench_pmix(args):
     u3 = np.ascontiguousarray(m3["init"](g3.solution_points().reshape(-1, 3)).reshape(g3.shape))
     t3 = timed_run(g3, u3, args.steps, args.warmup)
     dof3 = g3.E * g3.nu * g3.nv
-    # step roofline: algorithmic bytes of both fused launches of every order group, four
-    # stages, over the measured step time (the mortar points' table entries and partner
-    # values, read inside those launches, are not counted)
+    # step roofline: the method's algorithmic bytes per curved element and stage at each
+    # element's order, four stages, over the measured step time (the mortar points' table
+    # entries and partner values are not counted)
     orders, counts = np.unique(m["orders"], return_counts=True)
     step_bytes = 0.0
     for p, c in zip(orders, counts):
-        cost, _ = per_element_cost(3, int(p), 4)
-        step_bytes += 4 * c * (cost[6]["bytes"] + cost[7]["bytes"])
+        step_bytes += 4 * c * algorithmic_bytes_per_element_stage(3, int(p), 4, True)
     achieved = step_bytes / (t32 / args.steps) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK["hbm"], "unit": "GB/s",
             "frac": round(achieved / PEAK["hbm"], 4), "kernel": "whole step (all order groups)", "traffic": None}
@@ -781,12 +808,55 @@ def bench_pmix(args):
     print(json.dumps(out))
 
 
+def bench_pmix_batch(args):
+    """Variable order in a batch: the sixteen designs of the default batch, each with the
+    paper's low-resolution P-distribution on its own O-grid (P3 in the inner quarter of
+    its radial layers, then P2, P1 and P0 outward), advanced together: every order group
+    covers that order's elements of all designs."""
+    from paper_2501_05709_amd import workloads as W
+    from paper_2501_05709_amd.solver import FRMesh
+    meshes = W.config_batch(0)
+    designs = []
+    for m in meshes:
+        ni, nj, nk = m["grid"]
+        q = max(1, nj // 4)
+        m = dict(m, orders=W.ring_orders(ni, nj, nk, ((q, 3), (2 * q, 2), (3 * q, 1), (nj, 0))))
+        designs.append(m)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        b = FRMesh(designs, prec)
+        u0 = np.concatenate([W.uniform_state(int(((np.asarray(m["orders"]) + 1) ** 3).sum()), m["freestream"][0],
+                                             m["freestream"][1:4], m["freestream"][4]) for m in designs])
+        dof = b.n_points * b.nv
+        b.set_state(u0)
+        if args.warmup:
+            b.step(args.warmup)
+        rate, med = median_rate(dof, windows(b, args.steps))
+        out[prec] = {"value": rate, "ms_per_step": med * 1e3, "dof": dof}
+        b.close()
+        del b
+        torch_empty()
+    res = {
+        "metric": "FR DOF-updates/s, variable-order batch of 16 airfoil designs (FP32 form; FP64 beside it)",
+        "value": round(out["fp32"]["value"], 1), "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(out["fp32"]["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "16 NACA 4-digit O-grids of the default batch, each with P3/P2/P1/P0 rings by "
+                               "quarters of its radial layers, seed 0", "dof": out["fp32"]["dof"],
+                   "elements": int(sum(len(m["elem_nodes"]) for m in designs))},
+        "fp64": {"value": round(out["fp64"]["value"], 1), "ms_per_step": round(out["fp64"]["ms_per_step"], 4)},
+        "speedup_fp32_over_fp64": round(out["fp32"]["value"] / out["fp64"]["value"], 3),
+    }
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="batch", choices=["batch", "tgv", "airfoil", "serve", "fwh", "pmix"])
+    ap.add_argument("--workload", default="batch",
+                    choices=["batch", "tgv", "airfoil", "serve", "fwh", "pmix", "pmix_batch"])
     ap.add_argument("--solves", type=int, default=5, help="batch: repeated batched solves for p50/p99 latency")
     ap.add_argument("--solve-steps", type=int, default=200, help="batch: RK4 steps of one batched solve")
     ap.add_argument("--no-extras", action="store_true", help="batch: skip the single-mesh workloads")
@@ -824,6 +894,8 @@ def main():
         return bench_fwh(args)
     if args.workload == "pmix":
         return bench_pmix(args)
+    if args.workload == "pmix_batch":
+        return bench_pmix_batch(args)
     return bench_single(args)
 
 
@@ -899,7 +971,7 @@ def bench_single(args):
     # --- per-kernel times (HIP events on the solver's stream) and roofline
     g32.set_state(u0)
     ms, nl = g32.profile_kernels(5)
-    cost, dof_per_elem = per_element_cost(g32.dim, g32.order, 4)
+    cost, dof_per_elem = per_element_cost(g32.dim, g32.order, 4, metric_source(mask32))
     kernels = {}
     fused = bool(mask32 & 1)
     for k in ((6, 7) if fused else range(1, 6)):

@@ -112,10 +112,13 @@ typedef struct {
  * conservative.  The state of such a mesh is ragged: [sum of n_u(e)][nv],
  * element e's solution points contiguous, in element order (fr_set_state,
  * fr_get_state, fr_residual, fr_solution_points).  Variable-order meshes run
- * the fused two-launch stage only; they are built one at a time (not in a
- * batch), and fr_neighbours, fr_state_device and fr_profile_kernels report
- * FR_E_UNSUPPORTED for them.  Probes and served requests with a data surface
- * work on them (each point is evaluated with its element's order). */
+ * the fused two-launch stage only, and fr_neighbours, fr_state_device and
+ * fr_profile_kernels report FR_E_UNSUPPORTED for them.  They batch like
+ * one-order meshes (fr_batch_create): designs with and without elem_order
+ * together, each order group of the batch covering the elements of that order
+ * of every design, the batch state the designs' ragged states concatenated.
+ * Probes and served requests with a data surface work on them (each point is
+ * evaluated with its element's order). */
 
 /* Build a solver for one mesh: connectivity (faces matched by node ids,
  * periodic faces by the listed translations, flux points by position),
@@ -129,9 +132,11 @@ fr_status fr_mesh_create(const fr_mesh_desc *desc, fr_mesh **out);
 /* Several meshes (candidate designs) advanced together by every kernel
  * launch: the layer of parallelism that runs the 2n poll designs of the
  * paper's Algorithm 1 concurrently.  All descriptors must share dim,
- * order, precision, gamma, prandtl, mu, device and stream; dt, free stream
+ * precision, gamma, prandtl, mu, device and stream, and, unless some
+ * descriptor sets elem_order (variable order, above), order; dt, free stream
  * and force normalisation are per design.  State arrays of the batch are
- * the designs' canonical arrays concatenated in descriptor order. */
+ * the designs' canonical arrays concatenated in descriptor order.  FR_E_ARG
+ * if the descriptors do not share those fields. */
 fr_status fr_batch_create(const fr_mesh_desc *descs, int32_t n_designs, fr_mesh **out);
 
 void fr_mesh_destroy(fr_mesh *m);
@@ -224,17 +229,31 @@ fr_status fr_profile_kernels(fr_mesh *m, int64_t steps, double *ms_per_kernel, i
  * launches per stage (face, gradient/flux, viscous trace, divergence/RK
  * update, interpolation); bit k (k = 2, 3, 4, 5 for those four operator
  * kernels) set selects sum factorisation (VALU, LDS-staged inputs), clear
- * the dense element-batched MFMA contraction.  Every choice gives the same
- * result to round-off.  The default is the last autotuned choice for this
- * (precision, dim, order) in the process, else the fused stage. */
+ * the dense element-batched MFMA contraction.  Bit 6 (3D, fused stage): read
+ * the stored FP64 metrics instead of forming S, |J|, the face normals and
+ * areas in FP64 from each element's 27 geometry nodes.  Bit 8 (meshes whose
+ * elements are all z-extruded, x and y the same in every node layer and z a
+ * function of zeta alone, as spanwise-extruded airfoil grids and boxes are):
+ * form them from per-element column metrics instead, the 2D Jacobian at the
+ * solution-point columns, z_zeta per layer and the face columns (FP64; the
+ * default on such meshes; FR_E_UNSUPPORTED on others).  Bit 7 set turns off
+ * the remap that sends the workgroups of consecutive element blocks to one
+ * XCD (and so into one L2).  Every choice gives the same result
+ * to round-off (bit 7 bit for bit).  The default is the last
+ * autotuned choice for this (precision, dim, order, size class) in the
+ * process, else the fused stage with metrics from the nodes (column metrics
+ * on an extruded mesh). */
 fr_status fr_select_kernels(fr_mesh *m, int32_t mask);
 fr_status fr_selected_kernels(const fr_mesh *m, int32_t *mask);
 
-/* Autotuner: times the fused stage and both variants of every split
- * operator kernel for `steps` steps on this mesh with HIP events (the state
- * is saved and restored), keeps the fastest configuration, records it for
- * later meshes of the same precision, dimension and order, and returns the
- * mask. */
+/* Autotuner: times the fused stage (in 3D with metrics from the nodes and
+ * with stored metrics, and with column metrics on an extruded mesh, each with
+ * and without the XCD remap of bit 7) and
+ * both variants of every split operator kernel for
+ * `steps` steps on this mesh with HIP events (the state is saved and
+ * restored), keeps the fastest configuration, records it for later meshes of
+ * the same precision, dimension, order and size class (the bit length of the
+ * count of 16-element blocks), and returns the mask. */
 fr_status fr_autotune(fr_mesh *m, int64_t steps, int32_t *mask_out);
 
 /* ---- served requests: continuous batching under an HBM budget ---------- */

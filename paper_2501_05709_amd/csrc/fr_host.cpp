@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -327,6 +328,54 @@ double metric_rows(int dim, double a[3][3], double S[3][3]) {
   return a[0][0] * S[0][0] + a[0][1] * S[0][1] + a[0][2] * S[0][2];
 }
 
+// A z-extruded element: x and y the same in every node layer and z a function of
+// zeta alone (equal across each layer), so J = [[x_xi, x_eta, 0], [y_xi, y_eta, 0],
+// [0, 0, z_zeta]] with the 2D part independent of zeta and z_zeta of zeta alone.
+bool elem_extruded(const fr_mesh_desc &d, int64_t e) {
+  if (d.dim != 3) return false;
+  const int na = d.geom_order + 1;
+  const int64_t *en = d.elem_nodes + e * na * na * na;
+  for (int a2 = 0; a2 < na; ++a2)
+    for (int a1 = 0; a1 < na; ++a1)
+      for (int a0 = 0; a0 < na; ++a0) {
+        const double *X = d.nodes + en[a0 + na * a1 + na * na * a2] * 3;
+        const double *X0 = d.nodes + en[a0 + na * a1] * 3;
+        const double *Z = d.nodes + en[na * na * a2] * 3;
+        if (X[0] != X0[0] || X[1] != X0[1] || X[2] != Z[2]) return false;
+      }
+  return true;
+}
+
+// Column metrics of an extruded element at the order's Gauss-Legendre points x[]: the 2D
+// Jacobian (x_xi, x_eta, y_xi, y_eta) at (x[i0], x[i1]), from the node layer a2 = 0, and
+// z_zeta at x[i2], from the nodes of column (0, 0)
+void extruded_jacobian(const fr_mesh_desc &d, int64_t e, double xi, double eta, double jac[4]) {
+  const int q = d.geom_order, na = q + 1;
+  const int64_t *en = d.elem_nodes + e * na * na * na;
+  double N0[3], dN0[3], N1[3], dN1[3];
+  shape_q(q, xi, N0, dN0);
+  shape_q(q, eta, N1, dN1);
+  for (int c = 0; c < 4; ++c) jac[c] = 0.0;
+  for (int a1 = 0; a1 < na; ++a1)
+    for (int a0 = 0; a0 < na; ++a0) {
+      const double *X = d.nodes + en[a0 + na * a1] * 3;
+      const double w0 = dN0[a0] * N1[a1], w1 = N0[a0] * dN1[a1];
+      jac[0] += w0 * X[0];
+      jac[1] += w1 * X[0];
+      jac[2] += w0 * X[1];
+      jac[3] += w1 * X[1];
+    }
+}
+double extruded_zzeta(const fr_mesh_desc &d, int64_t e, double zeta) {
+  const int q = d.geom_order, na = q + 1;
+  const int64_t *en = d.elem_nodes + e * na * na * na;
+  double N[3], dN[3];
+  shape_q(q, zeta, N, dN);
+  double z = 0.0;
+  for (int a2 = 0; a2 < na; ++a2) z += dN[a2] * d.nodes[en[na * na * a2] * 3 + 2];
+  return z;
+}
+
 struct KeyHash {
   size_t operator()(const std::array<int64_t, 4> &k) const {
     size_t h = 1469598103934665603ull;
@@ -566,14 +615,17 @@ struct fr_mesh {
   DevArrays a;
   LaunchCfg cfg;
   bool state_set = false;
-  hipGraphExec_t graph_first = nullptr, graph_rest = nullptr;
+  hipGraphExec_t graph_first = nullptr, graph_rest = nullptr, graph_multi = nullptr;
+  bool extruded = false;  // 3D, every element z-extruded: column metrics present
 
   // variable order: one uniform-order solver per order present (ascending order),
   // all on this handle's stream and sharing its mortar tables (DevArrays MO.., MT, PO..)
   std::vector<std::unique_ptr<fr_mesh>> groups;
   std::vector<int> eorder;              // [E] element order
   std::vector<int> egroup;              // [E] group of the element
-  std::vector<int64_t> elocal;          // [E] index of the element within its group
+  std::vector<int64_t> elocal;          // [E] canonical index of the element within its group
+  std::vector<int64_t> eslot;           // [E] block * EB + slot of the element in its group
+  std::vector<std::vector<int>> gdesign;  // [group][design]: the design's index in the group, or -1
   std::vector<int64_t> uoff;            // [E + 1] first solution point of the element
   int64_t n_mortar = 0;                 // mortar points
   std::vector<const void *> group_uf, group_pv;  // the groups' UF and PV arrays
@@ -603,6 +655,7 @@ struct fr_mesh {
   ~fr_mesh() {
     if (graph_first) hipGraphExecDestroy(graph_first);
     if (graph_rest) hipGraphExecDestroy(graph_rest);
+    if (graph_multi) hipGraphExecDestroy(graph_multi);
     groups.clear();  // they run on this handle's stream
     if (stream) hipStreamSynchronize(stream);
     for (void *p : allocations) {
@@ -631,11 +684,29 @@ void validate_desc(const fr_mesh_desc *d) {
 }
 
 // kernels (bit = enum Kernel) that run the sum-factorised variant unless tuned otherwise
-std::map<int, unsigned> g_tuned;  // key prec*100 + dim*10 + order
-unsigned default_variants(int prec, int dim, int order) {
-  auto it = g_tuned.find(prec * 100 + dim * 10 + order);
-  if (it != g_tuned.end()) return it->second;
-  return 1u | (1u << K_INTERP);  // fused stage, sum-factorised trace
+// keyed by (precision, dim, order, size class): the size class is the bit length of the
+// block count, so a choice timed on a small mesh is not carried over to a large batch
+std::map<int, unsigned> g_tuned;
+std::mutex g_tuned_mu;
+int tune_key(int prec, int dim, int order, int64_t nblk) {
+  int bits = 0;
+  while (nblk > 0) {
+    ++bits;
+    nblk >>= 1;
+  }
+  return ((prec * 10 + dim) * 10 + order) * 64 + bits;
+}
+unsigned default_variants(int prec, int dim, int order, int64_t nblk, bool extruded) {
+  std::lock_guard<std::mutex> lock(g_tuned_mu);
+  auto it = g_tuned.find(tune_key(prec, dim, order, nblk));
+  if (it != g_tuned.end()) {
+    // a choice timed on an extruded mesh: other meshes of its class take the stored metrics
+    if ((it->second & EXTRUDED_METRICS) && !extruded) return (it->second & ~EXTRUDED_METRICS) | STORED_METRICS;
+    return it->second;
+  }
+  // fused stage, sum-factorised trace; column metrics on an extruded mesh, else the stored
+  // ones (faster than forming them from the geometry nodes on every mesh timed)
+  return 1u | (1u << K_INTERP) | (extruded ? EXTRUDED_METRICS : dim == 3 ? STORED_METRICS : 0u);
 }
 
 constexpr unsigned FUSED = 1u;  // variant-mask bit 0: two fused launches per stage
@@ -645,7 +716,8 @@ void drop_graphs(fr_mesh *M);
 // Mortar points of one order group: for (element, face) of the group, the first
 // mortar point of the face and the side (1: the lower-order element)
 struct MortarMap {
-  std::unordered_map<int64_t, std::pair<int64_t, int>> face;  // key element * 2 dim + face
+  // key: the element's canonical index in the group (its designs concatenated) * 2 dim + face
+  std::unordered_map<int64_t, std::pair<int64_t, int>> face;
 };
 
 void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap *mm = nullptr) {
@@ -707,6 +779,37 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
   std::vector<double> SM(size_t(NB) * NUP * dim * dim * EB, 0.0), IJ(size_t(NB) * NUP * EB, 0.0);
   std::vector<double> FN(size_t(NB) * NFPAD * dim * EB, 0.0), FA(size_t(NB) * NFPAD * EB, 0.0);
   std::vector<int> NBt(size_t(NB) * NFPAD * EB, 0);
+  // 3D meshes of z-extruded elements: column metrics; empty slots hold the unit cube
+  bool extruded = dim == 3;
+  for (int di = 0; di < nd && extruded; ++di)
+    for (int64_t e = 0; e < descs[di].n_elems && extruded; ++e) extruded = elem_extruded(descs[di], e);
+  M->extruded = extruded;
+  const int ncol = D.n * D.n, nfc = 4 * D.n + D.n * D.n;
+  std::vector<double> XC(extruded ? size_t(NB) * ncol * 4 * EB : 0, 0.0), ZZ(extruded ? size_t(NB) * D.n * EB : 0, 1.0),
+      FCX(extruded ? size_t(NB) * nfc * 2 * EB : 0, 0.0);
+  if (extruded)
+    for (int64_t blk = 0; blk < NB; ++blk)
+      for (int sl = 0; sl < EB; ++sl) {
+        for (int c = 0; c < ncol; ++c) {
+          XC[lay(blk, c, 0, sl, ncol, 4)] = 1.0;
+          XC[lay(blk, c, 3, sl, ncol, 4)] = 1.0;
+          FCX[lay(blk, 4 * D.n + c, 0, sl, nfc, 2)] = 1.0;
+        }
+        for (int m = 0; m < D.n; ++m)
+          for (int sd = 0; sd < 2; ++sd) {
+            FCX[lay(blk, sd * D.n + m, 1, sl, nfc, 2)] = 1.0;      // xi faces: y_eta
+            FCX[lay(blk, 2 * D.n + sd * D.n + m, 0, sl, nfc, 2)] = 1.0;  // eta faces: x_xi
+          }
+      }
+  // 3D: triquadratic geometry nodes per element; empty slots hold the reference cube
+  constexpr int NX = 27;
+  std::vector<double> XN(dim == 3 ? size_t(NB) * NX * 3 * EB : 0, 0.0);
+  if (dim == 3)
+    for (int64_t blk = 0; blk < NB; ++blk)
+      for (int sl = 0; sl < EB; ++sl)
+        for (int a = 0; a < NX; ++a)
+          for (int c = 0; c < 3; ++c)
+            XN[lay(blk, a, c, sl, NX, 3)] = double((c == 0 ? a % 3 : c == 1 ? (a / 3) % 3 : a / 9) - 1);
   std::vector<int> bcount(NB), bdesign(NB);
   std::vector<int64_t> bcanon(NB), wall_first(nd + 1);
   std::vector<double> bdt(NB), fsd(size_t(nd) * 5);
@@ -721,6 +824,7 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
     return std::pair<int64_t, int>(di.blk0 + le / EB, int(le % EB));
   };
   if (int64_t(NB) * NFPAD * EB >= (int64_t(1) << 31)) fail(FR_E_UNSUPPORTED, "mesh too large for 32-bit tables");
+  const Basis1D basis_n(M->order);
   for (int di = 0; di < nd; ++di) {
     const auto &H = hm[di];
     const auto &ds = M->designs[di];
@@ -745,6 +849,35 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
       const int64_t g = ds.e0 + e;
       const int64_t blk = ds.blk0 + e / EB;
       const int s = int(e % EB);
+      if (dim == 3)
+        for (int a = 0; a < NX; ++a) {
+          const std::array<double, 3> r{double(a % 3 - 1), double((a / 3) % 3 - 1), double(a / 9 - 1)};
+          double x[3], jac[3][3];
+          geom_map(descs[di], e, r, x, jac);
+          for (int c = 0; c < 3; ++c) XN[lay(blk, a, c, s, NX, 3)] = x[c];
+        }
+      if (extruded) {
+        const Basis1D &gl = basis_n;
+        for (int i1 = 0; i1 < D.n; ++i1)
+          for (int i0 = 0; i0 < D.n; ++i0) {
+            double jc[4];
+            extruded_jacobian(descs[di], e, gl.x[size_t(i0)], gl.x[size_t(i1)], jc);
+            for (int c = 0; c < 4; ++c) XC[lay(blk, i0 + D.n * i1, c, s, ncol, 4)] = jc[c];
+            FCX[lay(blk, 4 * D.n + i0 + D.n * i1, 0, s, nfc, 2)] = jc[0] * jc[3] - jc[2] * jc[1];
+            FCX[lay(blk, 4 * D.n + i0 + D.n * i1, 1, s, nfc, 2)] = 0.0;
+          }
+        for (int i2 = 0; i2 < D.n; ++i2) ZZ[lay(blk, i2, 0, s, D.n, 1)] = extruded_zzeta(descs[di], e, gl.x[size_t(i2)]);
+        for (int sd = 0; sd < 2; ++sd)
+          for (int m = 0; m < D.n; ++m) {
+            double jc[4];
+            extruded_jacobian(descs[di], e, sd ? 1.0 : -1.0, gl.x[size_t(m)], jc);  // xi face: x_eta, y_eta
+            FCX[lay(blk, sd * D.n + m, 0, s, nfc, 2)] = jc[1];
+            FCX[lay(blk, sd * D.n + m, 1, s, nfc, 2)] = jc[3];
+            extruded_jacobian(descs[di], e, gl.x[size_t(m)], sd ? 1.0 : -1.0, jc);  // eta face: x_xi, y_xi
+            FCX[lay(blk, 2 * D.n + sd * D.n + m, 0, s, nfc, 2)] = jc[0];
+            FCX[lay(blk, 2 * D.n + sd * D.n + m, 1, s, nfc, 2)] = jc[2];
+          }
+      }
       for (int i = 0; i < nu; ++i) {
         for (int c = 0; c < dim * dim; ++c)
           SM[lay(blk, i, c, s, NUP, dim * dim)] = H.S[(size_t(e) * nu + i) * dim * dim + c];
@@ -764,7 +897,7 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
           code = int(lay(bs.first, qp, 0, bs.second, NFPAD, 1));
           M->nbr_canon[size_t(g) * nf + qq] = gp * nf + qp;
         } else if (-p == KIND_MORTAR) {
-          const auto &fs = mm->face.at(e * 2 * dim + qq / D.nfp);
+          const auto &fs = mm->face.at(g * 2 * dim + qq / D.nfp);
           const int64_t idx = ((fs.first + qq % D.nfp) << 1) | fs.second;
           code = -int(BC_MORTAR | (idx << 2));
           M->nbr_canon[size_t(g) * nf + qq] = p;
@@ -827,6 +960,25 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
   a.FN = M->upload(FN);
   a.FA = M->upload(FA);
   a.NB = M->upload(NBt);
+  if (extruded) {
+    a.XC = M->upload(XC);
+    a.ZZ = M->upload(ZZ);
+    a.FCX = M->upload(FCX);
+  }
+  if (dim == 3) {
+    a.XN = M->upload(XN);
+    Basis1D b(M->order);
+    std::vector<double> gq(size_t(6) * b.n);
+    for (int i = 0; i < b.n; ++i) {
+      double l[3], d[3];
+      shape_q(2, b.x[size_t(i)], l, d);
+      for (int k = 0; k < 3; ++k) {
+        gq[size_t(k * b.n + i)] = l[k];
+        gq[size_t((3 + k) * b.n + i)] = d[k];
+      }
+    }
+    a.GQ = M->upload(gq);
+  }
   a.bcount = M->upload(bcount);
   a.bdesign = M->upload(bdesign);
   a.bcanon = M->upload(bcanon);
@@ -868,7 +1020,7 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
   c.mu = M->mu;
   c.prandtl = M->prandtl;
   c.stream = M->stream;
-  c.variant_mask = default_variants(c.prec, dim, M->order);
+  c.variant_mask = default_variants(c.prec, dim, M->order, NB, M->extruded);
   hip_check(hipStreamSynchronize(M->stream), "mesh upload");
 }
 
@@ -892,9 +1044,9 @@ struct MortarFace {
   int64_t baseH = 0, baseL = 0;  // first mortar point of each side
 };
 
-void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
+void build_mixed(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
+  const fr_mesh_desc &d = descs[0];
   const int dim = d.dim, nfe = 2 * dim;
-  const int64_t E = d.n_elems;
   M->dim = dim;
   M->prec = d.precision;
   M->device = d.device;
@@ -904,7 +1056,6 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
   M->alloc = d.alloc;
   M->dfree = d.free;
   M->alloc_ctx = d.alloc_ctx;
-  M->E = E;
   hip_check(hipSetDevice(d.device), "hipSetDevice");
   if (d.stream) {
     M->stream = (hipStream_t)d.stream;
@@ -912,66 +1063,105 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
     hip_check(hipStreamCreateWithFlags(&M->stream, hipStreamNonBlocking), "hipStreamCreate");
     M->own_stream = true;
   }
-  // orders present
-  M->eorder.assign(d.elem_order, d.elem_order + E);
+  // element orders of all designs, concatenated (a design without elem_order has its
+  // `order` everywhere), and the orders present
+  std::vector<int64_t> de0(size_t(nd) + 1, 0);
+  for (int i = 0; i < nd; ++i) {
+    de0[size_t(i) + 1] = de0[size_t(i)] + descs[i].n_elems;
+    for (int64_t e = 0; e < descs[i].n_elems; ++e)
+      M->eorder.push_back(descs[i].elem_order ? descs[i].elem_order[e] : descs[i].order);
+  }
+  const int64_t E = de0[size_t(nd)];
+  M->E = E;
+  std::vector<int> edes(static_cast<size_t>(E));
+  for (int i = 0; i < nd; ++i)
+    for (int64_t e = de0[size_t(i)]; e < de0[size_t(i) + 1]; ++e) edes[size_t(e)] = i;
   std::vector<int> present;
   for (int p : M->eorder) {
     if (!kernels_available(d.precision, dim, p)) fail(FR_E_UNSUPPORTED, "element order not compiled in (0..4)");
     if (std::find(present.begin(), present.end(), p) == present.end()) present.push_back(p);
   }
   std::sort(present.begin(), present.end());
+  const size_t ng = present.size();
   M->order = present.back();
   M->dm = Dims(dim, M->order);
-  // faces and their orientation from the whole mesh at order 1 (2 or 2 x 2 face points
-  // at +-1/sqrt(3) along each face axis, matched by position)
-  fr_mesh_desc d1 = d;
-  d1.order = 1;
-  d1.elem_order = nullptr;
-  const HostMesh H1 = build_host_mesh(d1);
+  // groups: the designs with elements of each order, in design order; per element its
+  // group, its index within its design's part of the group and its canonical index in
+  // the group (the group's designs concatenated)
+  M->gdesign.assign(ng, std::vector<int>(size_t(nd), -1));
+  std::vector<std::vector<int64_t>> gcount(ng, std::vector<int64_t>(size_t(nd), 0));
+  M->egroup.resize(size_t(E));
+  M->elocal.resize(size_t(E));
+  M->eslot.resize(size_t(E));
+  M->uoff.assign(size_t(E) + 1, 0);
+  std::vector<int64_t> eli(static_cast<size_t>(E));  // index within the design's part of the group
+  for (int64_t e = 0; e < E; ++e) {
+    const int g = int(std::find(present.begin(), present.end(), M->eorder[size_t(e)]) - present.begin());
+    M->egroup[size_t(e)] = g;
+    eli[size_t(e)] = gcount[size_t(g)][size_t(edes[size_t(e)])]++;
+    const int n = M->eorder[size_t(e)] + 1;
+    M->uoff[size_t(e) + 1] = M->uoff[size_t(e)] + (dim == 2 ? n * n : n * n * n);
+  }
+  std::vector<std::vector<int64_t>> gde0(ng), gdblk0(ng);  // per group, per design in it
+  for (size_t g = 0; g < ng; ++g) {
+    int64_t c = 0, blk = 0;
+    for (int i = 0; i < nd; ++i) {
+      if (!gcount[g][size_t(i)]) continue;
+      M->gdesign[g][size_t(i)] = int(gde0[g].size());
+      gde0[g].push_back(c);
+      gdblk0[g].push_back(blk);
+      c += gcount[g][size_t(i)];
+      blk += (gcount[g][size_t(i)] + EB - 1) / EB;
+    }
+  }
+  for (int64_t e = 0; e < E; ++e) {
+    const size_t g = size_t(M->egroup[size_t(e)]);
+    const int gi = M->gdesign[g][size_t(edes[size_t(e)])];
+    M->elocal[size_t(e)] = gde0[g][size_t(gi)] + eli[size_t(e)];
+    M->eslot[size_t(e)] = (gdblk0[g][size_t(gi)] + eli[size_t(e)] / EB) * EB + eli[size_t(e)] % EB;
+  }
+  // faces and their orientation from each design at order 1 (2 or 2 x 2 face points at
+  // +-1/sqrt(3) along each face axis, matched by position); element indices global
   const int nfp1 = dim == 2 ? 2 : 4, nf1 = nfe * nfp1;
   const double x1 = 1.0 / std::sqrt(3.0);
   auto coords1 = [&](int m, double s[2]) {
     s[0] = (m & 1) ? x1 : -x1;
     s[1] = dim == 3 ? (((m >> 1) & 1) ? x1 : -x1) : 0.0;
   };
-  M->egroup.resize(size_t(E));
-  M->elocal.resize(size_t(E));
-  M->uoff.assign(size_t(E) + 1, 0);
-  std::vector<int64_t> gcount(present.size(), 0);
-  for (int64_t e = 0; e < E; ++e) {
-    const int g = int(std::find(present.begin(), present.end(), M->eorder[size_t(e)]) - present.begin());
-    M->egroup[size_t(e)] = g;
-    M->elocal[size_t(e)] = gcount[size_t(g)]++;
-    const int n = M->eorder[size_t(e)] + 1;
-    M->uoff[size_t(e) + 1] = M->uoff[size_t(e)] + (dim == 2 ? n * n : n * n * n);
-  }
   std::vector<MortarFace> faces;
-  for (int64_t e = 0; e < E; ++e)
-    for (int f = 0; f < nfe; ++f) {
-      const int64_t p = H1.nbr[size_t(e) * nf1 + f * nfp1];
-      if (p < 0) continue;
-      const int64_t ep = p / nf1;
-      const int fp = int((p % nf1) / nfp1);
-      const int oe = M->eorder[size_t(e)], op = M->eorder[size_t(ep)];
-      if (oe <= op) continue;  // each mortar face once, from its higher-order side
-      MortarFace mf;
-      mf.eH = e; mf.fH = f; mf.eL = ep; mf.fL = fp;
-      // O from the images of face points 1 and 2 (steps along each face axis) of point 0
-      double t[3][2];
-      for (int m = 0; m < (dim == 2 ? 2 : 3); ++m) {
-        const int64_t q = H1.nbr[size_t(e) * nf1 + f * nfp1 + m];
-        coords1(int(q % nf1) % nfp1, t[m]);
+  for (int i = 0; i < nd; ++i) {
+    fr_mesh_desc d1 = descs[i];
+    d1.order = 1;
+    d1.elem_order = nullptr;
+    const HostMesh H1 = build_host_mesh(d1);
+    const int64_t base = de0[size_t(i)];
+    for (int64_t le = 0; le < descs[i].n_elems; ++le)
+      for (int f = 0; f < nfe; ++f) {
+        const int64_t p = H1.nbr[size_t(le) * nf1 + f * nfp1];
+        if (p < 0) continue;
+        const int64_t e = base + le, ep = base + p / nf1;
+        const int fp = int((p % nf1) / nfp1);
+        const int oe = M->eorder[size_t(e)], op = M->eorder[size_t(ep)];
+        if (oe <= op) continue;  // each mortar face once, from its higher-order side
+        MortarFace mf;
+        mf.eH = e; mf.fH = f; mf.eL = ep; mf.fL = fp;
+        // O from the images of face points 1 and 2 (steps along each face axis) of point 0
+        double t[3][2];
+        for (int m = 0; m < (dim == 2 ? 2 : 3); ++m) {
+          const int64_t q = H1.nbr[size_t(le) * nf1 + f * nfp1 + m];
+          coords1(int(q % nf1) % nfp1, t[m]);
+        }
+        for (int r = 0; r < 2; ++r)
+          for (int c = 0; c < 2; ++c) mf.O[r][c] = 0;
+        for (int r = 0; r < (dim == 2 ? 1 : 2); ++r) {
+          mf.O[r][0] = int(std::lround((t[1][r] - t[0][r]) / (2.0 * x1)));
+          if (dim == 3) mf.O[r][1] = int(std::lround((t[2][r] - t[0][r]) / (2.0 * x1)));
+        }
+        faces.push_back(mf);
       }
-      for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 2; ++c) mf.O[r][c] = 0;
-      for (int r = 0; r < (dim == 2 ? 1 : 2); ++r) {
-        mf.O[r][0] = int(std::lround((t[1][r] - t[0][r]) / (2.0 * x1)));
-        if (dim == 3) mf.O[r][1] = int(std::lround((t[2][r] - t[0][r]) / (2.0 * x1)));
-      }
-      faces.push_back(mf);
-    }
+  }
   // mortar points: each face's higher-order points, then its lower-order points
-  std::vector<MortarMap> maps(present.size());
+  std::vector<MortarMap> maps(ng);
   int64_t np = 0;
   auto nfp_of = [&](int p) { return dim == 2 ? p + 1 : (p + 1) * (p + 1); };
   for (auto &mf : faces) {
@@ -984,45 +1174,74 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
   }
   M->n_mortar = np;
   if ((np << 3) >= (int64_t(1) << 31)) fail(FR_E_UNSUPPORTED, "too many mortar points for 32-bit codes");
-  // the order groups: sub-meshes whose faces to other orders are listed as mortar faces
-  for (size_t g = 0; g < present.size(); ++g) {
-    std::vector<int64_t> en, bf;
-    const int na = d.geom_order + 1, nn = dim == 2 ? na * na : na * na * na;
-    for (int64_t e = 0; e < E; ++e)
-      if (M->egroup[size_t(e)] == int(g)) en.insert(en.end(), d.elem_nodes + e * nn, d.elem_nodes + (e + 1) * nn);
-    for (int64_t i = 0; i < d.n_bfaces; ++i) {
-      const int64_t e = d.bfaces[3 * i];
-      if (e < 0 || e >= E) fail(FR_E_ARG, "invalid boundary face entry");
-      if (M->egroup[size_t(e)] != int(g)) continue;
-      bf.insert(bf.end(), {M->elocal[size_t(e)], d.bfaces[3 * i + 1], d.bfaces[3 * i + 2]});
+  // the order groups: per design present, the sub-mesh of its elements of that order,
+  // whose faces to other orders are listed as mortar faces
+  for (size_t g = 0; g < ng; ++g) {
+    std::vector<std::vector<int64_t>> en(static_cast<size_t>(nd)), bf(static_cast<size_t>(nd));
+    for (int i = 0; i < nd; ++i) {
+      if (M->gdesign[g][size_t(i)] < 0) continue;
+      const fr_mesh_desc &di = descs[i];
+      const int na = di.geom_order + 1, nn = dim == 2 ? na * na : na * na * na;
+      const int64_t base = de0[size_t(i)];
+      for (int64_t le = 0; le < di.n_elems; ++le)
+        if (M->egroup[size_t(base + le)] == int(g))
+          en[size_t(i)].insert(en[size_t(i)].end(), di.elem_nodes + le * nn, di.elem_nodes + (le + 1) * nn);
+      for (int64_t k = 0; k < di.n_bfaces; ++k) {
+        const int64_t le = di.bfaces[3 * k];
+        if (le < 0 || le >= di.n_elems) fail(FR_E_ARG, "invalid boundary face entry");
+        if (M->egroup[size_t(base + le)] != int(g)) continue;
+        bf[size_t(i)].insert(bf[size_t(i)].end(), {eli[size_t(base + le)], di.bfaces[3 * k + 1], di.bfaces[3 * k + 2]});
+      }
     }
-    for (const auto &kv : maps[g].face) bf.insert(bf.end(), {kv.first / nfe, kv.first % nfe, KIND_MORTAR});
-    fr_mesh_desc dg = d;
-    dg.order = present[g];
-    dg.elem_order = nullptr;
-    dg.n_elems = gcount[g];
-    dg.elem_nodes = en.data();
-    dg.n_bfaces = int64_t(bf.size() / 3);
-    dg.bfaces = bf.empty() ? nullptr : bf.data();
-    dg.stream = M->stream;
+    for (const auto &kv : maps[g].face) {
+      // group-canonical element -> its design and its index within the design's part
+      const int64_t ge = kv.first / nfe;
+      int gi = int(std::upper_bound(gde0[g].begin(), gde0[g].end(), ge) - gde0[g].begin()) - 1;
+      int i = 0;
+      while (M->gdesign[g][size_t(i)] != gi) ++i;
+      bf[size_t(i)].insert(bf[size_t(i)].end(), {ge - gde0[g][size_t(gi)], kv.first % nfe, KIND_MORTAR});
+    }
+    std::vector<fr_mesh_desc> dgs;
+    for (int i = 0; i < nd; ++i) {
+      if (M->gdesign[g][size_t(i)] < 0) continue;
+      fr_mesh_desc dg = descs[i];
+      dg.order = present[g];
+      dg.elem_order = nullptr;
+      dg.n_elems = gcount[g][size_t(i)];
+      dg.elem_nodes = en[size_t(i)].data();
+      dg.n_bfaces = int64_t(bf[size_t(i)].size() / 3);
+      dg.bfaces = bf[size_t(i)].empty() ? nullptr : bf[size_t(i)].data();
+      dg.stream = M->stream;
+      dgs.push_back(dg);
+    }
     std::unique_ptr<fr_mesh> G(new fr_mesh());
-    build_solver(G.get(), &dg, 1, &maps[g]);
-    G->cfg.variant_mask = FUSED | (1u << K_INTERP);
+    build_solver(G.get(), dgs.data(), int(dgs.size()), &maps[g]);
+    G->cfg.variant_mask = FUSED | (1u << K_INTERP) | (G->extruded ? EXTRUDED_METRICS : 0u);
     M->groups.push_back(std::move(G));
   }
   for (auto &G : M->groups) {
     M->nblk += G->nblk;
     M->nwall += G->nwall;
   }
-  M->designs.push_back(M->groups[0]->designs[0]);
-  M->designs[0].e0 = 0;
-  M->designs[0].E = E;
+  for (int i = 0; i < nd; ++i) {
+    DesignInfo di;
+    di.e0 = de0[size_t(i)];
+    di.E = descs[i].n_elems;
+    di.dt = descs[i].dt;
+    for (int k = 0; k < 5; ++k) di.fs[k] = descs[i].freestream[k];
+    di.ref_area = descs[i].ref_area;
+    for (int k = 0; k < 3; ++k) {
+      di.lift[k] = descs[i].lift_dir[k];
+      di.drag[k] = descs[i].drag_dir[k];
+    }
+    M->designs.push_back(di);
+  }
   // gather tables
   auto code_of = [&](int64_t e, int f, int m) {  // partner code of a face point in its group
     const fr_mesh &G = *M->groups[size_t(M->egroup[size_t(e)])];
-    const int64_t le = M->elocal[size_t(e)];
+    const int64_t sl = M->eslot[size_t(e)];
     const int q = f * G.dm.nfp + m;
-    return int(lay(le / EB, q, 0, int(le % EB), G.dm.nfpad, 1));
+    return int(lay(sl / EB, q, 0, int(sl % EB), G.dm.nfpad, 1));
   };
   std::vector<int> row_out, row_off{0}, ent_grp, ent_code;
   std::vector<double> ent_w;
@@ -1159,8 +1378,7 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc &d) {
     G->a.PW = M->a.PW;
   }
   M->a.flag = (int *)M->dalloc(sizeof(int));
-  M->cfg = M->groups[0]->cfg;
-  M->cfg.variant_mask = FUSED | (1u << K_INTERP);
+  M->cfg = M->groups[0]->cfg;  // reports the kernel structure of the (first) order group
   hip_check(hipStreamSynchronize(M->stream), "mesh upload");
 }
 
@@ -1170,7 +1388,8 @@ void profile_steps(fr_mesh *m, int64_t steps, double *ms, int64_t *launches);
 void drop_graphs(fr_mesh *M) {
   if (M->graph_first) hipGraphExecDestroy(M->graph_first);
   if (M->graph_rest) hipGraphExecDestroy(M->graph_rest);
-  M->graph_first = M->graph_rest = nullptr;
+  if (M->graph_multi) hipGraphExecDestroy(M->graph_multi);
+  M->graph_first = M->graph_rest = M->graph_multi = nullptr;
 }
 
 void lk(fr_mesh *M, int kernel, int stage, int mode, bool forces) {
@@ -1220,11 +1439,14 @@ void enqueue_step(fr_mesh *M, bool forces) {
   }
 }
 
-hipGraphExec_t capture_step(fr_mesh *M, bool forces) {
+// steps captured in one graph: the whole batch advances GRAPH_STEPS RK4 steps per launch
+constexpr int64_t GRAPH_STEPS = 8;
+
+hipGraphExec_t capture_step(fr_mesh *M, bool forces, int64_t steps = 1) {
   hipGraph_t g = nullptr;
   hip_check(hipStreamBeginCapture(M->stream, hipStreamCaptureModeThreadLocal), "begin capture");
   try {
-    enqueue_step(M, forces);
+    for (int64_t s = 0; s < steps; ++s) enqueue_step(M, forces);
   } catch (...) {
     hipStreamEndCapture(M->stream, &g);
     if (g) hipGraphDestroy(g);
@@ -1244,13 +1466,21 @@ void step_async(fr_mesh *M, int64_t n, bool clear_flag = true) {
   hip_check(hipSetDevice(M->device), "hipSetDevice");
   if (!M->graph_first) M->graph_first = capture_step(M, false);
   if (!M->graph_rest) M->graph_rest = capture_step(M, true);
+  if (!M->graph_multi && n > GRAPH_STEPS) M->graph_multi = capture_step(M, true, GRAPH_STEPS);
+  // the first step's input state is not averaged; then GRAPH_STEPS steps per launch
+  auto launch_steps = [&] {
+    hip_check(hipGraphLaunch(M->graph_first, M->stream), "graph launch");
+    int64_t left = n - 1;
+    for (; left >= GRAPH_STEPS && M->graph_multi; left -= GRAPH_STEPS)
+      hip_check(hipGraphLaunch(M->graph_multi, M->stream), "graph launch");
+    for (; left > 0; --left) hip_check(hipGraphLaunch(M->graph_rest, M->stream), "graph launch");
+  };
   if (M->mixed()) {
     for (auto &G : M->groups) {
       if (clear_flag) hip_check(launch_clear_flag(G->cfg, G->a), "clear flag");
       lk(G.get(), K_INTERP, 0, 0, false);
     }
-    for (int64_t s = 0; s < n; ++s)
-      hip_check(hipGraphLaunch(s == 0 ? M->graph_first : M->graph_rest, M->stream), "graph launch");
+    launch_steps();
     if (M->nwall > 0) {  // wall force of the final state
       for (auto &G : M->groups)
         if (G->nwall > 0) {
@@ -1262,8 +1492,7 @@ void step_async(fr_mesh *M, int64_t n, bool clear_flag = true) {
   }
   if (clear_flag) hip_check(launch_clear_flag(M->cfg, M->a), "clear flag");
   lk(M, K_INTERP, 0, 0, false);
-  for (int64_t s = 0; s < n; ++s)
-    hip_check(hipGraphLaunch(s == 0 ? M->graph_first : M->graph_rest, M->stream), "graph launch");
+  launch_steps();
   if (M->nwall > 0) {  // wall force of the final state
     if (M->cfg.variant_mask & FUSED) {
       lk(M, K_STAGE_A, 0, 0, true);
@@ -1304,17 +1533,25 @@ fr_status fr_batch_create(const fr_mesh_desc *descs, int32_t n, fr_mesh **out) {
     if (!out) fail(FR_E_ARG, "null output");
     *out = nullptr;
     if (!descs || n <= 0) fail(FR_E_ARG, "no descriptors");
-    for (int i = 0; i < n; ++i)
-      if (descs[i].elem_order) {
-        if (n != 1) fail(FR_E_UNSUPPORTED, "variable-order meshes are built one at a time");
-        fr_mesh_desc d = descs[0];
-        d.order = 1;  // each element's own order is checked when the groups are built
+    bool mixed = false;
+    for (int i = 0; i < n; ++i) mixed = mixed || descs[i].elem_order != nullptr;
+    if (mixed) {
+      // variable order: designs with and without per-element orders together; each order
+      // group covers every design that has elements of its order
+      for (int i = 0; i < n; ++i) {
+        fr_mesh_desc d = descs[i];
+        if (d.elem_order) d.order = 1;  // each element's own order is checked with the groups
         validate_desc(&d);
-        std::unique_ptr<fr_mesh> M(new fr_mesh());
-        build_mixed(M.get(), descs[0]);
-        *out = M.release();
-        return;
+        const auto &a = descs[0], &b = descs[i];
+        if (a.dim != b.dim || a.precision != b.precision || a.gamma != b.gamma || a.prandtl != b.prandtl ||
+            a.mu != b.mu || a.device != b.device || a.stream != b.stream)
+          fail(FR_E_ARG, "batched designs must share dim, precision, gas constants, device and stream");
       }
+      std::unique_ptr<fr_mesh> M(new fr_mesh());
+      build_mixed(M.get(), descs, n);
+      *out = M.release();
+      return;
+    }
     for (int i = 0; i < n; ++i) {
       validate_desc(&descs[i]);
       const auto &a = descs[0], &b = descs[i];
@@ -1483,11 +1720,13 @@ fr_status fr_forces(const fr_mesh *m, int32_t design, double *out) {
   return guarded([&] {
     if (!m || !out || design < 0 || design >= int(m->designs.size())) fail(FR_E_ARG, "bad argument");
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (m->mixed()) {  // the groups' wall sums add up; their step counts agree
-      for (auto &G : m->groups) {
-        if (G->nwall == 0) continue;
+    if (m->mixed()) {  // the design's wall sums in every group add up; their step counts agree
+      for (size_t g = 0; g < m->groups.size(); ++g) {
+        const fr_mesh &G = *m->groups[g];
+        const int gi = m->gdesign[g][size_t(design)];
+        if (gi < 0 || G.designs[size_t(gi)].nwall == 0) continue;
         double sg[8];
-        hip_check(hipMemcpyAsync(sg, G->a.fsum, sizeof(sg), hipMemcpyDeviceToHost, m->stream), "forces");
+        hip_check(hipMemcpyAsync(sg, G.a.fsum + 8 * gi, sizeof(sg), hipMemcpyDeviceToHost, m->stream), "forces");
         hip_check(hipStreamSynchronize(m->stream), "forces");
         for (int k : {0, 1, 2, 4, 5, 6}) s[k] += sg[k];
         s[3] = sg[3];
@@ -1577,7 +1816,10 @@ fr_status fr_select_kernels(fr_mesh *m, int32_t mask) {
       if (!(unsigned(mask) & FUSED)) fail(FR_E_UNSUPPORTED, "variable-order meshes run the fused stage only");
       return;
     }
-    m->cfg.variant_mask = unsigned(mask) & (FUSED | (1u << K_INTERP) | (1u << K_GRAD) | (1u << K_VISC) | (1u << K_DIVRK));
+    if ((unsigned(mask) & EXTRUDED_METRICS) && !m->extruded)
+      fail(FR_E_UNSUPPORTED, "column metrics need a mesh of z-extruded elements");
+    m->cfg.variant_mask = unsigned(mask) & (FUSED | (1u << K_INTERP) | (1u << K_GRAD) | (1u << K_VISC) |
+                                            (1u << K_DIVRK) | STORED_METRICS | NO_XCD_REMAP | EXTRUDED_METRICS);
     drop_graphs(m);
   });
 }
@@ -1610,18 +1852,36 @@ fr_status fr_autotune(fr_mesh *m, int64_t steps, int32_t *mask_out) {
     m->cfg.variant_mask = all;
     profile_steps(m, steps, ms_tensor, n);
     hip_check(hipMemcpyAsync(m->a.U, m->a.RES, nb, hipMemcpyDeviceToDevice, m->stream), "restore state");
-    m->cfg.variant_mask = FUSED | (1u << K_INTERP);
-    profile_steps(m, steps, ms_fused, n);
-    hip_check(hipMemcpyAsync(m->a.U, m->a.RES, nb, hipMemcpyDeviceToDevice, m->stream), "restore state");
+    // the fused stage: in 3D with metrics from the nodes or stored, each with the tiles
+    // of consecutive blocks remapped onto one XCD or not
+    double fused = 1e300;
+    unsigned fused_mask = FUSED | (1u << K_INTERP);
+    for (unsigned metrics : {0u, STORED_METRICS, EXTRUDED_METRICS}) {
+      if (metrics && m->dim != 3) continue;
+      if (metrics == EXTRUDED_METRICS && !m->extruded) continue;
+      for (unsigned shape : {0u, NO_XCD_REMAP}) {
+        m->cfg.variant_mask = FUSED | (1u << K_INTERP) | metrics | shape;
+        profile_steps(m, steps, ms_fused, n);
+        hip_check(hipMemcpyAsync(m->a.U, m->a.RES, nb, hipMemcpyDeviceToDevice, m->stream), "restore state");
+        const double t = ms_fused[K_STAGE_A] + ms_fused[K_STAGE_B];
+        if (t < fused) {
+          fused = t;
+          fused_mask = m->cfg.variant_mask;
+        }
+      }
+    }
     unsigned mask = 0;
     double split = ms_dense[K_FACE];
     for (int k : {int(K_INTERP), int(K_GRAD), int(K_VISC), int(K_DIVRK)}) {
       if (ms_tensor[k] < ms_dense[k]) mask |= 1u << k;
       split += std::min(ms_tensor[k], ms_dense[k]);
     }
-    if (ms_fused[K_STAGE_A] + ms_fused[K_STAGE_B] < split) mask = FUSED | (1u << K_INTERP);
+    if (fused < split) mask = fused_mask;
     m->cfg.variant_mask = mask;
-    g_tuned[m->prec * 100 + m->dim * 10 + m->order] = mask;
+    {
+      std::lock_guard<std::mutex> lock(g_tuned_mu);
+      g_tuned[tune_key(m->prec, m->dim, m->order, m->nblk)] = mask;
+    }
     drop_graphs(m);
     hip_check(hipStreamSynchronize(m->stream), "autotune");
     if (mask_out) *mask_out = int32_t(mask);
@@ -1687,6 +1947,13 @@ void profile_steps(fr_mesh *m, int64_t steps, double *ms, int64_t *launches) {
 }  // namespace
 
 void fr::set_last_error(const char *msg) { g_err = msg ? msg : ""; }
+
+bool fr::desc_extruded(const fr_mesh_desc &d) {
+  if (d.dim != 3) return false;
+  for (int64_t e = 0; e < d.n_elems; ++e)
+    if (!elem_extruded(d, e)) return false;
+  return true;
+}
 
 // ---------------------------------------------------------------------------
 // sampling the solution at points
@@ -1778,7 +2045,7 @@ fr_status fr_probe_create(fr_mesh *m, const fr_mesh_desc *desc, int32_t design, 
     *out = nullptr;
     if (!m || !desc || n <= 0 || !points || design < 0 || design >= int(m->designs.size()))
       fail(FR_E_ARG, "bad argument");
-    if (m->mixed() != (desc->elem_order != nullptr)) fail(FR_E_ARG, "descriptor does not match the mesh design");
+    if (!m->mixed() && desc->elem_order) fail(FR_E_ARG, "descriptor does not match the mesh design");
     if (m->mixed()) {
       fr_mesh_desc d1 = *desc;
       d1.order = 1;
@@ -1865,10 +2132,9 @@ fr_status fr_probe_create(fr_mesh *m, const fr_mesh_desc *desc, int32_t design, 
           std::vector<int64_t> slot, dst;
           std::vector<double> w;
           for (int64_t i = 0; i < n; ++i) {
-            const int64_t e = p->elem[size_t(i)];
+            const int64_t e = ds.e0 + p->elem[size_t(i)];
             if (m->egroup[size_t(e)] != int(g)) continue;
-            const int64_t le = m->elocal[size_t(e)];
-            slot.push_back((le / EB) * EB + le % EB);
+            slot.push_back(m->eslot[size_t(e)]);
             dst.push_back(i);
             for (int k = 0; k < dim; ++k) {
               const auto l = B.eval_all(p->xi[size_t(i) * 3 + k]);

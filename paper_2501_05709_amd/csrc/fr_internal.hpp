@@ -46,6 +46,14 @@ enum Kernel {
   K_STAGE_B = 7, // fused: flux correction, RK4 stage update, next trace
 };
 
+// Variant-mask bit of the fused stage on 3D one-order meshes: read the stored FP64
+// metrics instead of forming them from the geometry nodes
+constexpr unsigned STORED_METRICS = 1u << 6;
+// Launch shape of the fused stage: no remap of consecutive tiles onto one XCD
+constexpr unsigned NO_XCD_REMAP = 1u << 7;
+// Fused stage on a mesh of z-extruded elements: metrics from the column data (XC, ZZ, FCX)
+constexpr unsigned EXTRUDED_METRICS = 1u << 8;
+
 // Modes of K_DIVRK
 enum { MODE_RK0 = 0, MODE_RK1 = 1, MODE_RK2 = 2, MODE_RK3 = 3, MODE_RESID = 4 };
 
@@ -63,6 +71,18 @@ struct DevArrays {
   double *FN = nullptr;  // NFPAD points, dim channels: outward unit normal
   double *FA = nullptr;  // NFPAD points, 1 channel: |S^T n_hat|
   int *NB = nullptr;     // NFPAD points, 1 channel: partner lay(blk, q, 0, slot, NFPAD, 1), or boundary code
+  // 3D: the element map as 27 triquadratic nodes (lay: 27 points, 3 channels), from which
+  // the fused stage forms its metrics, and the quadratic basis and its derivative at the
+  // Gauss-Legendre points, GQ[(kind * 3 + a) * n + i] (kind 0: l_a, 1: l_a')
+  double *XN = nullptr;
+  double *GQ = nullptr;
+  // 3D meshes whose elements are all z-extruded: per element the 2D Jacobian columns
+  // (x_xi, x_eta, y_xi, y_eta) at the n^2 solution-point columns (lay: n^2 points, 4
+  // channels), z_zeta at the n solution-point layers (n points, 1 channel), and per face
+  // column (4n + n^2 points, 2 channels): (x_eta, y_eta) on the xi faces (side s, eta
+  // point m: s n + m), (x_xi, y_xi) on the eta faces (2n + s n + m), the 2D Jacobian
+  // determinant of the zeta faces' columns (4n + column)
+  double *XC = nullptr, *ZZ = nullptr, *FCX = nullptr;
   int *bcount = nullptr;   // [blk] valid elements in the block
   int *bdesign = nullptr;  // [blk]
   int64_t *bcanon = nullptr;  // [blk] canonical element index of slot 0
@@ -160,6 +180,10 @@ fr_status fwh_append_probe_async(::fr_fwh *h, ::fr_probe *p);
 // Upper bounds of the device bytes held by a probe of n points and by an FW-H record
 // of n_points panels and capacity samples, including what its pressure calls grow.
 size_t probe_footprint(int64_t n, int dim, int order);
+
+// Whether every element of a 3D mesh is z-extruded (x and y the same in every node layer,
+// z the same across each layer): such meshes also carry column metrics (DevArrays::XC..)
+bool desc_extruded(const fr_mesh_desc &d);
 size_t fwh_footprint(int64_t n_points, int64_t capacity);
 
 }  // namespace fr

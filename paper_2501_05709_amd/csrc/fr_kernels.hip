@@ -29,6 +29,7 @@
 #include <cstdint>
 
 #include "fr_internal.hpp"
+#include "fr_geom.hpp"
 
 namespace fr {
 
@@ -73,6 +74,8 @@ template <typename T> struct KArgs {
   T *U, *US, *ACC, *UF, *DU, *FI, *GU, *FT, *PV, *RES;
   const T *opInt, *opGrad, *opGcorr, *opDivS, *opCorr, *basis;
   const double *SM, *IJ, *FN, *FA, *bdt, *fsd, *wface;
+  const double *XN, *GQ;
+  const double *XC, *ZZ, *FCX;
   double *FC, *fsum, *stage64;
   const int *NB, *bcount, *bdesign;
   const int64_t *bcanon, *wall_first;
@@ -85,6 +88,7 @@ template <typename T> struct KArgs {
   const double *PW;
   int64_t nblk, n_canon;
   int ndesign;
+  int xcd;  // fused stage: map consecutive tiles to one XCD
   T gam, mu, kappa;
 };
 
@@ -970,6 +974,8 @@ __device__ inline int64_t xcd_remap(int64_t wg, int64_t nwg) {
   return wg < full ? (wg % 8) * (nwg / 8) + wg / 8 : wg;
 }
 
+enum { FV_NODE = 0, FV_STORED = 1, FV_MORTAR = 2, FV_EXTR = 3 };
+
 template <typename T, int DIM, int ORDER> struct FS {
   using S = Shape<DIM, ORDER>;
   static constexpr int ew(int bytes, int budget) {
@@ -992,15 +998,51 @@ template <typename T, int DIM, int ORDER> struct FS {
 
 // MORTAR: the mesh is one order group of a variable-order mesh, whose neighbour codes
 // may name mortar points (compiled out otherwise)
-template <typename T, int DIM, int ORDER, bool MORTAR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2, 8)))
-void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
+// Fused-stage variants (FV): FV_NODE, a 3D one-order mesh forms its metrics from the
+// geometry nodes (fr_geom.hpp) instead of reading them: S and 1/|J| at the solution
+// points, the unit normal and area factor at the flux points.  The area factor is folded
+// into the half fluxes the first launch writes (Q and P are stored as A Q and A P), so
+// the second launch reads no face metrics.  FV_STORED reads the stored metrics (2D
+// meshes, and the 3D alternative the autotuner times); FV_MORTAR is an order group of a
+// variable-order mesh with mortar points (stored metrics); FV_EXTR, a mesh of z-extruded
+// elements, forms S, 1/|J|, normals and area factors from its column metrics (the 2D
+// Jacobian at the n^2 solution-point columns, z_zeta at the n layers, the face columns)
+// with a few FP64 products, and scales the half fluxes as FV_NODE does.
+template <typename T, int DIM, int ORDER, int FV> struct NodeMetrics {
   using S = Shape<DIM, ORDER>;
   using F = FS<T, DIM, ORDER>;
+  static constexpr bool ON = DIM == 3 && FV == FV_NODE;
+  static constexpr int EW = F::EW_A;
+  using G = geom::Lay<S::N, EW>;
+  static constexpr int cmax(int x, int y) { return x > y ? x : y; }
+  // bytes: the stage's own LDS; with node metrics, pass A outputs from 0 (the state and
+  // jumps later reuse them) and the nodes, then pass B outputs, past both
+  static constexpr int STATE_B = (S::NU + S::NF) * S::NV * int(sizeof(T)) * EW;
+  static constexpr int OWN_B = F::LDS_A_ELEM * int(sizeof(T)) * EW;
+  static constexpr int VB_OFF = ON ? (cmax(G::NA * 8 * EW, STATE_B) + 15) / 16 * 16 : 0;
+  static constexpr int BYTES = ON ? cmax(OWN_B, VB_OFF + cmax(G::NB, G::NX) * 8 * EW) : OWN_B;
+};
+
+// register budget: 4 waves per SIMD in FP32 (3 with node metrics, whose FP64 metric
+// products need more registers), 2 in FP64
+template <typename T, int DIM, int ORDER, int FV>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (NodeMetrics<T, DIM, ORDER, FV>::ON ? 3 : 4) : 2, 8)))
+void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
+  constexpr bool MORTAR = FV == FV_MORTAR;
+  using S = Shape<DIM, ORDER>;
+  using F = FS<T, DIM, ORDER>;
+  using NM = NodeMetrics<T, DIM, ORDER, FV>;
+  constexpr bool NODEM = NM::ON;
+  constexpr bool EXTR = DIM == 3 && FV == FV_EXTR;
+  constexpr bool SCALED = NODEM || EXTR;  // Q and P stored times the area factor
+  constexpr int NCOL = S::N * S::N, NFC = 4 * S::N + S::N * S::N;
   constexpr int EW = F::EW_A, WG = F::WG_A, NS = EB / EW, N = S::N, NV = S::NV, NG = S::NG;
   constexpr int FI = (S::NF * EW + WG - 1) / WG, PI = (S::NU * EW + WG - 1) / WG;
-  // LDS: [state | jumps] while the gradient is formed, then [gradient | flux]
-  __shared__ T L[F::LDS_A_ELEM * EW];
+  // LDS: [state | jumps] while the gradient is formed, then [gradient | flux]; before
+  // both, with node metrics, the geometry passes
+  __shared__ __align__(16) unsigned char Lraw[NM::BYTES];
+  T *L = reinterpret_cast<T *>(Lraw);
   T *Us = L, *Ds = L + S::NU * NV * EW;
   T *Gs = L, *Fs = L + S::NU * NG * EW;
   __shared__ Basis<T, N> B;
@@ -1008,7 +1050,9 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   // passes (each lane reads back only what it wrote); held in registers they spill
   constexpr bool FQL = sizeof(T) == 4;
   __shared__ T Lq[FQL ? S::NF * NV * EW : 1];
-  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  // node metrics: the quadratic basis table
+  __shared__ double GQs[NODEM ? 6 * N : 1];
+  const int64_t wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : int64_t(blockIdx.x);
   const int64_t blk = wg / NS;
   const int e0 = int(wg % NS) * EW;
   const int nvalid = a.bcount[blk];
@@ -1024,6 +1068,19 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   constexpr int SI = (S::NU * NV * EW + WG - 1) / WG;
   BasisRegs<T, N, WG> bas;
   bas.issue(a.basis, tid);
+  // geometry nodes and the quadratic basis table first: the geometry passes run while the
+  // other prefetches are in flight
+  constexpr int XI = NODEM ? (geom::NODES * 3 * EW + WG - 1) / WG : 1;
+  double xr[XI], gqv = 0.0;
+  if constexpr (NODEM) {
+#pragma unroll
+    for (int r = 0; r < XI; ++r) {
+      const int t = min(tid + r * WG, geom::NODES * 3 * EW - 1);
+      const int eg = e0 + t % EW;
+      xr[r] = a.XN[(size_t(blk * NSB + eg / SB) * (geom::NODES * 3) + t / EW) * SB + eg % SB];
+    }
+    gqv = a.GQ[min(tid, 6 * N - 1)];
+  }
   int nbv[FI];
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
@@ -1038,12 +1095,26 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
     const int e = e0 + t % EW;
     ust[r] = Xb[(size_t(e / SB) * S::NUP * NV + t / EW) * SB + e % SB];
   }
-  double nrd[FI][DIM];
+  double nrd[FI][DIM], Av[FI];
+  double fcv[EXTR ? FI : 1][2], fzv[EXTR ? FI : 1];  // column metrics of the flux point's face
+  if constexpr (EXTR) {
 #pragma unroll
-  for (int it = 0; it < FI; ++it) {
-    const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
+    for (int it = 0; it < FI; ++it) {
+      const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
+      const int f = q / S::NFP, m = q % S::NFP, k = f / 2, sd = f & 1;
+      const int col = k == 0 ? sd * N + m % N : (k == 1 ? 2 * N + sd * N + m % N : 4 * N + m);
+      fcv[it][0] = a.FCX[lay(blk, col, 0, eg, NFC, 2)];
+      fcv[it][1] = a.FCX[lay(blk, col, 1, eg, NFC, 2)];
+      fzv[it] = a.ZZ[lay(blk, m / N, 0, eg, N, 1)];
+    }
+  } else if constexpr (!NODEM) {
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) nrd[it][c] = a.FN[at(blk, q, c, eg, S::NFPAD, DIM)];
+    for (int it = 0; it < FI; ++it) {
+      const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) nrd[it][c] = a.FN[at(blk, q, c, eg, S::NFPAD, DIM)];
+      Av[it] = 1.0;
+    }
   }
   T ur[FI][NV];
 #pragma unroll
@@ -1062,14 +1133,56 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
     }
   }
   double Sm[PI][DIM][DIM], ijv[PI];
+  double xcv[EXTR ? PI : 1][4], zzv[EXTR ? PI : 1];  // column metrics of the solution point
+  if constexpr (EXTR) {
 #pragma unroll
-  for (int it = 0; it < PI; ++it) {
-    const int t = tid + it * WG, i = min(t / EW, S::NU - 1), eg = e0 + t % EW;
+    for (int it = 0; it < PI; ++it) {
+      const int t = tid + it * WG, i = min(t / EW, S::NU - 1), eg = e0 + t % EW;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k)
+      for (int c = 0; c < 4; ++c) xcv[it][c] = a.XC[lay(blk, i % NCOL, c, eg, NCOL, 4)];
+      zzv[it] = a.ZZ[lay(blk, i / NCOL, 0, eg, N, 1)];
+    }
+  } else if constexpr (!NODEM) {
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) Sm[it][k][c] = a.SM[at(blk, i, k * DIM + c, eg, S::NUP, DIM * DIM)];
-    ijv[it] = a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
+    for (int it = 0; it < PI; ++it) {
+      const int t = tid + it * WG, i = min(t / EW, S::NU - 1), eg = e0 + t % EW;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) Sm[it][k][c] = a.SM[at(blk, i, k * DIM + c, eg, S::NUP, DIM * DIM)];
+      ijv[it] = a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
+    }
+  } else {
+    // ---- metrics from the nodes, in FP64: pass A (VA, FA0, FA1 from offset 0), pass B
+    // (VB over the nodes, past the state and jumps, so that it lasts until the gradient
+    // pass), then per thread its flux points' normals and area factors (the xi and eta
+    // faces before the barrier that frees pass A's outputs for the state, the zeta faces
+    // after it); S and 1/|J| of the solution points follow in the gradient pass
+    double *GA = reinterpret_cast<double *>(Lraw);
+    double *GB = reinterpret_cast<double *>(Lraw + NM::VB_OFF);
+#pragma unroll
+    for (int r = 0; r < XI; ++r) {
+      const int t = tid + r * WG;
+      if (t < geom::NODES * 3 * EW) GB[t] = xr[r];
+    }
+    if (tid < 6 * N) GQs[tid] = gqv;
+    __syncthreads();
+#pragma unroll 2
+    for (int t = tid; t < NM::G::NA * EW; t += WG) GA[t] = geom::pass_a<N, EW>(GB, GQs, t);
+    __syncthreads();
+#pragma unroll 2
+    for (int t = tid; t < NM::G::NB * EW; t += WG) GB[t] = geom::pass_b<N, EW>(GA, GQs, t);
+#pragma unroll
+    for (int it = 0; it < FI; ++it) {
+      const int t = tid + it * WG, q = min(t / EW, S::NF - 1);
+      if (q / S::NFP < 4) Av[it] = geom::face_metrics<N, EW>(GA, GB, GQs, t % EW, q, nrd[it]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < FI; ++it) {
+      const int t = tid + it * WG, q = min(t / EW, S::NF - 1);
+      if (q / S::NFP >= 4) Av[it] = geom::face_metrics<N, EW>(GA, GB, GQs, t % EW, q, nrd[it]);
+    }
   }
   bas.store(B, tid);
 #pragma unroll
@@ -1082,6 +1195,26 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 
   // ---- faces: own trace, common solution jump (LDS), Rusanov flux (registers)
   T ufv[FI][NV], fiv[FI][NV], nrm[FI][DIM];
+  if constexpr (EXTR) {
+    // face row S_k of J = [[x_xi, x_eta, 0], [y_xi, y_eta, 0], [0, 0, z_zeta]]: on a xi face
+    // (y_eta z, -x_eta z, 0), on an eta face (-z y_xi, z x_xi, 0), on a zeta face
+    // (0, 0, x_xi y_eta - y_xi x_eta); area factor |S_k|, outward normal (2s - 1) S_k / |S_k|
+#pragma unroll
+    for (int it = 0; it < FI; ++it) {
+      const int t = tid + it * WG, q = min(t / EW, S::NF - 1);
+      const int f = q / S::NFP, k = f / 2;
+      const double z = fzv[it], u = fcv[it][0], w = fcv[it][1];
+      double sk[3];
+      sk[0] = k == 0 ? w * z : (k == 1 ? -(z * w) : 0.0);
+      sk[1] = k == 0 ? -(u * z) : (k == 1 ? z * u : 0.0);
+      sk[2] = k == 2 ? u : 0.0;
+      const double area = sqrt(sk[0] * sk[0] + sk[1] * sk[1] + sk[2] * sk[2]);
+      const double sg = (f & 1) ? 1.0 : -1.0;
+      Av[it] = area;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) nrd[it][c] = sg * sk[c] / area;
+    }
+  }
 #pragma unroll
   for (int it = 0; it < FI; ++it)
 #pragma unroll
@@ -1137,11 +1270,22 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   }
   __syncthreads();
 
-  // ---- solution points: corrected reference gradient (registers), then LDS is reused
+  // ---- solution points: corrected reference gradient (registers), then LDS is reused;
+  // with node metrics also S and 1/|J| from pass B's outputs, still intact above the
+  // state and jumps
   T Gr[PI][DIM][NV], ui[PI][NV];
 #pragma unroll
   for (int it = 0; it < PI; ++it) {
     const int t = tid + it * WG, e = t % EW, i = t / EW;
+    if constexpr (NODEM) {
+      double Sg[3][3];
+      ijv[it] = 1.0 / geom::point_metrics<N, EW>(reinterpret_cast<const double *>(Lraw + NM::VB_OFF), GQs, e,
+                                                  min(i, S::NU - 1), Sg);
+#pragma unroll
+      for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) Sm[it][k][c] = Sg[k][c];
+    }
     if (t >= S::NU * EW) break;
 #pragma unroll
     for (int v = 0; v < NV; ++v) ui[it][v] = Us[(i * NV + v) * EW + e];
@@ -1166,6 +1310,21 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   for (int it = 0; it < PI; ++it) {
     const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
     if (t >= S::NU * EW) break;
+    if constexpr (EXTR) {
+      // S = |J| J^-1 by rows (a_{k+1} x a_{k+2}) and |J| = a_0 . S_0 for
+      // a_0 = (x_xi, y_xi, 0), a_1 = (x_eta, y_eta, 0), a_2 = (0, 0, z_zeta)
+      const double xx = xcv[it][0], xe = xcv[it][1], yx = xcv[it][2], ye = xcv[it][3], z = zzv[it];
+      Sm[it][0][0] = ye * z;
+      Sm[it][0][1] = -(xe * z);
+      Sm[it][0][2] = 0.0;
+      Sm[it][1][0] = -(z * yx);
+      Sm[it][1][1] = z * xx;
+      Sm[it][1][2] = 0.0;
+      Sm[it][2][0] = 0.0;
+      Sm[it][2][1] = 0.0;
+      Sm[it][2][2] = xx * ye - yx * xe;
+      ijv[it] = 1.0 / (xx * Sm[it][0][0] + yx * Sm[it][0][1]);
+    }
     if (eg >= nvalid) {
 #pragma unroll
       for (int c = 0; c < NG; ++c) Gs[(i * NG + c) * EW + e] = Fs[(i * NG + c) * EW + e] = 0;
@@ -1178,7 +1337,10 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       for (int v = 0; v < NV; ++v) {
         double sg = 0.0;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) sg += Sm[it][k][c] * double(Gr[it][k][v]);
+        for (int k = 0; k < DIM; ++k) {
+          if (EXTR && (k == 2) != (c == 2)) continue;  // zero in the block form of S
+          sg += Sm[it][k][c] * double(Gr[it][k][v]);
+        }
         gu[c][v] = T(sg * ijv[it]);
         Gs[(i * NG + c * NV + v) * EW + e] = gu[c][v];
       }
@@ -1191,7 +1353,10 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       for (int v = 0; v < NV; ++v) {
         double sf = 0.0;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) sf += Sm[it][k][c] * double(Fi[c][v] - Fv[c][v]);
+        for (int c = 0; c < DIM; ++c) {
+          if (EXTR && (k == 2) != (c == 2)) continue;
+          sf += Sm[it][k][c] * double(Fi[c][v] - Fv[c][v]);
+        }
         Fs[(i * NG + k * NV + v) * EW + e] = T(sf);
       }
   }
@@ -1222,8 +1387,9 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const T pv = T(0.5) * fn[v];
-        a.PV[at(blk, q, v, eg, S::NFPAD, NV)] = pv;
-        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = (FQL ? Lq[(q * NV + v) * EW + e] : fiv[it][v]) - pv;
+        const T qv = (FQL ? Lq[(q * NV + v) * EW + e] : fiv[it][v]) - pv;
+        a.PV[at(blk, q, v, eg, S::NFPAD, NV)] = SCALED ? T(Av[it] * double(pv)) : pv;
+        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = SCALED ? T(Av[it] * double(qv)) : qv;
       }
     } else {
       const int code = -nb;
@@ -1236,8 +1402,10 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
         gas.flux_vis_n(ub, gf, nrm[it], fn, true);
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
-        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = (FQL ? Lq[(q * NV + v) * EW + e] : fiv[it][v]) - fn[v];
+      for (int v = 0; v < NV; ++v) {
+        const T qv = (FQL ? Lq[(q * NV + v) * EW + e] : fiv[it][v]) - fn[v];
+        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = SCALED ? T(Av[it] * double(qv)) : qv;
+      }
       if (forces && (code & 3) == BC_WALL) {
         // traction of the fluid on the body: W A (p n - tau . n), interior trace
         T Fw[DIM][NV];
@@ -1286,17 +1454,22 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   }
 }
 
-template <typename T, int DIM, int ORDER, int MODE, bool MORTAR>
-__global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
+// register budget: 5 waves per SIMD in FP32 (the occupancy its LDS sizing is made for)
+template <typename T, int DIM, int ORDER, int MODE, int FV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 2, 8)))
+void k_stage_b(KArgs<T> a) {
   constexpr int mode = MODE;  // RK stage or residual: fixes what is read and written
+  constexpr bool MORTAR = FV == FV_MORTAR;
   using S = Shape<DIM, ORDER>;
   using F = FS<T, DIM, ORDER>;
+  // the first launch stored the half fluxes times the area factor (node metrics)
+  constexpr bool NODEM = NodeMetrics<T, DIM, ORDER, FV>::ON;
   constexpr int EW = F::EW_B, WG = F::WG_B, NS = EB / EW, N = S::N, NV = S::NV;
   constexpr int FI = (S::NF * EW + WG - 1) / WG, PI = (S::NU * EW + WG - 1) / WG;
   __shared__ T Cs[S::NF * NV * EW];
   __shared__ T Un[S::NU * NV * EW];
   __shared__ Basis<T, N> B;
-  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : int64_t(blockIdx.x);
   const int64_t blk = wg / NS;
   const int e0 = int(wg % NS) * EW;
   const int nvalid = a.bcount[blk];
@@ -1326,7 +1499,7 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
     if (!SKIP || (t < S::NF * EW && eg < nvalid)) {
-      Av[it] = a.FA[lay(blk, q, 0, eg, S::NFPAD, 1)];
+      Av[it] = NODEM ? 1.0 : a.FA[lay(blk, q, 0, eg, S::NFPAD, 1)];
 #pragma unroll
       for (int v = 0; v < NV; ++v) qv[it][v] = a.FI[at(blk, q, v, eg, S::NFPAD, NV)];
     }
@@ -1394,7 +1567,7 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
       const int code = -nbv[it];
       if (nbv[it] >= 0) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) b[v] = T(Av[it] * double(qv[it][v] + pn[it][v]));
+        for (int v = 0; v < NV; ++v) b[v] = NODEM ? qv[it][v] + pn[it][v] : T(Av[it] * double(qv[it][v] + pn[it][v]));
       } else if (MORTAR && (code & 3) == BC_MORTAR) {
         const size_t base = size_t(code >> 3) * NV;
         if ((code >> 2) & 1) {
@@ -1409,7 +1582,7 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
         }
       } else {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) b[v] = T(Av[it] * double(qv[it][v]));
+        for (int v = 0; v < NV; ++v) b[v] = NODEM ? qv[it][v] : T(Av[it] * double(qv[it][v]));
       }
     }
 #pragma unroll
@@ -1486,6 +1659,7 @@ __global__ __launch_bounds__(256) void k_stage_b(KArgs<T> a) {
       a.UF[at(blk, q, v, eg, S::NFPAD, NV)] = sv;
     }
   }
+
 }
 
 // ---------------------------------------------------------------------------
@@ -1593,6 +1767,8 @@ template <typename T> static KArgs<T> make_args(const LaunchCfg &c, const DevArr
   a.opInt = (const T *)d.opInt; a.opGrad = (const T *)d.opGrad; a.opGcorr = (const T *)d.opGcorr;
   a.opDivS = (const T *)d.opDivS; a.opCorr = (const T *)d.opCorr; a.basis = (const T *)d.basis;
   a.SM = d.SM; a.IJ = d.IJ; a.FN = d.FN; a.FA = d.FA; a.bdt = d.bdt; a.fsd = d.fsd; a.wface = d.wface;
+  a.XN = d.XN; a.GQ = d.GQ;
+  a.XC = d.XC; a.ZZ = d.ZZ; a.FCX = d.FCX;
   a.FC = d.FC; a.fsum = d.fsum; a.stage64 = d.stage64;
   a.NB = d.NB; a.bcount = d.bcount; a.bdesign = d.bdesign; a.bcanon = d.bcanon; a.wall_first = d.wall_first;
   a.flag = d.flag;
@@ -1600,20 +1776,23 @@ template <typename T> static KArgs<T> make_args(const LaunchCfg &c, const DevArr
   a.GUF = (const T *const *)d.GUF; a.GPV = (const T *const *)d.GPV; a.MT = (T *)d.MT;
   a.PO = d.PO; a.PC = d.PC; a.PW = d.PW;
   a.nblk = c.nblk; a.n_canon = c.n_canon; a.ndesign = c.ndesign;
+  a.xcd = (c.variant_mask & NO_XCD_REMAP) ? 0 : 1;
   a.gam = T(c.gamma); a.mu = T(c.mu); a.kappa = T(c.mu * c.gamma / c.prandtl);
   return a;
 }
 
-template <typename T, int DIM, int ORDER, bool MORTAR>
-static hipError_t launch_stage_b(int mode, dim3 grid, dim3 wgs, hipStream_t stream, const KArgs<T> &a) {
+template <typename T, int DIM, int ORDER, int FV>
+static hipError_t launch_stage_b(const LaunchCfg &c, int mode, int64_t ntiles, dim3 wgs, const KArgs<T> &a) {
+  auto go = [&](auto kern) {
+    const dim3 grid(static_cast<unsigned>(ntiles));
+    hipLaunchKernelGGL(kern, grid, wgs, 0, c.stream, a);
+  };
   switch (mode) {
-    case MODE_RK0: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK0, MORTAR>), grid, wgs, 0, stream, a); break;
-    case MODE_RK1: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK1, MORTAR>), grid, wgs, 0, stream, a); break;
-    case MODE_RK2: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK2, MORTAR>), grid, wgs, 0, stream, a); break;
-    case MODE_RK3: hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RK3, MORTAR>), grid, wgs, 0, stream, a); break;
-    case MODE_RESID:
-      hipLaunchKernelGGL((k_stage_b<T, DIM, ORDER, MODE_RESID, MORTAR>), grid, wgs, 0, stream, a);
-      break;
+    case MODE_RK0: go(k_stage_b<T, DIM, ORDER, MODE_RK0, FV>); break;
+    case MODE_RK1: go(k_stage_b<T, DIM, ORDER, MODE_RK1, FV>); break;
+    case MODE_RK2: go(k_stage_b<T, DIM, ORDER, MODE_RK2, FV>); break;
+    case MODE_RK3: go(k_stage_b<T, DIM, ORDER, MODE_RK3, FV>); break;
+    case MODE_RESID: go(k_stage_b<T, DIM, ORDER, MODE_RESID, FV>); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1655,17 +1834,30 @@ static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, i
                            int(forces));
       break;
     case K_STAGE_A: {
-      const dim3 grid(c.nblk * (EB / FS<T, DIM, ORDER>::EW_A)), wgs(FS<T, DIM, ORDER>::WG_A);
+      const int64_t ntiles = c.nblk * (EB / FS<T, DIM, ORDER>::EW_A);
+      const dim3 wgs(FS<T, DIM, ORDER>::WG_A);
+      auto go = [&](auto kern) {
+        const dim3 grid(static_cast<unsigned>(ntiles));
+        hipLaunchKernelGGL(kern, grid, wgs, 0, c.stream, a, X, int(forces));
+      };
       if (d.MO)
-        hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER, true>), grid, wgs, 0, c.stream, a, X, int(forces));
+        go(k_stage_a<T, DIM, ORDER, FV_MORTAR>);
+      else if (DIM == 3 && (c.variant_mask & EXTRUDED_METRICS) && d.XC)
+        go(k_stage_a<T, DIM, ORDER, DIM == 3 ? FV_EXTR : FV_STORED>);
+      else if (DIM == 3 && !(c.variant_mask & STORED_METRICS))
+        go(k_stage_a<T, DIM, ORDER, DIM == 3 ? FV_NODE : FV_STORED>);
       else
-        hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER, false>), grid, wgs, 0, c.stream, a, X, int(forces));
+        go(k_stage_a<T, DIM, ORDER, FV_STORED>);
       break;
     }
     case K_STAGE_B: {
-      const dim3 grid(c.nblk * (EB / FS<T, DIM, ORDER>::EW_B)), wgs(FS<T, DIM, ORDER>::WG_B);
-      if (d.MO) return launch_stage_b<T, DIM, ORDER, true>(mode, grid, wgs, c.stream, a);
-      return launch_stage_b<T, DIM, ORDER, false>(mode, grid, wgs, c.stream, a);
+      const int64_t ntiles = c.nblk * (EB / FS<T, DIM, ORDER>::EW_B);
+      const dim3 wgs(FS<T, DIM, ORDER>::WG_B);
+      if (d.MO) return launch_stage_b<T, DIM, ORDER, FV_MORTAR>(c, mode, ntiles, wgs, a);
+      // the extruded first launch scales the half fluxes by the area factor like FV_NODE
+      if (DIM == 3 && (((c.variant_mask & EXTRUDED_METRICS) && d.XC) || !(c.variant_mask & STORED_METRICS)))
+        return launch_stage_b<T, DIM, ORDER, DIM == 3 ? FV_NODE : FV_STORED>(c, mode, ntiles, wgs, a);
+      return launch_stage_b<T, DIM, ORDER, FV_STORED>(c, mode, ntiles, wgs, a);
     }
     case K_DIVRK:
       if (tensor)

@@ -90,6 +90,9 @@ fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
     const fr::Dims D(d->dim, int(maxp));
     const size_t rs = d->precision == FR_FP32 ? 4 : 8;
     total += size_t(nwall) * D.nfp * 3 * 8;
+    if (d->dim == 3)  // column metrics of groups of extruded elements, at the highest order
+      total += size_t(d->n_elems + 8 * fr::EB) * 8 *
+               (size_t(D.n) * D.n * 4 + D.n + (4 * size_t(D.n) + size_t(D.n) * D.n) * 2);
     // mortar data. Faces are matched by their corner node ids; a face shared by elements
     // of two orders carries nfp_H + nfp_L mortar points, nfp_H nfp_L interpolation entries
     // and, for its lower-order points, nfp_L nfp_H trace and nfp_L nfp_H projection
@@ -158,6 +161,9 @@ fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
   b += size_t(nblk) * D.nup * dim * dim * fr::EB * 8 + size_t(nblk) * D.nup * fr::EB * 8;
   b += size_t(nblk) * D.nfpad * dim * fr::EB * 8 + size_t(nblk) * D.nfpad * fr::EB * 8;
   b += size_t(nblk) * D.nfpad * fr::EB * 4;
+  if (dim == 3) b += size_t(nblk) * 27 * 3 * fr::EB * 8 + size_t(6 * D.n) * 8;  // geometry nodes, basis
+  if (fr::desc_extruded(*d))  // column metrics
+    b += size_t(nblk) * fr::EB * 8 * (size_t(D.n) * D.n * 4 + D.n + (4 * size_t(D.n) + size_t(D.n) * D.n) * 2);
   b += r256(nblk * 4) * 2 + r256(nblk * 8) * 2 + r256(5 * 8) + r256(2 * 8) + r256(D.nfpad * 8);
   // state and stage arrays
   const size_t nU = size_t(nblk) * D.nup * nv * fr::EB, nF = size_t(nblk) * D.nfpad * nv * fr::EB;

@@ -169,7 +169,7 @@ def naca_ogrid(m, pc, t, ni, nj, nk, span=0.2, radius=20.0, ratio=1.1, q=2, orde
         np.stack([inner, np.full_like(inner, 2), np.full_like(inner, inner_bc)], 1),
         np.stack([outer, np.full_like(outer, 3), np.full_like(outer, outer_bc)], 1)]).astype(np.int64)
     return dict(dim=3, order=order, q=q, nodes=nodes, elem_nodes=elem.astype(np.int64),
-                periodic=np.array([[0.0, 0.0, span]]), bfaces=bfaces)
+                periodic=np.array([[0.0, 0.0, span]]), bfaces=bfaces, grid=(ni, nj, nk))
 
 
 def ring_orders(ni, nj, nk, bands):

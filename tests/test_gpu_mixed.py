@@ -10,7 +10,8 @@ uniform order-0 mesh (one solution point per element: a finite volume).
 Bars (as for one order, relative L2 per physical field): FP64 residual and FP64 RK4
 state 1e-12; FP32 form 1e-5 after 100 steps; wall force means 1e-10; a variable-order
 mesh whose orders are all equal bit-identical to the one-order mesh; a pool request
-bit-identical to its solo run.
+bit-identical to its solo run; designs of a variable-order batch bit-identical to
+their solo runs.
 """
 import numpy as np
 import pytest
@@ -167,7 +168,7 @@ def test_equal_orders_bit_identical_to_one_order(precision):
     m = W.config_airfoil(3, ni=24, nj=5, nk=2)
     mm = dict(m, orders=np.full(len(m["elem_nodes"]), 3, dtype=np.int32))
     g1, g2 = FRMesh(m, precision), FRMesh(mm, precision)
-    g1.select_kernels(1 | (1 << 5))   # the structure variable-order meshes run
+    g1.select_kernels(g2.selected_kernels())   # the structure the order group runs
     o = OracleMesh(m)
     u0 = state(o, m).reshape(o.shape)
     g1.set_state(u0)
@@ -258,6 +259,61 @@ def test_mixed_sampled_pool_request_matches_hand_driven_pipeline():
     assert np.array_equal(f, g.forces())
 
 
+def _batch_designs():
+    """Two O-grids with their own order rings (P3-P0, and P3-P1 on a smaller grid) and a
+    uniform-order O-grid: one batch of variable-order designs of uneven size."""
+    a = ogrid(seed=7, ni=24, nj=8, nk=2)
+    b = W.config_airfoil(8, ni=16, nj=6, nk=1)
+    b["orders"] = W.ring_orders(16, 6, 1, ((1, 3), (3, 2), (6, 1)))
+    b["dt"] = W.airfoil_dt(dict(b, order=3), 3)
+    c = W.config_airfoil(9, ni=16, nj=4, nk=2)
+    return [a, b, c]
+
+
+def _points(m):
+    if m.get("orders") is None:
+        return len(m["elem_nodes"]) * (m["order"] + 1) ** 3
+    return int(((np.asarray(m["orders"]) + 1) ** 3).sum())
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_mixed_batch_members_match_solo_and_oracle(precision, tol):
+    """Variable order in a batch: every order group covers the elements of that order of
+    all designs.  Designs with mortar faces are bit-identical to their solo runs (same
+    kernel build), the uniform-order design (run by the batch's mortar build) within the
+    bar; two designs against the oracle."""
+    meshes = _batch_designs()
+    states = [state(OracleMesh(m), m, seed=i) for i, m in enumerate(meshes)]
+    b = FRMesh(meshes, precision)
+    assert b.n_designs == 3 and b.n_points == sum(_points(m) for m in meshes)
+    b.set_state(np.concatenate(states))
+    n = 10
+    b.step(n)
+    ub = b.get_state()
+    off = np.cumsum([0] + [_points(m) for m in meshes])
+    for i, m in enumerate(meshes):
+        g = FRMesh(m, precision)
+        g.set_state(states[i])
+        g.step(n)
+        us = g.get_state().reshape(-1, ub.shape[-1])
+        part = ub[off[i]:off[i + 1]]
+        if m.get("orders") is not None:
+            assert np.array_equal(part, us), i
+            assert np.array_equal(b.forces(i), g.forces()), i
+        else:
+            err = rel_err(part, us)
+            print(f"uniform design in the variable-order batch vs solo ({precision}): {err:.2e}", flush=True)
+            assert err <= tol
+        g.close()
+    for i in (0, 2):
+        o = OracleMesh(meshes[i])
+        ref = o.rk4(states[i].reshape(o.shape), meshes[i]["dt"], n)
+        err = rel_err(ub[off[i]:off[i + 1]], ref)
+        print(f"design {i} in the variable-order batch vs oracle, {n} steps ({precision}): {err:.2e}", flush=True)
+        assert err <= tol
+    b.close()
+
+
 def test_mixed_unsupported_calls_are_rejected():
     m = box(2, 1, 0.0, 1, 5, False)
     g = FRMesh(m, "fp64")
@@ -267,9 +323,9 @@ def test_mixed_unsupported_calls_are_rejected():
     with pytest.raises(_lib.FRError) as e:
         g.neighbours()
     assert e.value.code == _lib.FR_E_UNSUPPORTED
-    with pytest.raises(_lib.FRError) as e:
-        FRMesh([m, m], "fp64")
-    assert e.value.code == _lib.FR_E_UNSUPPORTED
+    with pytest.raises(_lib.FRError) as e:  # batched designs share the gas constants
+        FRMesh([m, dict(m, mu=0.05)], "fp64")
+    assert e.value.code == _lib.FR_E_ARG
     bad = dict(m, orders=np.full(len(m["elem_nodes"]), 6, dtype=np.int32))
     with pytest.raises(_lib.FRError) as e:
         FRMesh(bad, "fp64")

@@ -79,19 +79,36 @@ CASES = ["vortex2d_p3", "vortex2d_p1", "vortex2d_p4", "box2d_curved_p2", "tgv_p1
          "airfoil_p3", "airfoil_p2", "airfoil_p4"]
 # kernel structures / operator back-ends: five launches per stage with dense
 # element-batched MFMA contractions or sum factorisation, or the fused
-# two-launch stage (sum factorised)
-VARIANTS = {"dense": 0, "tensor": (1 << 2) | (1 << 3) | (1 << 4) | (1 << 5), "fused": 1 | (1 << 5)}
+# two-launch stage (sum factorised), in 3D with its FP64 metrics formed from the
+# geometry nodes, read from the stored arrays, or formed from the column metrics of
+# z-extruded elements
+VARIANTS = {"dense": 0, "tensor": (1 << 2) | (1 << 3) | (1 << 4) | (1 << 5), "fused": 1 | (1 << 5),
+            "fused_stored": 1 | (1 << 5) | (1 << 6), "fused_extruded": 1 | (1 << 5) | (1 << 8)}
 
 
-@pytest.mark.parametrize("variant", sorted(VARIANTS))
-@pytest.mark.parametrize("name", CASES)
+def select(g, variant):
+    """Select a kernel structure; column metrics exist only on meshes of z-extruded elements."""
+    try:
+        g.select_kernels(VARIANTS[variant])
+    except _lib.FRError as e:
+        if e.code == _lib.FR_E_UNSUPPORTED and variant == "fused_extruded":
+            pytest.skip("column metrics need a mesh of z-extruded elements")
+        raise
+
+
+# column metrics exist on 3D meshes only
+VARIANTS_2D = sorted(v for v in VARIANTS if v != "fused_extruded")
+CASE_VARIANTS = [(n, v) for n in CASES for v in (VARIANTS_2D if n.startswith(("vortex2d", "box2d")) else sorted(VARIANTS))]
+
+
+@pytest.mark.parametrize("name,variant", CASE_VARIANTS)
 def test_residual_fp64_matches_oracle(name, variant):
     m = case(name)
     o = OracleMesh(m)
     u = perturbed(o, m)
     ref = o.residual(u)
     g = FRMesh(m, "fp64")
-    g.select_kernels(VARIANTS[variant])
+    select(g, variant)
     assert g.selected_kernels() == VARIANTS[variant]
     assert np.array_equal(g.neighbours(), o.neighbours())
     r = g.residual(u)
@@ -102,17 +119,28 @@ def test_residual_fp64_matches_oracle(name, variant):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-4)])
 def test_variants_agree_and_mix(prec, tol):
-    """Every per-kernel mix of the two back-ends gives the same residual to round-off
-    (FP32: the residual amplifies the flux rounding, as in the FP32-vs-oracle test)."""
+    """Every per-kernel mix of the two back-ends on the stored metrics gives the same
+    residual to round-off (FP32: the residual amplifies the flux rounding, as in the
+    FP32-vs-oracle test).  The fused stage with metrics formed from the geometry nodes
+    or from the column metrics of the O-grid's z-extruded elements evaluates S, |J|,
+    normals and areas in FP64 by another route, equal to round-off;
+    on this O-grid's sliver elements the residual amplifies that to a few 1e-13, so it
+    is held to the oracle bar (1e-12 in FP64)."""
     m = case("airfoil_p3")
     o = OracleMesh(m)
     u = perturbed(o, m)
     g = FRMesh(m, prec)
     g.select_kernels(0)
     ref = g.residual(u)
-    for mask in (VARIANTS["tensor"], VARIANTS["fused"], 1, 1 << 2, (1 << 3) | (1 << 5), 1 << 4):
+    for mask in (VARIANTS["tensor"], VARIANTS["fused_stored"], 1 | (1 << 6), 1 << 2, (1 << 3) | (1 << 5), 1 << 4):
         g.select_kernels(mask)
         assert rel_err(g.residual(u), ref) <= tol, mask
+    for mask in (VARIANTS["fused"], 1, VARIANTS["fused_extruded"]):
+        g.select_kernels(mask)
+        err = rel_err(g.residual(u), ref)
+        print(f"airfoil_p3 {prec}: metrics from nodes or columns (mask {mask}) vs stored, residual rel L2 "
+              f"{err:.2e}", flush=True)
+        assert err <= (1e-12 if prec == "fp64" else tol), mask
 
 
 @pytest.mark.parametrize("name", ["vortex2d_p3", "tgv_p3", "airfoil_p3"])
@@ -130,7 +158,7 @@ def test_residual_fp32_close_to_oracle(name):
     assert err <= 1e-3
 
 
-@pytest.mark.parametrize("variant", sorted(VARIANTS))
+@pytest.mark.parametrize("variant", VARIANTS_2D)
 def test_vortex_state_after_100_steps(variant):
     """Isentropic vortex, 16x16 periodic quads, p = 3, 100 RK4 steps of 1e-3."""
     m = W.config_vortex(0)
@@ -139,7 +167,7 @@ def test_vortex_state_after_100_steps(variant):
     ref = o.rk4(u0, m["dt"], 100)
     for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
         g = FRMesh(m, prec)
-        g.select_kernels(VARIANTS[variant])
+        select(g, variant)
         g.set_state(u0)
         g.step(100)
         err = rel_err(g.get_state(), ref)
@@ -155,7 +183,7 @@ def test_tgv_state_after_steps(variant):
     ref = o.rk4(u0, m["dt"], 100)
     for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
         g = FRMesh(m, prec)
-        g.select_kernels(VARIANTS[variant])
+        select(g, variant)
         g.set_state(u0)
         g.step(100)
         err = rel_err(g.get_state(), ref)
@@ -171,7 +199,7 @@ def test_airfoil_state_and_forces(variant):
     n = 20
     ref, hist = o.rk4(u0, m["dt"], n, forces=True)
     g = FRMesh(m, "fp64")
-    g.select_kernels(VARIANTS[variant])
+    select(g, variant)
     g.set_state(u0)
     g.step(n)
     err = rel_err(g.get_state(), ref)
@@ -203,7 +231,7 @@ def test_airfoil_p4_state_after_100_steps(variant):
     scale = np.abs(hist).max() / qref
     for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
         g = FRMesh(m, prec)
-        g.select_kernels(VARIANTS[variant])
+        select(g, variant)
         g.set_state(u0)
         g.step(n)
         err = rel_err(g.get_state(), ref)
