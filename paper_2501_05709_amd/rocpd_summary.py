@@ -12,6 +12,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sqlite3
 from collections import defaultdict
 
@@ -41,17 +42,23 @@ def kernels(db):
 
 
 def traffic_entry(fetch_db, write_db, kernel, copy_bytes):
-    """HBM bytes per launch of `kernel` from FETCH_SIZE and WRITE_SIZE runs, each scaled by
-    what the same counter reads for the largest device copy (copy_bytes read and written)."""
+    """HBM bytes per launch of the kernels whose names match the regular expression
+    `kernel` (all their dispatches together: the RK-stage instances of one kernel, say),
+    from FETCH_SIZE and WRITE_SIZE runs, each scaled by what the same counter reads for
+    the largest device copy (copy_bytes read and written)."""
+    pat = re.compile(kernel)
+
     def per_kernel(db, counter):
         agg = counters(db)
-        k = [v for (name, c), v in agg.items() if c == counter and kernel in name]
+        k = [v for (name, c), v in agg.items() if c == counter and pat.search(name)]
+        if not k:
+            raise SystemExit(f"no dispatch of a kernel matching {kernel!r} with {counter} in {db}")
         con = sqlite3.connect(db)
         # the calibration copy is the device copy dispatch with the largest count
         big = max(float(r[0]) for r in con.execute(
             "select value from counters_collection where counter_name = ? and kernel_name like '%copyBuffer%'",
             (counter,)))
-        return k[0][1] / k[0][0], big
+        return sum(v[1] for v in k) / sum(v[0] for v in k), big
     f_k, f_copy = per_kernel(fetch_db, "FETCH_SIZE")
     w_k, w_copy = per_kernel(write_db, "WRITE_SIZE")
     f_scale = copy_bytes / (f_copy * 1024.0)
@@ -66,8 +73,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db", nargs="+")
     ap.add_argument("--match", default="")
-    ap.add_argument("--traffic", nargs=4, metavar=("WORKLOAD", "KERNEL", "FETCH_DB", "WRITE_DB"),
-                    help="write the counter traffic of KERNEL into profiles/counters.json")
+    ap.add_argument("--traffic", nargs=4, metavar=("WORKLOAD", "KERNEL_REGEX", "FETCH_DB", "WRITE_DB"),
+                    help="write the counter traffic of the kernels matching KERNEL_REGEX into "
+                         "profiles/counters.json, keyed by the name before the template arguments")
     ap.add_argument("--copy-bytes", type=float, default=2.0 ** 30)
     args = ap.parse_args()
     if args.traffic:
@@ -79,7 +87,7 @@ def main():
         entry["kernel_match"] = kernel
         path = os.path.join(root, "profiles", "counters.json")
         data = json.load(open(path)) if os.path.exists(path) else {}
-        data.setdefault(workload, {})[kernel.split("<")[0]] = entry
+        data.setdefault(workload, {})[re.split(r"[<\\]", kernel)[0]] = entry
         json.dump(data, open(path, "w"), indent=1, sort_keys=True)
         print(json.dumps(entry))
         return
