@@ -45,7 +45,7 @@ def traffic_entry(fetch_db, write_db, kernel, copy_bytes):
     """HBM bytes per launch of the kernels whose names match the regular expression
     `kernel` (all their dispatches together: the RK-stage instances of one kernel, say),
     from FETCH_SIZE and WRITE_SIZE runs, each scaled by what the same counter reads for
-    the largest device copy (copy_bytes read and written)."""
+    the calibration copy (copy_bytes read and written), the first copy of the run."""
     pat = re.compile(kernel)
 
     def per_kernel(db, counter):
@@ -54,11 +54,13 @@ def traffic_entry(fetch_db, write_db, kernel, copy_bytes):
         if not k:
             raise SystemExit(f"no dispatch of a kernel matching {kernel!r} with {counter} in {db}")
         con = sqlite3.connect(db)
-        # the calibration copy is the device copy dispatch with the largest count
-        big = max(float(r[0]) for r in con.execute(
-            "select value from counters_collection where counter_name = ? and kernel_name like '%copyBuffer%'",
-            (counter,)))
-        return sum(v[1] for v in k) / sum(v[0] for v in k), big
+        # the calibration copy is the first device copy of the run (bench.py
+        # --calibrate-copy copies copy_bytes before anything else); larger copies may
+        # follow (a batch's FP64 state saved by the autotuner)
+        first = con.execute(
+            "select value from counters_collection where counter_name = ? and kernel_name like '%copyBuffer%' "
+            "order by dispatch_id limit 1", (counter,)).fetchone()
+        return sum(v[1] for v in k) / sum(v[0] for v in k), float(first[0])
     f_k, f_copy = per_kernel(fetch_db, "FETCH_SIZE")
     w_k, w_copy = per_kernel(write_db, "WRITE_SIZE")
     f_scale = copy_bytes / (f_copy * 1024.0)
