@@ -20,7 +20,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfr.so")
-SOURCES = ["fr_kernels.hip", "fr_host.cpp", "fr_pool.cpp", "fr_fwh.hip"]
+# (source, object stem, extra defines): the FR kernel file is compiled in five parts, its
+# launchers of one precision and dimension each plus the dispatch, built in parallel
+KERNEL_PARTS = 5
+SOURCES = ([("fr_kernels.hip", f"fr_kernels_part{k}", [f"-DFR_PART={k}"]) for k in range(KERNEL_PARTS)]
+           + [(s, s, []) for s in ("fr_host.cpp", "fr_pool.cpp", "fr_fwh.hip")])
 ARCH = "gfx950"
 
 
@@ -59,21 +63,22 @@ def parse_resource_usage(text):
     return out
 
 
-def _compile(src, verbose):
+def _compile(job, verbose):
+    src, stem, defines = job
     os.makedirs(OBJ, exist_ok=True)
-    out = os.path.join(OBJ, os.path.basename(src) + ".o")
+    out = os.path.join(OBJ, stem + ".o")
     device = src.endswith(".hip")
     lang = ["-x", "hip"] if device else []
     # device sources also report each kernel's registers, spills, occupancy and LDS
     remarks = ["-Rpass-analysis=kernel-resource-usage"] if device else []
-    cmd = [hipcc()] + common_flags() + lang + remarks + ["-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [hipcc()] + common_flags() + defines + lang + remarks + ["-c", os.path.join(CSRC, src), "-o", out]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {src}\n{r.stdout}\n{r.stderr}")
     if device:
-        with open(os.path.join(OBJ, os.path.basename(src) + ".resources.json"), "w") as f:
+        with open(os.path.join(OBJ, stem + ".resources.json"), "w") as f:
             json.dump(parse_resource_usage(r.stderr), f, indent=0, sort_keys=True)
     warnings = "\n".join(l for l in r.stderr.splitlines() if "warning:" in l)
     if verbose and warnings:
@@ -82,8 +87,15 @@ def _compile(src, verbose):
 
 
 def build(verbose=False):
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    # one resource report for the kernel file: the union of its parts
+    merged = {}
+    for k in range(KERNEL_PARTS):
+        with open(os.path.join(OBJ, f"fr_kernels_part{k}.resources.json")) as f:
+            merged.update(json.load(f))
+    with open(os.path.join(OBJ, "fr_kernels.hip.resources.json"), "w") as f:
+        json.dump(merged, f, indent=0, sort_keys=True)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

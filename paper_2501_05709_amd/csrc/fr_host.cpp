@@ -1818,8 +1818,13 @@ fr_status fr_select_kernels(fr_mesh *m, int32_t mask) {
     }
     if ((unsigned(mask) & EXTRUDED_METRICS) && !m->extruded)
       fail(FR_E_UNSUPPORTED, "column metrics need a mesh of z-extruded elements");
+    if ((unsigned(mask) & TILE_BITS) &&
+        (!tiles_compiled(m->dim, m->order, false) || tile_a(unsigned(mask)) >= N_TILES ||
+         tile_b(unsigned(mask)) >= N_TILES))
+      fail(FR_E_UNSUPPORTED, "tile shapes other than the default exist for 3D meshes of order 1 to 4 only");
     m->cfg.variant_mask = unsigned(mask) & (FUSED | (1u << K_INTERP) | (1u << K_GRAD) | (1u << K_VISC) |
-                                            (1u << K_DIVRK) | STORED_METRICS | NO_XCD_REMAP | EXTRUDED_METRICS);
+                                            (1u << K_DIVRK) | STORED_METRICS | NO_XCD_REMAP | EXTRUDED_METRICS |
+                                            TILE_BITS);
     drop_graphs(m);
   });
 }
@@ -1869,6 +1874,33 @@ fr_status fr_autotune(fr_mesh *m, int64_t steps, int32_t *mask_out) {
           fused_mask = m->cfg.variant_mask;
         }
       }
+    }
+    // tile shapes of the two fused launches, each timed on its own kernel with the other
+    // launch at the shape chosen so far
+    if (tiles_compiled(m->dim, m->order, false)) {
+      double best_a = 1e300, best_b = 1e300;
+      int ta_best = 0, tb_best = 0;
+      for (int ta = 0; ta < N_TILES; ++ta) {
+        m->cfg.variant_mask = (fused_mask & ~TILE_BITS) | tile_bits(ta, 0);
+        profile_steps(m, steps, ms_fused, n);
+        hip_check(hipMemcpyAsync(m->a.U, m->a.RES, nb, hipMemcpyDeviceToDevice, m->stream), "restore state");
+        if (ms_fused[K_STAGE_A] < best_a) {
+          best_a = ms_fused[K_STAGE_A];
+          ta_best = ta;
+        }
+        if (ta == 0) best_b = ms_fused[K_STAGE_B];
+      }
+      for (int tb = 1; tb < N_TILES; ++tb) {
+        m->cfg.variant_mask = (fused_mask & ~TILE_BITS) | tile_bits(ta_best, tb);
+        profile_steps(m, steps, ms_fused, n);
+        hip_check(hipMemcpyAsync(m->a.U, m->a.RES, nb, hipMemcpyDeviceToDevice, m->stream), "restore state");
+        if (ms_fused[K_STAGE_B] < best_b) {
+          best_b = ms_fused[K_STAGE_B];
+          tb_best = tb;
+        }
+      }
+      fused_mask = (fused_mask & ~TILE_BITS) | tile_bits(ta_best, tb_best);
+      fused = std::min(fused, best_a + best_b);
     }
     unsigned mask = 0;
     double split = ms_dense[K_FACE];

@@ -53,6 +53,16 @@ constexpr unsigned STORED_METRICS = 1u << 6;
 constexpr unsigned NO_XCD_REMAP = 1u << 7;
 // Fused stage on a mesh of z-extruded elements: metrics from the column data (XC, ZZ, FCX)
 constexpr unsigned EXTRUDED_METRICS = 1u << 8;
+// Tile shape of the fused stage's first launch (bits 9-10) and second launch (bits 11-12):
+// 0 the default workgroup, 1 half its elements, 2 a quarter (at least one). Compiled for
+// 3D one-order meshes of order 1 up; other meshes run the default.
+constexpr int TILE_A_SHIFT = 9, TILE_B_SHIFT = 11;
+constexpr unsigned TILE_BITS = (3u << TILE_A_SHIFT) | (3u << TILE_B_SHIFT);
+constexpr int N_TILES = 3;
+inline int tile_a(unsigned mask) { return int((mask >> TILE_A_SHIFT) & 3u); }
+inline int tile_b(unsigned mask) { return int((mask >> TILE_B_SHIFT) & 3u); }
+inline unsigned tile_bits(int ta, int tb) { return (unsigned(ta) << TILE_A_SHIFT) | (unsigned(tb) << TILE_B_SHIFT); }
+inline bool tiles_compiled(int dim, int order, bool mixed) { return dim == 3 && order >= 1 && !mixed; }
 
 // Modes of K_DIVRK
 enum { MODE_RK0 = 0, MODE_RK1 = 1, MODE_RK2 = 2, MODE_RK3 = 3, MODE_RESID = 4 };

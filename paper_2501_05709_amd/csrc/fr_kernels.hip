@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fr_internal.hpp"
 #include "fr_geom.hpp"
@@ -976,10 +977,20 @@ __device__ inline int64_t xcd_remap(int64_t wg, int64_t nwg) {
 
 enum { FV_NODE = 0, FV_STORED = 1, FV_MORTAR = 2, FV_EXTR = 3 };
 
-template <typename T, int DIM, int ORDER> struct FS {
+// Tile shapes of the fused stage, one per launch (picked by the autotuner): TILE_DEFAULT
+// sizes the workgroup from the LDS budgets below; TILE_HALF and TILE_QUARTER give it a
+// half or a quarter of those elements (at least one): smaller workgroups, more of them
+// per compute unit, each waiting at its barriers for fewer waves.
+enum { TILE_DEFAULT = 0, TILE_HALF = 1, TILE_QUARTER = 2 };
+
+template <typename T, int DIM, int ORDER, int TILE = TILE_DEFAULT> struct FS {
   using S = Shape<DIM, ORDER>;
-  static constexpr int ew(int bytes, int budget) {
+  static constexpr int ew0(int bytes, int budget) {
     return bytes * 16 <= budget ? 16 : bytes * 8 <= budget ? 8 : bytes * 4 <= budget ? 4 : bytes * 2 <= budget ? 2 : 1;
+  }
+  static constexpr int ew(int bytes, int budget) {
+    return TILE == TILE_DEFAULT ? ew0(bytes, budget)
+                                : (ew0(bytes, budget) >> TILE) > 0 ? ew0(bytes, budget) >> TILE : 1;
   }
   // stage a: max(state + jumps, gradient + transformed flux) per element (aliased)
   static constexpr int LDS_A_ELEM = (S::NU * S::NV + S::NF * S::NV) > 2 * S::NU * S::NG
@@ -1008,9 +1019,9 @@ template <typename T, int DIM, int ORDER> struct FS {
 // elements, forms S, 1/|J|, normals and area factors from its column metrics (the 2D
 // Jacobian at the n^2 solution-point columns, z_zeta at the n layers, the face columns)
 // with a few FP64 products, and scales the half fluxes as FV_NODE does.
-template <typename T, int DIM, int ORDER, int FV> struct NodeMetrics {
+template <typename T, int DIM, int ORDER, int FV, int TILE = TILE_DEFAULT> struct NodeMetrics {
   using S = Shape<DIM, ORDER>;
-  using F = FS<T, DIM, ORDER>;
+  using F = FS<T, DIM, ORDER, TILE>;
   static constexpr bool ON = DIM == 3 && FV == FV_NODE;
   static constexpr int EW = F::EW_A;
   using G = geom::Lay<S::N, EW>;
@@ -1025,14 +1036,14 @@ template <typename T, int DIM, int ORDER, int FV> struct NodeMetrics {
 
 // register budget: 4 waves per SIMD in FP32 (3 with node metrics, whose FP64 metric
 // products need more registers), 2 in FP64
-template <typename T, int DIM, int ORDER, int FV>
+template <typename T, int DIM, int ORDER, int FV, int TILE>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (NodeMetrics<T, DIM, ORDER, FV>::ON ? 3 : 4) : 2, 8)))
 void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   constexpr bool MORTAR = FV == FV_MORTAR;
   using S = Shape<DIM, ORDER>;
-  using F = FS<T, DIM, ORDER>;
-  using NM = NodeMetrics<T, DIM, ORDER, FV>;
+  using F = FS<T, DIM, ORDER, TILE>;
+  using NM = NodeMetrics<T, DIM, ORDER, FV, TILE>;
   constexpr bool NODEM = NM::ON;
   constexpr bool EXTR = DIM == 3 && FV == FV_EXTR;
   constexpr bool SCALED = NODEM || EXTR;  // Q and P stored times the area factor
@@ -1454,14 +1465,15 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   }
 }
 
-// register budget: 5 waves per SIMD in FP32 (the occupancy its LDS sizing is made for)
-template <typename T, int DIM, int ORDER, int MODE, int FV>
+// register budget: 5 waves per SIMD in FP32 (the occupancy its default LDS sizing is made
+// for), 2 in FP64
+template <typename T, int DIM, int ORDER, int MODE, int FV, int TILE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 2, 8)))
 void k_stage_b(KArgs<T> a) {
   constexpr int mode = MODE;  // RK stage or residual: fixes what is read and written
   constexpr bool MORTAR = FV == FV_MORTAR;
   using S = Shape<DIM, ORDER>;
-  using F = FS<T, DIM, ORDER>;
+  using F = FS<T, DIM, ORDER, TILE>;
   // the first launch stored the half fluxes times the area factor (node metrics)
   constexpr bool NODEM = NodeMetrics<T, DIM, ORDER, FV>::ON;
   constexpr int EW = F::EW_B, WG = F::WG_B, NS = EB / EW, N = S::N, NV = S::NV;
@@ -1686,6 +1698,7 @@ __global__ __launch_bounds__(256) void k_pack(KArgs<T> a, T *dst, int to_device)
 // ---------------------------------------------------------------------------
 // wall force reduction: one workgroup per design, fixed summation order
 // ---------------------------------------------------------------------------
+#if FR_PART == 4
 __global__ __launch_bounds__(256) void k_force_reduce(const double *FC, const int64_t *wall_first,
                                                        double *fsum) {
   const int d = blockIdx.x;
@@ -1714,6 +1727,7 @@ __global__ __launch_bounds__(256) void k_force_reduce(const double *FC, const in
 __global__ void k_clear_flag(int *flag) {
   if (threadIdx.x == 0 && blockIdx.x == 0) flag[0] = 0;
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // sampling: the FR interpolant of the stage-0 state at points (one thread each)
@@ -1781,21 +1795,54 @@ template <typename T> static KArgs<T> make_args(const LaunchCfg &c, const DevArr
   return a;
 }
 
+template <typename T, int DIM, int ORDER, int FV, int TILE>
+static void go_stage_a(const LaunchCfg &c, const KArgs<T> &a, const T *X, bool forces) {
+  using F = FS<T, DIM, ORDER, TILE>;
+  const dim3 grid(static_cast<unsigned>(c.nblk * (EB / F::EW_A)));
+  hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER, FV, TILE>), grid, dim3(F::WG_A), 0, c.stream, a, X, int(forces));
+}
+
+// tile shapes other than the default are compiled for 3D one-order meshes of order 1 up
+template <int DIM, int ORDER, int FV> constexpr bool tiled() { return DIM == 3 && ORDER >= 1 && FV != FV_MORTAR; }
+
 template <typename T, int DIM, int ORDER, int FV>
-static hipError_t launch_stage_b(const LaunchCfg &c, int mode, int64_t ntiles, dim3 wgs, const KArgs<T> &a) {
-  auto go = [&](auto kern) {
-    const dim3 grid(static_cast<unsigned>(ntiles));
-    hipLaunchKernelGGL(kern, grid, wgs, 0, c.stream, a);
-  };
+static void launch_stage_a(const LaunchCfg &c, const KArgs<T> &a, const T *X, bool forces) {
+  if constexpr (tiled<DIM, ORDER, FV>()) {
+    switch (tile_a(c.variant_mask)) {
+      case TILE_HALF: return go_stage_a<T, DIM, ORDER, FV, TILE_HALF>(c, a, X, forces);
+      case TILE_QUARTER: return go_stage_a<T, DIM, ORDER, FV, TILE_QUARTER>(c, a, X, forces);
+      default: break;
+    }
+  }
+  go_stage_a<T, DIM, ORDER, FV, TILE_DEFAULT>(c, a, X, forces);
+}
+
+template <typename T, int DIM, int ORDER, int FV, int TILE>
+static hipError_t go_stage_b(const LaunchCfg &c, int mode, const KArgs<T> &a) {
+  using F = FS<T, DIM, ORDER, TILE>;
+  const dim3 grid(static_cast<unsigned>(c.nblk * (EB / F::EW_B))), wgs(F::WG_B);
+  auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, wgs, 0, c.stream, a); };
   switch (mode) {
-    case MODE_RK0: go(k_stage_b<T, DIM, ORDER, MODE_RK0, FV>); break;
-    case MODE_RK1: go(k_stage_b<T, DIM, ORDER, MODE_RK1, FV>); break;
-    case MODE_RK2: go(k_stage_b<T, DIM, ORDER, MODE_RK2, FV>); break;
-    case MODE_RK3: go(k_stage_b<T, DIM, ORDER, MODE_RK3, FV>); break;
-    case MODE_RESID: go(k_stage_b<T, DIM, ORDER, MODE_RESID, FV>); break;
+    case MODE_RK0: go(k_stage_b<T, DIM, ORDER, MODE_RK0, FV, TILE>); break;
+    case MODE_RK1: go(k_stage_b<T, DIM, ORDER, MODE_RK1, FV, TILE>); break;
+    case MODE_RK2: go(k_stage_b<T, DIM, ORDER, MODE_RK2, FV, TILE>); break;
+    case MODE_RK3: go(k_stage_b<T, DIM, ORDER, MODE_RK3, FV, TILE>); break;
+    case MODE_RESID: go(k_stage_b<T, DIM, ORDER, MODE_RESID, FV, TILE>); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T, int DIM, int ORDER, int FV>
+static hipError_t launch_stage_b(const LaunchCfg &c, int mode, const KArgs<T> &a) {
+  if constexpr (tiled<DIM, ORDER, FV>()) {
+    switch (tile_b(c.variant_mask)) {
+      case TILE_HALF: return go_stage_b<T, DIM, ORDER, FV, TILE_HALF>(c, mode, a);
+      case TILE_QUARTER: return go_stage_b<T, DIM, ORDER, FV, TILE_QUARTER>(c, mode, a);
+      default: break;
+    }
+  }
+  return go_stage_b<T, DIM, ORDER, FV, TILE_DEFAULT>(c, mode, a);
 }
 
 template <typename T, int DIM, int ORDER>
@@ -1833,32 +1880,22 @@ static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, i
         hipLaunchKernelGGL((k_visc<T, DIM, ORDER>), dim3((c.nblk * S::RTF + 3) / 4), blk, 0, c.stream, a,
                            int(forces));
       break;
-    case K_STAGE_A: {
-      const int64_t ntiles = c.nblk * (EB / FS<T, DIM, ORDER>::EW_A);
-      const dim3 wgs(FS<T, DIM, ORDER>::WG_A);
-      auto go = [&](auto kern) {
-        const dim3 grid(static_cast<unsigned>(ntiles));
-        hipLaunchKernelGGL(kern, grid, wgs, 0, c.stream, a, X, int(forces));
-      };
+    case K_STAGE_A:
       if (d.MO)
-        go(k_stage_a<T, DIM, ORDER, FV_MORTAR>);
+        launch_stage_a<T, DIM, ORDER, FV_MORTAR>(c, a, X, forces);
       else if (DIM == 3 && (c.variant_mask & EXTRUDED_METRICS) && d.XC)
-        go(k_stage_a<T, DIM, ORDER, DIM == 3 ? FV_EXTR : FV_STORED>);
+        launch_stage_a<T, DIM, ORDER, DIM == 3 ? FV_EXTR : FV_STORED>(c, a, X, forces);
       else if (DIM == 3 && !(c.variant_mask & STORED_METRICS))
-        go(k_stage_a<T, DIM, ORDER, DIM == 3 ? FV_NODE : FV_STORED>);
+        launch_stage_a<T, DIM, ORDER, DIM == 3 ? FV_NODE : FV_STORED>(c, a, X, forces);
       else
-        go(k_stage_a<T, DIM, ORDER, FV_STORED>);
+        launch_stage_a<T, DIM, ORDER, FV_STORED>(c, a, X, forces);
       break;
-    }
-    case K_STAGE_B: {
-      const int64_t ntiles = c.nblk * (EB / FS<T, DIM, ORDER>::EW_B);
-      const dim3 wgs(FS<T, DIM, ORDER>::WG_B);
-      if (d.MO) return launch_stage_b<T, DIM, ORDER, FV_MORTAR>(c, mode, ntiles, wgs, a);
+    case K_STAGE_B:
+      if (d.MO) return launch_stage_b<T, DIM, ORDER, FV_MORTAR>(c, mode, a);
       // the extruded first launch scales the half fluxes by the area factor like FV_NODE
       if (DIM == 3 && (((c.variant_mask & EXTRUDED_METRICS) && d.XC) || !(c.variant_mask & STORED_METRICS)))
-        return launch_stage_b<T, DIM, ORDER, DIM == 3 ? FV_NODE : FV_STORED>(c, mode, ntiles, wgs, a);
-      return launch_stage_b<T, DIM, ORDER, FV_STORED>(c, mode, ntiles, wgs, a);
-    }
+        return launch_stage_b<T, DIM, ORDER, DIM == 3 ? FV_NODE : FV_STORED>(c, mode, a);
+      return launch_stage_b<T, DIM, ORDER, FV_STORED>(c, mode, a);
     case K_DIVRK:
       if (tensor)
         hipLaunchKernelGGL((t_divrk<T, DIM, ORDER>), dim3(c.nblk * (EB / TT::EW_DIV)), blk, 0, c.stream, a, mode);
@@ -1881,32 +1918,68 @@ static hipError_t pack_t(const LaunchCfg &c, const DevArrays &d, bool to_dev, vo
   return hipGetLastError();
 }
 
-#define FR_DISPATCH(FN, ...)                                                              \
-  do {                                                                                    \
-    const int key = c.prec * 100 + c.dim * 10 + c.order;                                  \
-    switch (key) {                                                                        \
-      case 20: return FN<double, 2, 0>(__VA_ARGS__);                                      \
-      case 21: return FN<double, 2, 1>(__VA_ARGS__);                                      \
-      case 22: return FN<double, 2, 2>(__VA_ARGS__);                                      \
-      case 23: return FN<double, 2, 3>(__VA_ARGS__);                                      \
-      case 24: return FN<double, 2, 4>(__VA_ARGS__);                                      \
-      case 30: return FN<double, 3, 0>(__VA_ARGS__);                                      \
-      case 31: return FN<double, 3, 1>(__VA_ARGS__);                                      \
-      case 32: return FN<double, 3, 2>(__VA_ARGS__);                                      \
-      case 33: return FN<double, 3, 3>(__VA_ARGS__);                                      \
-      case 34: return FN<double, 3, 4>(__VA_ARGS__);                                      \
-      case 120: return FN<float, 2, 0>(__VA_ARGS__);                                      \
-      case 121: return FN<float, 2, 1>(__VA_ARGS__);                                      \
-      case 122: return FN<float, 2, 2>(__VA_ARGS__);                                      \
-      case 123: return FN<float, 2, 3>(__VA_ARGS__);                                      \
-      case 124: return FN<float, 2, 4>(__VA_ARGS__);                                      \
-      case 130: return FN<float, 3, 0>(__VA_ARGS__);                                      \
-      case 131: return FN<float, 3, 1>(__VA_ARGS__);                                      \
-      case 132: return FN<float, 3, 2>(__VA_ARGS__);                                      \
-      case 133: return FN<float, 3, 3>(__VA_ARGS__);                                      \
-      case 134: return FN<float, 3, 4>(__VA_ARGS__);                                      \
-      default: return hipErrorInvalidValue;                                               \
-    }                                                                                     \
+// The launchers are compiled in five parts, one object each, built in parallel: parts
+// 0-3 hold the kernels of one precision and dimension (0 FP64 2D, 1 FP64 3D, 2 FP32 2D,
+// 3 FP32 3D) for every order, part 4 the dispatch over them and the small kernels.
+#ifndef FR_PART
+#error "compile with -DFR_PART=0..4"
+#endif
+#define FR_CAT2(a, b) a##b
+#define FR_CAT(a, b) FR_CAT2(a, b)
+
+#if FR_PART < 4
+using PartT = typename std::conditional<(FR_PART >= 2), float, double>::type;
+constexpr int PART_DIM = (FR_PART & 1) ? 3 : 2;
+
+#define FR_ORDERS(FN, ...)                                \
+  do {                                                    \
+    switch (c.order) {                                    \
+      case 0: return FN<PartT, PART_DIM, 0>(__VA_ARGS__); \
+      case 1: return FN<PartT, PART_DIM, 1>(__VA_ARGS__); \
+      case 2: return FN<PartT, PART_DIM, 2>(__VA_ARGS__); \
+      case 3: return FN<PartT, PART_DIM, 3>(__VA_ARGS__); \
+      case 4: return FN<PartT, PART_DIM, 4>(__VA_ARGS__); \
+      default: return hipErrorInvalidValue;               \
+    }                                                     \
+  } while (0)
+
+hipError_t FR_CAT(launch_kernel_part, FR_PART)(int kernel, const LaunchCfg &c, const DevArrays &a, int stage,
+                                               int mode, bool forces) {
+  FR_ORDERS(launch_t, kernel, c, a, stage, mode, forces);
+}
+hipError_t FR_CAT(launch_pack_part, FR_PART)(const LaunchCfg &c, const DevArrays &a, bool to_dev, void *dst) {
+  FR_ORDERS(pack_t, c, a, to_dev, dst);
+}
+hipError_t FR_CAT(launch_probe_part, FR_PART)(const LaunchCfg &c, const DevArrays &a, int64_t n, const int64_t *slot,
+                                              const double *w, const int64_t *dst, double *out) {
+  FR_ORDERS(probe_t, c, a, n, slot, w, dst, out);
+}
+#else
+#define FR_PART_DECL(k)                                                                                         \
+  hipError_t launch_kernel_part##k(int, const LaunchCfg &, const DevArrays &, int, int, bool);                   \
+  hipError_t launch_pack_part##k(const LaunchCfg &, const DevArrays &, bool, void *);                           \
+  hipError_t launch_probe_part##k(const LaunchCfg &, const DevArrays &, int64_t, const int64_t *, const double *, \
+                                  const int64_t *, double *);
+FR_PART_DECL(0)
+FR_PART_DECL(1)
+FR_PART_DECL(2)
+FR_PART_DECL(3)
+
+// part holding the kernels of a launch configuration (precision 0 = FP64, 1 = FP32)
+static int part_of(const LaunchCfg &c) {
+  if ((c.prec != 0 && c.prec != 1) || (c.dim != 2 && c.dim != 3)) return -1;
+  return 2 * c.prec + (c.dim == 3 ? 1 : 0);
+}
+
+#define FR_PARTS(FN, ...)                       \
+  do {                                          \
+    switch (part_of(c)) {                       \
+      case 0: return FN##_part0(__VA_ARGS__);   \
+      case 1: return FN##_part1(__VA_ARGS__);   \
+      case 2: return FN##_part2(__VA_ARGS__);   \
+      case 3: return FN##_part3(__VA_ARGS__);   \
+      default: return hipErrorInvalidValue;     \
+    }                                           \
   } while (0)
 
 bool kernels_available(int prec, int dim, int order) {
@@ -1914,16 +1987,16 @@ bool kernels_available(int prec, int dim, int order) {
 }
 
 hipError_t launch_kernel(int kernel, const LaunchCfg &c, const DevArrays &a, int stage, int mode, bool forces) {
-  FR_DISPATCH(launch_t, kernel, c, a, stage, mode, forces);
+  FR_PARTS(launch_kernel, kernel, c, a, stage, mode, forces);
 }
 
 hipError_t launch_pack(const LaunchCfg &c, const DevArrays &a, bool to_dev, void *dst) {
-  FR_DISPATCH(pack_t, c, a, to_dev, dst);
+  FR_PARTS(launch_pack, c, a, to_dev, dst);
 }
 
 hipError_t launch_probe(const LaunchCfg &c, const DevArrays &a, int64_t n, const int64_t *slot, const double *w,
                         const int64_t *dst, double *out) {
-  FR_DISPATCH(probe_t, c, a, n, slot, w, dst, out);
+  FR_PARTS(launch_probe, c, a, n, slot, w, dst, out);
 }
 
 hipError_t launch_force_reduce(const LaunchCfg &c, const DevArrays &a) {
@@ -1935,5 +2008,6 @@ hipError_t launch_clear_flag(const LaunchCfg &c, const DevArrays &a) {
   hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, c.stream, a.flag);
   return hipGetLastError();
 }
+#endif
 
 }  // namespace fr

@@ -316,3 +316,44 @@ def test_pool_results_bit_identical_to_solo():
         assert np.array_equal(u, g.get_state())
         assert np.array_equal(out, g.forces())
     assert pool.usage() == (0, 0)
+
+
+# tile shapes of the fused stage (variant bits 9-10: first launch, 11-12: second launch;
+# 0 default, 1 half the elements per workgroup, 2 a quarter): only the split of the
+# elements over workgroups changes, not the arithmetic of any point, so every shape must
+# give the default's results bit for bit
+TILE_SHAPES = [(1, 0), (2, 0), (0, 1), (0, 2), (2, 2), (1, 1)]
+
+
+@pytest.mark.parametrize("name", ["tgv_p1", "tgv_p2", "tgv_p3_one", "tgv_p4", "airfoil_p2", "airfoil_p3",
+                                  "airfoil_p4"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("metrics", ["fused", "fused_stored", "fused_extruded"])
+def test_tile_shapes_bit_identical(name, prec, metrics):
+    m = case(name)
+    o = OracleMesh(m)
+    u = perturbed(o, m)
+    g = FRMesh(m, prec)
+    select(g, metrics)
+    r0 = g.residual(u)
+    g.set_state(u)
+    g.step(3)
+    s0, f0 = g.get_state(), g.forces()
+    for ta, tb in TILE_SHAPES:
+        g.select_kernels(VARIANTS[metrics] | (ta << 9) | (tb << 11))
+        r = g.residual(u)
+        g.set_state(u)
+        g.step(3)
+        assert np.array_equal(r, r0), (ta, tb)
+        assert np.array_equal(g.get_state(), s0), (ta, tb)
+        assert np.array_equal(g.forces(), f0, equal_nan=True), (ta, tb)  # NaN coefficients: no wall
+    print(f"{name} {prec} {metrics}: tiles {TILE_SHAPES} bit-identical to the default")
+    g.close()
+
+
+def test_tile_shapes_rejected_where_not_compiled():
+    g = FRMesh(case("vortex2d_p3"), "fp32")
+    with pytest.raises(_lib.FRError) as e:
+        g.select_kernels(VARIANTS["fused"] | (1 << 9))
+    assert e.value.code == _lib.FR_E_UNSUPPORTED
+    g.close()
