@@ -1819,7 +1819,7 @@ fr_status fr_select_kernels(fr_mesh *m, int32_t mask) {
     if ((unsigned(mask) & EXTRUDED_METRICS) && !m->extruded)
       fail(FR_E_UNSUPPORTED, "column metrics need a mesh of z-extruded elements");
     if ((unsigned(mask) & TILE_BITS) &&
-        (!tiles_compiled(m->dim, m->order, false) || tile_a(unsigned(mask)) >= N_TILES ||
+        (!tiles_compiled(m->dim, m->order, false) || tile_a(unsigned(mask)) >= N_TILES_A ||
          tile_b(unsigned(mask)) >= N_TILES))
       fail(FR_E_UNSUPPORTED, "tile shapes other than the default exist for 3D meshes of order 1 to 4 only");
     m->cfg.variant_mask = unsigned(mask) & (FUSED | (1u << K_INTERP) | (1u << K_GRAD) | (1u << K_VISC) |
@@ -1880,7 +1880,7 @@ fr_status fr_autotune(fr_mesh *m, int64_t steps, int32_t *mask_out) {
     if (tiles_compiled(m->dim, m->order, false)) {
       double best_a = 1e300, best_b = 1e300;
       int ta_best = 0, tb_best = 0;
-      for (int ta = 0; ta < N_TILES; ++ta) {
+      for (int ta = 0; ta < N_TILES_A; ++ta) {
         m->cfg.variant_mask = (fused_mask & ~TILE_BITS) | tile_bits(ta, 0);
         profile_steps(m, steps, ms_fused, n);
         hip_check(hipMemcpyAsync(m->a.U, m->a.RES, nb, hipMemcpyDeviceToDevice, m->stream), "restore state");

@@ -54,11 +54,13 @@ constexpr unsigned NO_XCD_REMAP = 1u << 7;
 // Fused stage on a mesh of z-extruded elements: metrics from the column data (XC, ZZ, FCX)
 constexpr unsigned EXTRUDED_METRICS = 1u << 8;
 // Tile shape of the fused stage's first launch (bits 9-10) and second launch (bits 11-12):
-// 0 the default workgroup, 1 half its elements, 2 a quarter (at least one). Compiled for
-// 3D one-order meshes of order 1 up; other meshes run the default.
+// 0 the default workgroup, 1 half its elements, 2 a quarter (at least one); for the first
+// launch also 3, the default workgroup with the reference gradient and the volume
+// divergence on the matrix cores (FP32 at order 3; elsewhere it runs the default).
+// Compiled for 3D one-order meshes of order 1 up; other meshes run the default.
 constexpr int TILE_A_SHIFT = 9, TILE_B_SHIFT = 11;
 constexpr unsigned TILE_BITS = (3u << TILE_A_SHIFT) | (3u << TILE_B_SHIFT);
-constexpr int N_TILES = 3;
+constexpr int N_TILES = 3, N_TILES_A = 4;
 inline int tile_a(unsigned mask) { return int((mask >> TILE_A_SHIFT) & 3u); }
 inline int tile_b(unsigned mask) { return int((mask >> TILE_B_SHIFT) & 3u); }
 inline unsigned tile_bits(int ta, int tb) { return (unsigned(ta) << TILE_A_SHIFT) | (unsigned(tb) << TILE_B_SHIFT); }

@@ -980,8 +980,11 @@ enum { FV_NODE = 0, FV_STORED = 1, FV_MORTAR = 2, FV_EXTR = 3 };
 // Tile shapes of the fused stage, one per launch (picked by the autotuner): TILE_DEFAULT
 // sizes the workgroup from the LDS budgets below; TILE_HALF and TILE_QUARTER give it a
 // half or a quarter of those elements (at least one): smaller workgroups, more of them
-// per compute unit, each waiting at its barriers for fewer waves.
-enum { TILE_DEFAULT = 0, TILE_HALF = 1, TILE_QUARTER = 2 };
+// per compute unit, each waiting at its barriers for fewer waves. TILE_MFMA (first launch
+// only) is the default workgroup with the reference gradient and the volume divergence
+// on the matrix cores (FP32 at order 3) instead of the vector ALUs; the same fused
+// multiply-adds in the same order, so the same results bit for bit.
+enum { TILE_DEFAULT = 0, TILE_HALF = 1, TILE_QUARTER = 2, TILE_MFMA = 3 };
 
 template <typename T, int DIM, int ORDER, int TILE = TILE_DEFAULT> struct FS {
   using S = Shape<DIM, ORDER>;
@@ -989,8 +992,9 @@ template <typename T, int DIM, int ORDER, int TILE = TILE_DEFAULT> struct FS {
     return bytes * 16 <= budget ? 16 : bytes * 8 <= budget ? 8 : bytes * 4 <= budget ? 4 : bytes * 2 <= budget ? 2 : 1;
   }
   static constexpr int ew(int bytes, int budget) {
-    return TILE == TILE_DEFAULT ? ew0(bytes, budget)
-                                : (ew0(bytes, budget) >> TILE) > 0 ? ew0(bytes, budget) >> TILE : 1;
+    return TILE == TILE_DEFAULT || TILE == TILE_MFMA ? ew0(bytes, budget)
+           : (ew0(bytes, budget) >> TILE) > 0        ? ew0(bytes, budget) >> TILE
+                                                     : 1;
   }
   // stage a: max(state + jumps, gradient + transformed flux) per element (aliased)
   static constexpr int LDS_A_ELEM = (S::NU * S::NV + S::NF * S::NV) > 2 * S::NU * S::NG
@@ -1047,6 +1051,10 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   constexpr bool NODEM = NM::ON;
   constexpr bool EXTR = DIM == 3 && FV == FV_EXTR;
   constexpr bool SCALED = NODEM || EXTR;  // Q and P stored times the area factor
+  // the matrix-core tile: FP32 at p = 3 with 4 elements per workgroup of 4 waves (node
+  // metrics keep their geometry passes in the LDS the gradient pass reuses)
+  constexpr bool MFG =
+      sizeof(T) == 4 && DIM == 3 && ORDER == 3 && !NODEM && TILE == TILE_MFMA && F::EW_A == 4 && F::WG_A == 256;
   constexpr int NCOL = S::N * S::N, NFC = 4 * S::N + S::N * S::N;
   constexpr int EW = F::EW_A, WG = F::WG_A, NS = EB / EW, N = S::N, NV = S::NV, NG = S::NG;
   constexpr int FI = (S::NF * EW + WG - 1) / WG, PI = (S::NU * EW + WG - 1) / WG;
@@ -1220,10 +1228,10 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       sk[1] = k == 0 ? -(u * z) : (k == 1 ? z * u : 0.0);
       sk[2] = k == 2 ? u : 0.0;
       const double area = sqrt(sk[0] * sk[0] + sk[1] * sk[1] + sk[2] * sk[2]);
-      const double sg = (f & 1) ? 1.0 : -1.0;
+      const double ia = ((f & 1) ? 1.0 : -1.0) / area;
       Av[it] = area;
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) nrd[it][c] = sg * sk[c] / area;
+      for (int c = 0; c < DIM; ++c) nrd[it][c] = sk[c] * ia;
     }
   }
 #pragma unroll
@@ -1285,6 +1293,47 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   // with node metrics also S and 1/|J| from pass B's outputs, still intact above the
   // state and jumps
   T Gr[PI][DIM][NV], ui[PI][NV];
+  if constexpr (MFG) {
+    // On the matrix cores: for axis k and variable v, the 16 solution-point lines along k
+    // of the 4 elements are the 16 blocks of one v_mfma_f32_4x4x1 chain (block = line,
+    // its 4 columns = the elements, its 4 rows = the points of the line). Six rank-1 steps
+    // accumulate G = D u + g_R' (u_c - u_f)_+ + g_L' (u_c - u_f)_-; the A operand is the
+    // basis column (lane = 4 line + row), the B operand the line's value of each element
+    // (lane = 4 line + element). Lane 4 m + e then holds G_k at the 4 points of line m of
+    // element e, which it writes to the flux region of LDS (free until the transformed
+    // flux overwrites it point by point); each thread reads back its own point's 15
+    // channels after the barrier. Waves take the 15 (k, v) pairs in turn.
+    const int lane = tid & 63, wave = tid >> 6, ml = lane >> 2, el = lane & 3;
+    T ad[N], agr = B.gr[el], agl = B.gl[el];
+#pragma unroll
+    for (int j = 0; j < N; ++j) ad[j] = B.D[el][j];
+    T *Gref = L + S::NU * NG * EW;
+#pragma unroll
+    for (int sk = 0; sk < (NG + 3) / 4; ++sk) {
+      const int tk = wave + 4 * sk;
+      if (tk >= NG) break;  // wave-uniform: every lane of the wave runs the chain
+      const int k = tk / NV, v = tk % NV;
+      int base, stride;
+      Ref<DIM, N>::line_of(k, ml, base, stride);
+      const T *ul = Us + (base * NV + v) * EW + el;
+      floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < N; ++j) c = __builtin_amdgcn_mfma_f32_4x4x1f32(ad[j], ul[j * stride * NV * EW], c, 0, 0, 0);
+      const int qp = (2 * k + 1) * S::NFP + ml, qm = 2 * k * S::NFP + ml;
+      c = __builtin_amdgcn_mfma_f32_4x4x1f32(agr, Ds[(qp * NV + v) * EW + el], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_4x4x1f32(agl, Ds[(qm * NV + v) * EW + el], c, 0, 0, 0);
+      T *gl = Gref + (base * NG + tk) * EW + el;
+#pragma unroll
+      for (int r = 0; r < N; ++r) gl[r * stride * NG * EW] = c[r];
+    }
+#pragma unroll
+    for (int it = 0; it < PI; ++it) {
+      const int t = tid + it * WG, e = t % EW, i = t / EW;
+      if (t >= S::NU * EW) break;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ui[it][v] = Us[(i * NV + v) * EW + e];
+    }
+  } else {
 #pragma unroll
   for (int it = 0; it < PI; ++it) {
     const int t = tid + it * WG, e = t % EW, i = t / EW;
@@ -1307,13 +1356,16 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       const int qp = (2 * k + 1) * S::NFP + m, qm = 2 * k * S::NFP + m;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
+        // one fused multiply-add per term, in the order of the matrix-core chain
         T sv = 0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) sv += B.D[ik][j] * Us[(Ref<DIM, N>::line(k, m, j) * NV + v) * EW + e];
-        sv += B.gr[ik] * Ds[(qp * NV + v) * EW + e] + B.gl[ik] * Ds[(qm * NV + v) * EW + e];
+        for (int j = 0; j < N; ++j) sv = fma(B.D[ik][j], Us[(Ref<DIM, N>::line(k, m, j) * NV + v) * EW + e], sv);
+        sv = fma(B.gr[ik], Ds[(qp * NV + v) * EW + e], sv);
+        sv = fma(B.gl[ik], Ds[(qm * NV + v) * EW + e], sv);
         Gr[it][k][v] = sv;
       }
     }
+  }
   }
   __syncthreads();
   // physical gradient and transformed flux into the aliased LDS
@@ -1321,6 +1373,14 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   for (int it = 0; it < PI; ++it) {
     const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
     if (t >= S::NU * EW) break;
+    if constexpr (MFG) {
+      // this point's reference gradient from the matrix-core pass (before this thread's
+      // transformed flux overwrites the same words)
+#pragma unroll
+      for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Gr[it][k][v] = L[S::NU * NG * EW + (i * NG + k * NV + v) * EW + e];
+    }
     if constexpr (EXTR) {
       // S = |J| J^-1 by rows (a_{k+1} x a_{k+2}) and |J| = a_0 . S_0 for
       // a_0 = (x_xi, y_xi, 0), a_1 = (x_eta, y_eta, 0), a_2 = (0, 0, z_zeta)
@@ -1341,7 +1401,14 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       for (int c = 0; c < NG; ++c) Gs[(i * NG + c) * EW + e] = Fs[(i * NG + c) * EW + e] = 0;
       continue;
     }
+    // physical gradient S^T G / |J|; with column metrics the five nonzero entries of S
+    // are divided by |J| once per point (FP64), elsewhere each sum is
     T gu[DIM][NV];
+    double Mj[DIM][DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) Mj[k][c] = EXTR ? Sm[it][k][c] * ijv[it] : Sm[it][k][c];
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
 #pragma unroll
@@ -1350,9 +1417,9 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
           if (EXTR && (k == 2) != (c == 2)) continue;  // zero in the block form of S
-          sg += Sm[it][k][c] * double(Gr[it][k][v]);
+          sg += Mj[k][c] * double(Gr[it][k][v]);
         }
-        gu[c][v] = T(sg * ijv[it]);
+        gu[c][v] = T(EXTR ? sg : sg * ijv[it]);
         Gs[(i * NG + c * NV + v) * EW + e] = gu[c][v];
       }
     T Fi[DIM][NV], Fv[DIM][NV];
@@ -1440,6 +1507,59 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   }
 
   // ---- solution points: volume divergence with the interpolated normal-flux correction
+  if constexpr (MFG) {
+    // On the matrix cores, as the gradient: for axis k and variable v, the lines along k
+    // of the 4 elements are the 16 blocks of a v_mfma_f32_4x4x1 chain over the 4 points
+    // of each line, A = the rows of Dv. The per-axis parts wait in registers until every
+    // wave has read its last gradient trace, then go to the gradient's LDS; each thread
+    // sums its own point's three in axis order after the second barrier.
+    const int lane = tid & 63, wave = tid >> 6, ml = lane >> 2, el = lane & 3;
+    T av[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) av[j] = B.Dv[el][j];
+    constexpr int NT = (NG + 3) / 4;
+    floatx4 cd[NT];
+#pragma unroll
+    for (int sk = 0; sk < NT; ++sk) {
+      const int tk = wave + 4 * sk;
+      cd[sk] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if (tk >= NG) break;  // wave-uniform
+      int base, stride;
+      Ref<DIM, N>::line_of(tk / NV, ml, base, stride);
+      const T *fl = Fs + (base * NG + tk) * EW + el;
+#pragma unroll
+      for (int j = 0; j < N; ++j) cd[sk] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[j], fl[j * stride * NG * EW], cd[sk], 0, 0, 0);
+    }
+    __syncthreads();
+    // per-axis parts [axis][point][variable][element] over the gradient's LDS
+    T *Pk = Gs;
+#pragma unroll
+    for (int sk = 0; sk < NT; ++sk) {
+      const int tk = wave + 4 * sk;
+      if (tk >= NG) break;
+      const int k = tk / NV, v = tk % NV;
+      int base, stride;
+      Ref<DIM, N>::line_of(k, ml, base, stride);
+      T *pl = Pk + ((k * S::NU + base) * NV + v) * EW + el;
+#pragma unroll
+      for (int r = 0; r < N; ++r) pl[r * stride * NV * EW] = cd[sk][r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < PI; ++it) {
+      const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
+      if (t >= S::NU * EW) break;
+      if (eg >= nvalid) continue;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T div = 0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) div += Pk[((k * S::NU + i) * NV + v) * EW + e];
+        a.FT[at(blk, i, v, eg, S::NUP, NV)] = div;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int it = 0; it < PI; ++it) {
     const int t = tid + it * WG, e = t % EW, i = t / EW, eg = e0 + e;
@@ -1454,9 +1574,10 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       Ref<DIM, N>::locate(i, k, ik, m);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
+        // one fused multiply-add per term, in the order of the matrix-core chain
         T d = 0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) d += B.Dv[ik][j] * Fs[(Ref<DIM, N>::line(k, m, j) * NG + k * NV + v) * EW + e];
+        for (int j = 0; j < N; ++j) d = fma(B.Dv[ik][j], Fs[(Ref<DIM, N>::line(k, m, j) * NG + k * NV + v) * EW + e], d);
         div[v] += d;
       }
     }
@@ -1811,6 +1932,9 @@ static void launch_stage_a(const LaunchCfg &c, const KArgs<T> &a, const T *X, bo
     switch (tile_a(c.variant_mask)) {
       case TILE_HALF: return go_stage_a<T, DIM, ORDER, FV, TILE_HALF>(c, a, X, forces);
       case TILE_QUARTER: return go_stage_a<T, DIM, ORDER, FV, TILE_QUARTER>(c, a, X, forces);
+      case TILE_MFMA:
+        if constexpr (sizeof(T) == 4 && ORDER == 3) return go_stage_a<T, DIM, ORDER, FV, TILE_MFMA>(c, a, X, forces);
+        break;
       default: break;
     }
   }
