@@ -542,6 +542,29 @@ def bench_serve(args):
         clock = max(clock, arrival[i]) + dof[i] * steps / rate64[trace[i]["order"]]
         lat64.append(clock - arrival[i])
     lat64 = np.array(lat64)
+    serial_run = None
+    if args.serial_run:
+        # the same trace served FIFO one request at a time on the plain FP64 path (autotuned
+        # kernels, a fresh solver per request), in real time against the arrival clock
+        t0s = time.perf_counter()
+        done64 = []
+        for i in range(len(trace)):
+            while time.perf_counter() - t0s < arrival[i]:
+                time.sleep(0.001)
+            g = FRMesh(meshes[i], "fp64")
+            fs = meshes[i]["freestream"]
+            g.set_state(W.uniform_state(g.E * g.nu, fs[0], fs[1:4], fs[4]).reshape(g.shape))
+            g.step(steps)
+            g.forces()
+            g.close()
+            done64.append(time.perf_counter() - t0s)
+            progress(f"serial fp64 request {i + 1}/{len(trace)} done")
+        lat_s = np.array([done64[i] - arrival[i] for i in range(len(trace))])
+        serial_run = {"latency_p50_s": round(float(np.percentile(lat_s, 50)), 3),
+                      "latency_p99_s": round(float(np.percentile(lat_s, 99)), 3),
+                      "makespan_s": round(done64[-1], 3),
+                      "dof_updates_per_s": round(total / done64[-1], 1),
+                      "note": "run: FIFO one request at a time, plain FP64 path, same requests and arrivals"}
     res = {
         "metric": "served airfoil solves: p50/p99 latency (arrival to result) and aggregate DOF-updates/s",
         "value": round(total / makespan, 1), "unit": "DOF-updates/s", "n_gpus": 1, "steps": steps,
@@ -566,6 +589,8 @@ def bench_serve(args):
                                  "note": "not run: FIFO one-at-a-time service at the measured FP64 rates of "
                                          "the autotuned kernels (the main line's FP64 path)"},
         "modelled_speedup_vs_serial_fp64": round(clock / makespan, 3),
+        "serial_fp64_run": serial_run,
+        "speedup_vs_serial_fp64_run": None if serial_run is None else round(serial_run["makespan_s"] / makespan, 3),
     }
     print(json.dumps(res))
 
@@ -867,6 +892,8 @@ def main():
     ap.add_argument("--requests", type=int, default=64, help="serve: requests in the trace")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: mean arrivals per second")
     ap.add_argument("--budget-gb", type=float, default=96.0, help="serve: HBM budget of the pool")
+    ap.add_argument("--serial-run", action="store_true",
+                    help="serve: also run the same trace FIFO one request at a time on the plain FP64 path")
     ap.add_argument("--active-elements", type=int, default=150000,
                     help="serve: admit while the running requests hold fewer elements than this")
     ap.add_argument("--cpu-steps", type=int, default=None, help="oracle sample (steps)")
