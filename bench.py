@@ -27,7 +27,8 @@ sample (the smallest design for 100 steps).
 Other workloads: ``tgv`` (Taylor-Green 24^3 straight hexes, p = 3) and ``airfoil``
 (one 160x48x8 O-grid) alone; ``serve``: a Poisson stream of airfoil solve requests
 (mean 4/s, order 2..4, 500 steps each) through the request pool (p50/p99 latency
-from arrival to result, aggregate DOF-updates/s); ``pmix``: the airfoil grid with the
+from arrival to result, aggregate DOF-updates/s; ``--serial-run`` also serves the same trace
+FIFO, one request at a time, on the plain FP64 path); ``pmix``: the airfoil grid with the
 order falling from 3 at the wall to 0 toward the far field (variable order); ``fwh``:
 the far-field acoustic sum.
 """
@@ -72,13 +73,14 @@ def per_element_cost(dim, order, real_bytes, metrics="stored"):
     nf = 2 * dim * n ** (dim - 1)
     nv = dim + 2
     s = real_bytes
-    # metric bytes of the fused stage's first launch and its second (areas only when stored)
+    # metric bytes of the fused stage's first launch and its second (areas only when stored;
+    # 1/|J| per solution point, or from the column and layer factors on extruded meshes)
     if dim == 3 and metrics == "extruded":
-        met_a, area_b = (4 * n * n + n + 2 * (4 * n + n * n)) * 8, 0
+        met_a, area_b, ij_b = (4 * n * n + n + 2 * (4 * n + n * n)) * 8, 0, (n * n + n) * 8
     elif dim == 3 and metrics == "node":
-        met_a, area_b = 27 * 3 * 8, 0
+        met_a, area_b, ij_b = 27 * 3 * 8, 0, nu * 8
     else:
-        met_a, area_b = nf * dim * 8 + nu * (dim * dim + 1) * 8, nf * 8
+        met_a, area_b, ij_b = nf * dim * 8 + nu * (dim * dim + 1) * 8, nf * 8, nu * 8
     cost = {
         1: dict(flops=0, bytes=(2 * nf * nv * s + nf * dim * 8 + nf * 4) + 2 * nf * nv * s),
         2: dict(flops=2 * nv * (dim * nu * nu + dim * nu * nf),
@@ -92,11 +94,11 @@ def per_element_cost(dim, order, real_bytes, metrics="stored"):
         # fused stage a: stage state, partner traces, neighbour codes and the metric source
         # in; Q, P and the volume divergence out
         6: dict(flops=0, bytes=nu * nv * s + nf * nv * s + nf * 4 + met_a + 2 * nf * nv * s + nu * nv * s),
-        # fused stage b: Q, partner P, codes, areas (stored metrics only), divergence, 1/|J|,
+        # fused stage b: Q, partner P, per-face codes, areas (stored metrics only), divergence, 1/|J|,
         # u_n and acc in; acc, next stage state and its trace out; the first stage reads no
         # acc and the last writes none, so acc counts 3/4 each way (mean over the four RK
         # stages)
-        7: dict(flops=0, bytes=2 * nf * nv * s + nf * 4 + area_b + nu * nv * s + nu * 8
+        7: dict(flops=0, bytes=2 * nf * nv * s + 2 * dim * 4 + area_b + nu * nv * s + ij_b
                 + 1.75 * nu * nv * s + 1.75 * nu * nv * s + nf * nv * s),
     }
     return cost, nu * nv

@@ -786,7 +786,8 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
   M->extruded = extruded;
   const int ncol = D.n * D.n, nfc = 4 * D.n + D.n * D.n;
   std::vector<double> XC(extruded ? size_t(NB) * ncol * 4 * EB : 0, 0.0), ZZ(extruded ? size_t(NB) * D.n * EB : 0, 1.0),
-      FCX(extruded ? size_t(NB) * nfc * 2 * EB : 0, 0.0);
+      FCX(extruded ? size_t(NB) * nfc * 2 * EB : 0, 0.0), IJC(extruded ? size_t(NB) * ncol * EB : 0, 1.0),
+      IZ(extruded ? size_t(NB) * D.n * EB : 0, 1.0);
   if (extruded)
     for (int64_t blk = 0; blk < NB; ++blk)
       for (int sl = 0; sl < EB; ++sl) {
@@ -864,9 +865,13 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
             extruded_jacobian(descs[di], e, gl.x[size_t(i0)], gl.x[size_t(i1)], jc);
             for (int c = 0; c < 4; ++c) XC[lay(blk, i0 + D.n * i1, c, s, ncol, 4)] = jc[c];
             FCX[lay(blk, 4 * D.n + i0 + D.n * i1, 0, s, nfc, 2)] = jc[0] * jc[3] - jc[2] * jc[1];
+            IJC[lay(blk, i0 + D.n * i1, 0, s, ncol, 1)] = 1.0 / (jc[0] * jc[3] - jc[2] * jc[1]);
             FCX[lay(blk, 4 * D.n + i0 + D.n * i1, 1, s, nfc, 2)] = 0.0;
           }
-        for (int i2 = 0; i2 < D.n; ++i2) ZZ[lay(blk, i2, 0, s, D.n, 1)] = extruded_zzeta(descs[di], e, gl.x[size_t(i2)]);
+        for (int i2 = 0; i2 < D.n; ++i2) {
+          ZZ[lay(blk, i2, 0, s, D.n, 1)] = extruded_zzeta(descs[di], e, gl.x[size_t(i2)]);
+          IZ[lay(blk, i2, 0, s, D.n, 1)] = 1.0 / ZZ[lay(blk, i2, 0, s, D.n, 1)];
+        }
         for (int sd = 0; sd < 2; ++sd)
           for (int m = 0; m < D.n; ++m) {
             double jc[4];
@@ -911,6 +916,62 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
     });
   }
   wall_first[nd] = M->nwall;
+  // per-face neighbour codes from the per-point ones (one-order meshes): every point of a
+  // matched face must name the same partner element and face, through one symmetry of the
+  // square; a boundary face one kind, its wall points numbered on from the first. Any
+  // other face leaves the mesh on the per-point codes.
+  std::vector<int> NBFt;
+  if (!mm) {
+    const int nfc = 2 * dim, nfp = D.nfp;
+    NBFt.assign(size_t(NB) * nfc * EB, 0);
+    bool ok = true;
+    for (int64_t blk = 0; blk < NB && ok; ++blk)
+      for (int sl = 0; sl < bcount[size_t(blk)] && ok; ++sl)
+        for (int f = 0; f < nfc && ok; ++f) {
+          const int c0 = NBt[lay(blk, f * nfp, 0, sl, NFPAD, 1)];
+          int code = c0;
+          if (c0 < 0) {
+            for (int m = 1; m < nfp && ok; ++m) {
+              const int c = NBt[lay(blk, f * nfp + m, 0, sl, NFPAD, 1)];
+              const int want = ((-c0) & 3) == FR_BC_WALL ? -(((-c0) & 3) | ((((-c0) >> 2) + m) << 2)) : c0;
+              ok = c == want;
+            }
+          } else {
+            // decode the partner of point 0: c0 = lay(pblk, q', 0, pslot, NFPAD, 1)
+            const int64_t cs = c0 / SB, ps_blk = cs / (int64_t(NSB) * NFPAD);
+            const int pq = int((cs / 1) % (int64_t(NSB) * NFPAD) % NFPAD);
+            const int psl = int(((cs % (int64_t(NSB) * NFPAD)) / NFPAD) * SB + c0 % SB);
+            const int pf = pq / nfp;
+            int map = -1;
+            for (int o = 0; o < (dim == 2 ? 2 : 8) && map < 0; ++o) {
+              bool all = true;
+              for (int m = 0; m < nfp && all; ++m)
+                all = NBt[lay(blk, f * nfp + m, 0, sl, NFPAD, 1)] ==
+                      int(lay(ps_blk, pf * nfp + face_map(m, o, D.n, dim), 0, psl, NFPAD, 1));
+              if (all) map = o;
+            }
+            ok = map >= 0 && (ps_blk * EB + psl) < (int64_t(1) << 25);
+            code = int((((ps_blk * EB + psl) << 3) | pf) << 3 | map);
+          }
+          NBFt[lay(blk, f, 0, sl, nfc, 1)] = code;
+        }
+    // the decoding the kernels apply must give back every per-point code
+    for (int64_t blk = 0; blk < NB && ok; ++blk)
+      for (int sl = 0; sl < bcount[size_t(blk)] && ok; ++sl)
+        for (int q = 0; q < nf && ok; ++q) {
+          const int fc = NBFt[lay(blk, q / nfp, 0, sl, nfc, 1)], m = q % nfp;
+          int c;
+          if (fc < 0) {
+            const int kind = (-fc) & 3;
+            c = kind == FR_BC_WALL ? -(kind | ((((-fc) >> 2) + m) << 2)) : fc;
+          } else {
+            const int ps = fc >> 6, pf = (fc >> 3) & 7;
+            c = int(lay(ps / EB, pf * nfp + face_map(m, fc & 7, D.n, dim), 0, ps % EB, NFPAD, 1));
+          }
+          ok = c == NBt[lay(blk, q, 0, sl, NFPAD, 1)];
+        }
+    if (!ok) NBFt.clear();
+  }
   // operators
   Operators op(dim, M->order);
   const int RTU = NUP / 16, RTF = NFPAD / 16, KTU = D.ku / 4, KTF = D.kf / 4;
@@ -960,10 +1021,13 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
   a.FN = M->upload(FN);
   a.FA = M->upload(FA);
   a.NB = M->upload(NBt);
+  if (!NBFt.empty()) a.NBF = M->upload(NBFt);
   if (extruded) {
     a.XC = M->upload(XC);
     a.ZZ = M->upload(ZZ);
     a.FCX = M->upload(FCX);
+    a.IJC = M->upload(IJC);
+    a.IZ = M->upload(IZ);
   }
   if (dim == 3) {
     a.XN = M->upload(XN);
@@ -1822,9 +1886,11 @@ fr_status fr_select_kernels(fr_mesh *m, int32_t mask) {
         (!tiles_compiled(m->dim, m->order, false) || tile_a(unsigned(mask)) >= N_TILES_A ||
          tile_b(unsigned(mask)) >= N_TILES))
       fail(FR_E_UNSUPPORTED, "tile shapes other than the default exist for 3D meshes of order 1 to 4 only");
+    if ((unsigned(mask) & SCATTER_EXCHANGE) && !(unsigned(mask) & FUSED))
+      fail(FR_E_UNSUPPORTED, "the exchange by scatter belongs to the fused stage");
     m->cfg.variant_mask = unsigned(mask) & (FUSED | (1u << K_INTERP) | (1u << K_GRAD) | (1u << K_VISC) |
                                             (1u << K_DIVRK) | STORED_METRICS | NO_XCD_REMAP | EXTRUDED_METRICS |
-                                            TILE_BITS);
+                                            TILE_BITS | SCATTER_EXCHANGE);
     drop_graphs(m);
   });
 }
@@ -1857,14 +1923,15 @@ fr_status fr_autotune(fr_mesh *m, int64_t steps, int32_t *mask_out) {
     m->cfg.variant_mask = all;
     profile_steps(m, steps, ms_tensor, n);
     hip_check(hipMemcpyAsync(m->a.U, m->a.RES, nb, hipMemcpyDeviceToDevice, m->stream), "restore state");
-    // the fused stage: in 3D with metrics from the nodes or stored, each with the tiles
-    // of consecutive blocks remapped onto one XCD or not
+    // the fused stage: in 3D with each metric source the mesh allows, each with the tiles
+    // of consecutive blocks remapped onto one XCD or not, and the neighbour exchange by
+    // gather or by scatter
     double fused = 1e300;
     unsigned fused_mask = FUSED | (1u << K_INTERP);
     for (unsigned metrics : {0u, STORED_METRICS, EXTRUDED_METRICS}) {
       if (metrics && m->dim != 3) continue;
       if (metrics == EXTRUDED_METRICS && !m->extruded) continue;
-      for (unsigned shape : {0u, NO_XCD_REMAP}) {
+      for (unsigned shape : {0u, NO_XCD_REMAP, SCATTER_EXCHANGE, NO_XCD_REMAP | SCATTER_EXCHANGE}) {
         m->cfg.variant_mask = FUSED | (1u << K_INTERP) | metrics | shape;
         profile_steps(m, steps, ms_fused, n);
         hip_check(hipMemcpyAsync(m->a.U, m->a.RES, nb, hipMemcpyDeviceToDevice, m->stream), "restore state");

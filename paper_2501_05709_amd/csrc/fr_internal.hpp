@@ -61,10 +61,29 @@ constexpr unsigned EXTRUDED_METRICS = 1u << 8;
 constexpr int TILE_A_SHIFT = 9, TILE_B_SHIFT = 11;
 constexpr unsigned TILE_BITS = (3u << TILE_A_SHIFT) | (3u << TILE_B_SHIFT);
 constexpr int N_TILES = 3, N_TILES_A = 4;
+// Neighbour exchange of the fused stage by scatter: each trace and viscous half flux is
+// written into the partner's slot and read from the own slot (one-order meshes; mortar
+// faces keep the gather through the neighbour codes)
+constexpr unsigned SCATTER_EXCHANGE = 1u << 13;
 inline int tile_a(unsigned mask) { return int((mask >> TILE_A_SHIFT) & 3u); }
 inline int tile_b(unsigned mask) { return int((mask >> TILE_B_SHIFT) & 3u); }
 inline unsigned tile_bits(int ta, int tb) { return (unsigned(ta) << TILE_A_SHIFT) | (unsigned(tb) << TILE_B_SHIFT); }
 inline bool tiles_compiled(int dim, int order, bool mixed) { return dim == 3 && order >= 1 && !mixed; }
+// Face-point map of a per-face neighbour code (host and device): point m of a face with n
+// points per line goes to the partner face's point face_map(m); in 3D m = a + n b, the map
+// bits are 4 swap (a, b), 1 reverse a, 2 reverse b; on the lines of 2D faces only bit 1.
+__host__ __device__ inline int face_map(int m, int map, int n, int dim) {
+  if (dim == 2) return (map & 1) ? n - 1 - m : m;
+  int a = m % n, b = m / n;
+  if (map & 4) {
+    const int t = a;
+    a = b;
+    b = t;
+  }
+  if (map & 1) a = n - 1 - a;
+  if (map & 2) b = n - 1 - b;
+  return a + n * b;
+}
 
 // Modes of K_DIVRK
 enum { MODE_RK0 = 0, MODE_RK1 = 1, MODE_RK2 = 2, MODE_RK3 = 3, MODE_RESID = 4 };
@@ -83,6 +102,11 @@ struct DevArrays {
   double *FN = nullptr;  // NFPAD points, dim channels: outward unit normal
   double *FA = nullptr;  // NFPAD points, 1 channel: |S^T n_hat|
   int *NB = nullptr;     // NFPAD points, 1 channel: partner lay(blk, q, 0, slot, NFPAD, 1), or boundary code
+  // the same per face (2 dim faces, 1 channel), for one-order meshes whose matched faces
+  // all map their points by one of the 8 symmetries of the square (null otherwise): an
+  // interior face holds ((partner block * EB + slot) << 6) | (partner face << 3) | map, a
+  // boundary face the per-point code of its first point (wall points number on from it)
+  int *NBF = nullptr;
   // 3D: the element map as 27 triquadratic nodes (lay: 27 points, 3 channels), from which
   // the fused stage forms its metrics, and the quadratic basis and its derivative at the
   // Gauss-Legendre points, GQ[(kind * 3 + a) * n + i] (kind 0: l_a, 1: l_a')
@@ -95,6 +119,9 @@ struct DevArrays {
   // point m: s n + m), (x_xi, y_xi) on the eta faces (2n + s n + m), the 2D Jacobian
   // determinant of the zeta faces' columns (4n + column)
   double *XC = nullptr, *ZZ = nullptr, *FCX = nullptr;
+  // extruded meshes: 1/|J| = IJC[column] IZ[layer], the reciprocal 2D Jacobian determinant
+  // of the n^2 solution-point columns and the reciprocal z_zeta of the n layers
+  double *IJC = nullptr, *IZ = nullptr;
   int *bcount = nullptr;   // [blk] valid elements in the block
   int *bdesign = nullptr;  // [blk]
   int64_t *bcanon = nullptr;  // [blk] canonical element index of slot 0

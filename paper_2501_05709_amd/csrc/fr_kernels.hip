@@ -77,8 +77,9 @@ template <typename T> struct KArgs {
   const double *SM, *IJ, *FN, *FA, *bdt, *fsd, *wface;
   const double *XN, *GQ;
   const double *XC, *ZZ, *FCX;
+  const double *IJC, *IZ;
   double *FC, *fsum, *stage64;
-  const int *NB, *bcount, *bdesign;
+  const int *NB, *NBF, *bcount, *bdesign;
   const int64_t *bcanon, *wall_first;
   int *flag;
   const int *MO, *MG, *MC;
@@ -89,7 +90,8 @@ template <typename T> struct KArgs {
   const double *PW;
   int64_t nblk, n_canon;
   int ndesign;
-  int xcd;  // fused stage: map consecutive tiles to one XCD
+  int xcd;      // fused stage: map consecutive tiles to one XCD
+  int scatter;  // trace interpolation: write each trace into its partner's slot
   T gam, mu, kappa;
 };
 
@@ -804,7 +806,13 @@ __global__ __launch_bounds__(256) void t_interp(KArgs<T> a, const T *__restrict_
       T s = 0;
 #pragma unroll
       for (int j = 0; j < N; ++j) s += l[j] * Us[(Ref<DIM, N>::line(k, m, j) * S::NV + v) * EW + e];
-      a.UF[at(blk, q, v, e0 + e, S::NFPAD, S::NV)] = s;
+      if (a.scatter) {
+        // exchange by scatter: into the partner's slot (a boundary point has none)
+        const int nb = a.NB[lay(blk, q, 0, e0 + e, S::NFPAD, 1)];
+        if (nb >= 0) a.UF[size_t(nb / SB) * S::NV * SB + (nb % SB) + v * SB] = s;
+      } else {
+        a.UF[at(blk, q, v, e0 + e, S::NFPAD, S::NV)] = s;
+      }
     }
   }
 }
@@ -970,6 +978,26 @@ __device__ inline void mortar_sum(const KArgs<T> &a, const T *const *grp, int64_
 // and neighbouring blocks, run on the same XCD (dispatch is round-robin over
 // the 8 XCDs), keeping partner traces and shared segments in one L2.
 // ---------------------------------------------------------------------------
+// Per-point neighbour code (NB's form) of point m of a face from its per-face code (NBF)
+template <int DIM, int N, int NFP, int NFPAD> __device__ inline int point_code(int fc, int m) {
+  if (fc < 0) {
+    const int kind = (-fc) & 3;
+    return kind == BC_WALL ? -(kind | ((((-fc) >> 2) + m) << 2)) : fc;
+  }
+  const int ps = fc >> 6, pf = (fc >> 3) & 7;
+  return int(lay(ps / EB, pf * NFP + face_map(m, fc & 7, N, DIM), 0, ps % EB, NFPAD, 1));
+}
+
+// Face of flux point q in a fused-stage flux-point pass (slot t = tid + it * WG, q = t / EW,
+// WG a multiple of 64). When a wavefront's 64 slots are exactly the NFP points of one face
+// for EW elements (NFP * EW = 64: FP32 at p = 3 with 4 elements per workgroup), the face is
+// the same in every lane and is read as a scalar, so the face-axis selects that follow run
+// on the scalar unit instead of the vector ALUs.
+template <int NFP, int EW> __device__ inline int face_of(int q) {
+  if constexpr (NFP * EW == 64) return __builtin_amdgcn_readfirstlane(q / NFP);
+  return q / NFP;
+}
+
 __device__ inline int64_t xcd_remap(int64_t wg, int64_t nwg) {
   const int64_t full = nwg / 8 * 8;
   return wg < full ? (wg % 8) * (nwg / 8) + wg / 8 : wg;
@@ -1040,11 +1068,17 @@ template <typename T, int DIM, int ORDER, int FV, int TILE = TILE_DEFAULT> struc
 
 // register budget: 4 waves per SIMD in FP32 (3 with node metrics, whose FP64 metric
 // products need more registers), 2 in FP64
-template <typename T, int DIM, int ORDER, int FV, int TILE>
+// SCAT: the neighbour exchange by scatter. The previous launch (or the trace
+// interpolation) wrote each partner's trace into this element's slot of UF, so the
+// partner traces load from the own slots; the viscous half flux P goes to the partner's
+// slot of PV, where the second launch reads it from its own. Without SCAT both are
+// gathered through the neighbour codes. Not with mortar faces.
+template <typename T, int DIM, int ORDER, int FV, int TILE, bool SCAT>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (NodeMetrics<T, DIM, ORDER, FV>::ON ? 3 : 4) : 2, 8)))
 void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   constexpr bool MORTAR = FV == FV_MORTAR;
+  static_assert(!(SCAT && MORTAR), "mortar faces exchange by gather");
   using S = Shape<DIM, ORDER>;
   using F = FS<T, DIM, ORDER, TILE>;
   using NM = NodeMetrics<T, DIM, ORDER, FV, TILE>;
@@ -1120,7 +1154,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 #pragma unroll
     for (int it = 0; it < FI; ++it) {
       const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
-      const int f = q / S::NFP, m = q % S::NFP, k = f / 2, sd = f & 1;
+      const int f = face_of<S::NFP, EW>(q), m = q % S::NFP, k = f / 2, sd = f & 1;
       const int col = k == 0 ? sd * N + m % N : (k == 1 ? 2 * N + sd * N + m % N : 4 * N + m);
       fcv[it][0] = a.FCX[lay(blk, col, 0, eg, NFC, 2)];
       fcv[it][1] = a.FCX[lay(blk, col, 1, eg, NFC, 2)];
@@ -1139,7 +1173,12 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     const int nb = nbv[it];
-    if (MORTAR && nb < 0 && ((-nb) & 3) == BC_MORTAR) {
+    if constexpr (SCAT) {
+      // the partner's trace, written into this slot (never used at a boundary point)
+      const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ur[it][v] = a.UF[at(blk, q, v, eg, S::NFPAD, NV)];
+    } else if (MORTAR && nb < 0 && ((-nb) & 3) == BC_MORTAR) {
       // the other side's trace at this point: its face points' traces interpolated
       // (higher-order side) or projected (lower-order side)
       mortar_sum<T, NV>(a, a.GUF, (-nb) >> 3, ur[it]);
@@ -1221,7 +1260,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 #pragma unroll
     for (int it = 0; it < FI; ++it) {
       const int t = tid + it * WG, q = min(t / EW, S::NF - 1);
-      const int f = q / S::NFP, k = f / 2;
+      const int f = face_of<S::NFP, EW>(q), k = f / 2;
       const double z = fzv[it], u = fcv[it][0], w = fcv[it][1];
       double sk[3];
       sk[0] = k == 0 ? w * z : (k == 1 ? -(z * w) : 0.0);
@@ -1244,7 +1283,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
     if (t >= S::NF * EW) break;
     T du[NV];
     if (eg < nvalid) {
-      const int f = q / S::NFP, m = q % S::NFP, k = f / 2;
+      const int f = face_of<S::NFP, EW>(q), m = q % S::NFP, k = f / 2;
       const T *l = (f & 1) ? B.lp : B.lm;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -1446,7 +1485,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
     const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
     if (t >= S::NF * EW) break;
     if (eg >= nvalid) continue;
-    const int f = q / S::NFP, m = q % S::NFP, k = f / 2;
+    const int f = face_of<S::NFP, EW>(q), m = q % S::NFP, k = f / 2;
     const T *l = (f & 1) ? B.lp : B.lm;
     T gf[DIM][NV];
 #pragma unroll
@@ -1462,11 +1501,13 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
     T fn[NV];
     if (nb >= 0 || (MORTAR && ((-nb) & 3) == BC_MORTAR)) {
       gas.flux_vis_n(ufv[it], gf, nrm[it], fn, false);
+      // P to the partner's slot (exchange by scatter) or to this one
+      const size_t pbase = SCAT ? size_t(nb / SB) * NV * SB + (nb % SB) : at(blk, q, 0, eg, S::NFPAD, NV);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const T pv = T(0.5) * fn[v];
         const T qv = (FQL ? Lq[(q * NV + v) * EW + e] : fiv[it][v]) - pv;
-        a.PV[at(blk, q, v, eg, S::NFPAD, NV)] = SCALED ? T(Av[it] * double(pv)) : pv;
+        a.PV[pbase + v * SB] = SCALED ? T(Av[it] * double(pv)) : pv;
         a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = SCALED ? T(Av[it] * double(qv)) : qv;
       }
     } else {
@@ -1588,15 +1629,21 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 
 // register budget: 5 waves per SIMD in FP32 (the occupancy its default LDS sizing is made
 // for), 2 in FP64
-template <typename T, int DIM, int ORDER, int MODE, int FV, int TILE>
+// SCAT: the partner's half flux P loads from the own slot of PV (the first launch put it
+// there), and the next stage's trace goes to the partner's slot of UF
+template <typename T, int DIM, int ORDER, int MODE, int FV, int TILE, bool SCAT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 2, 8)))
 void k_stage_b(KArgs<T> a) {
   constexpr int mode = MODE;  // RK stage or residual: fixes what is read and written
   constexpr bool MORTAR = FV == FV_MORTAR;
+  static_assert(!(SCAT && MORTAR), "mortar faces exchange by gather");
   using S = Shape<DIM, ORDER>;
   using F = FS<T, DIM, ORDER, TILE>;
-  // the first launch stored the half fluxes times the area factor (node metrics)
-  constexpr bool NODEM = NodeMetrics<T, DIM, ORDER, FV>::ON;
+  // the first launch stored the half fluxes times the area factor (metrics from the
+  // geometry nodes or the extruded columns); with the columns, 1/|J| is the product of
+  // the column's and the layer's reciprocal factors (FP64)
+  constexpr bool COLJ = DIM == 3 && FV == FV_EXTR;
+  constexpr bool NODEM = NodeMetrics<T, DIM, ORDER, FV>::ON || COLJ;
   constexpr int EW = F::EW_B, WG = F::WG_B, NS = EB / EW, N = S::N, NV = S::NV;
   constexpr int FI = (S::NF * EW + WG - 1) / WG, PI = (S::NU * EW + WG - 1) / WG;
   __shared__ T Cs[S::NF * NV * EW];
@@ -1626,7 +1673,13 @@ void k_stage_b(KArgs<T> a) {
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
     nbv[it] = -BC_FARFIELD;
-    if (!SKIP || (t < S::NF * EW && eg < nvalid)) nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
+    if (!SKIP || (t < S::NF * EW && eg < nvalid)) {
+      // per-face codes where the mesh has them (24 B per element in 3D instead of 384)
+      if (!MORTAR && a.NBF)
+        nbv[it] = point_code<DIM, N, S::NFP, S::NFPAD>(a.NBF[lay(blk, q / S::NFP, 0, eg, 2 * DIM, 1)], q % S::NFP);
+      else
+        nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
+    }
   }
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
@@ -1640,7 +1693,13 @@ void k_stage_b(KArgs<T> a) {
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     const int nb = nbv[it];
-    if (MORTAR && nb < 0 && ((-nb) & 3) == BC_MORTAR) {
+    if constexpr (SCAT) {
+      const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
+      if (!SKIP || (t < S::NF * EW && eg < nvalid)) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[at(blk, q, v, eg, S::NFPAD, NV)];
+      }
+    } else if (MORTAR && nb < 0 && ((-nb) & 3) == BC_MORTAR) {
       const int64_t pt = (-nb) >> 3;
       if (((-nb) >> 2) & 1) {
         // lower-order side: the complete transformed common flux, the L2 projection of
@@ -1676,7 +1735,8 @@ void k_stage_b(KArgs<T> a) {
   for (int it = 0; it < PI; ++it) {
     const int t = tid + it * WG, i = min(t / EW, S::NU - 1), eg = e0 + t % EW;
     if (!SKIP || (t < S::NU * EW && eg < nvalid)) {
-      ijv[it] = a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
+      ijv[it] = COLJ ? a.IJC[lay(blk, i % (S::N * S::N), 0, eg, S::N * S::N, 1)] * a.IZ[lay(blk, i / (S::N * S::N), 0, eg, S::N, 1)]
+                     : a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const size_t x = at(blk, i, v, eg, S::NUP, NV);
@@ -1782,14 +1842,17 @@ void k_stage_b(KArgs<T> a) {
     const int t = tid + it * WG, e = t % EW, q = t / EW, eg = e0 + e;
     if (t >= S::NF * EW) break;
     if (eg >= nvalid) continue;
+    if (SCAT && nbv[it] < 0) continue;  // a boundary point has no partner to receive it
     const int f = q / S::NFP, m = q % S::NFP, k = f / 2;
     const T *l = (f & 1) ? B.lp : B.lm;
+    const size_t ubase =
+        SCAT ? size_t(nbv[it] / SB) * NV * SB + (nbv[it] % SB) : at(blk, q, 0, eg, S::NFPAD, NV);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       T sv = 0;
 #pragma unroll
       for (int j = 0; j < N; ++j) sv += l[j] * Un[(Ref<DIM, N>::line(k, m, j) * NV + v) * EW + e];
-      a.UF[at(blk, q, v, eg, S::NFPAD, NV)] = sv;
+      a.UF[ubase + v * SB] = sv;
     }
   }
 
@@ -1904,69 +1967,88 @@ template <typename T> static KArgs<T> make_args(const LaunchCfg &c, const DevArr
   a.SM = d.SM; a.IJ = d.IJ; a.FN = d.FN; a.FA = d.FA; a.bdt = d.bdt; a.fsd = d.fsd; a.wface = d.wface;
   a.XN = d.XN; a.GQ = d.GQ;
   a.XC = d.XC; a.ZZ = d.ZZ; a.FCX = d.FCX;
+  a.IJC = d.IJC; a.IZ = d.IZ;
   a.FC = d.FC; a.fsum = d.fsum; a.stage64 = d.stage64;
-  a.NB = d.NB; a.bcount = d.bcount; a.bdesign = d.bdesign; a.bcanon = d.bcanon; a.wall_first = d.wall_first;
+  a.NB = d.NB; a.NBF = d.NBF; a.bcount = d.bcount; a.bdesign = d.bdesign; a.bcanon = d.bcanon; a.wall_first = d.wall_first;
   a.flag = d.flag;
   a.MO = d.MO; a.MG = d.MG; a.MC = d.MC; a.MW = d.MW;
   a.GUF = (const T *const *)d.GUF; a.GPV = (const T *const *)d.GPV; a.MT = (T *)d.MT;
   a.PO = d.PO; a.PC = d.PC; a.PW = d.PW;
   a.nblk = c.nblk; a.n_canon = c.n_canon; a.ndesign = c.ndesign;
   a.xcd = (c.variant_mask & NO_XCD_REMAP) ? 0 : 1;
+  a.scatter = 0;
   a.gam = T(c.gamma); a.mu = T(c.mu); a.kappa = T(c.mu * c.gamma / c.prandtl);
   return a;
 }
 
-template <typename T, int DIM, int ORDER, int FV, int TILE>
+template <typename T, int DIM, int ORDER, int FV, int TILE, bool SCAT>
 static void go_stage_a(const LaunchCfg &c, const KArgs<T> &a, const T *X, bool forces) {
   using F = FS<T, DIM, ORDER, TILE>;
   const dim3 grid(static_cast<unsigned>(c.nblk * (EB / F::EW_A)));
-  hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER, FV, TILE>), grid, dim3(F::WG_A), 0, c.stream, a, X, int(forces));
+  hipLaunchKernelGGL((k_stage_a<T, DIM, ORDER, FV, TILE, SCAT>), grid, dim3(F::WG_A), 0, c.stream, a, X,
+                     int(forces));
 }
 
 // tile shapes other than the default are compiled for 3D one-order meshes of order 1 up
 template <int DIM, int ORDER, int FV> constexpr bool tiled() { return DIM == 3 && ORDER >= 1 && FV != FV_MORTAR; }
 
-template <typename T, int DIM, int ORDER, int FV>
-static void launch_stage_a(const LaunchCfg &c, const KArgs<T> &a, const T *X, bool forces) {
+template <typename T, int DIM, int ORDER, int FV, bool SCAT>
+static void launch_stage_a_tiles(const LaunchCfg &c, const KArgs<T> &a, const T *X, bool forces) {
   if constexpr (tiled<DIM, ORDER, FV>()) {
     switch (tile_a(c.variant_mask)) {
-      case TILE_HALF: return go_stage_a<T, DIM, ORDER, FV, TILE_HALF>(c, a, X, forces);
-      case TILE_QUARTER: return go_stage_a<T, DIM, ORDER, FV, TILE_QUARTER>(c, a, X, forces);
+      case TILE_HALF: return go_stage_a<T, DIM, ORDER, FV, TILE_HALF, SCAT>(c, a, X, forces);
+      case TILE_QUARTER: return go_stage_a<T, DIM, ORDER, FV, TILE_QUARTER, SCAT>(c, a, X, forces);
       case TILE_MFMA:
-        if constexpr (sizeof(T) == 4 && ORDER == 3) return go_stage_a<T, DIM, ORDER, FV, TILE_MFMA>(c, a, X, forces);
+        if constexpr (sizeof(T) == 4 && ORDER == 3)
+          return go_stage_a<T, DIM, ORDER, FV, TILE_MFMA, SCAT>(c, a, X, forces);
         break;
       default: break;
     }
   }
-  go_stage_a<T, DIM, ORDER, FV, TILE_DEFAULT>(c, a, X, forces);
+  go_stage_a<T, DIM, ORDER, FV, TILE_DEFAULT, SCAT>(c, a, X, forces);
 }
 
-template <typename T, int DIM, int ORDER, int FV, int TILE>
+// the exchange by scatter exists for one-order meshes (no mortar faces)
+template <typename T, int DIM, int ORDER, int FV>
+static void launch_stage_a(const LaunchCfg &c, const KArgs<T> &a, const T *X, bool forces) {
+  if constexpr (FV != FV_MORTAR)
+    if (c.variant_mask & SCATTER_EXCHANGE) return launch_stage_a_tiles<T, DIM, ORDER, FV, true>(c, a, X, forces);
+  launch_stage_a_tiles<T, DIM, ORDER, FV, false>(c, a, X, forces);
+}
+
+template <typename T, int DIM, int ORDER, int FV, int TILE, bool SCAT>
 static hipError_t go_stage_b(const LaunchCfg &c, int mode, const KArgs<T> &a) {
   using F = FS<T, DIM, ORDER, TILE>;
   const dim3 grid(static_cast<unsigned>(c.nblk * (EB / F::EW_B))), wgs(F::WG_B);
   auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, wgs, 0, c.stream, a); };
   switch (mode) {
-    case MODE_RK0: go(k_stage_b<T, DIM, ORDER, MODE_RK0, FV, TILE>); break;
-    case MODE_RK1: go(k_stage_b<T, DIM, ORDER, MODE_RK1, FV, TILE>); break;
-    case MODE_RK2: go(k_stage_b<T, DIM, ORDER, MODE_RK2, FV, TILE>); break;
-    case MODE_RK3: go(k_stage_b<T, DIM, ORDER, MODE_RK3, FV, TILE>); break;
-    case MODE_RESID: go(k_stage_b<T, DIM, ORDER, MODE_RESID, FV, TILE>); break;
+    case MODE_RK0: go(k_stage_b<T, DIM, ORDER, MODE_RK0, FV, TILE, SCAT>); break;
+    case MODE_RK1: go(k_stage_b<T, DIM, ORDER, MODE_RK1, FV, TILE, SCAT>); break;
+    case MODE_RK2: go(k_stage_b<T, DIM, ORDER, MODE_RK2, FV, TILE, SCAT>); break;
+    case MODE_RK3: go(k_stage_b<T, DIM, ORDER, MODE_RK3, FV, TILE, SCAT>); break;
+    case MODE_RESID: go(k_stage_b<T, DIM, ORDER, MODE_RESID, FV, TILE, SCAT>); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <typename T, int DIM, int ORDER, int FV>
-static hipError_t launch_stage_b(const LaunchCfg &c, int mode, const KArgs<T> &a) {
+template <typename T, int DIM, int ORDER, int FV, bool SCAT>
+static hipError_t launch_stage_b_tiles(const LaunchCfg &c, int mode, const KArgs<T> &a) {
   if constexpr (tiled<DIM, ORDER, FV>()) {
     switch (tile_b(c.variant_mask)) {
-      case TILE_HALF: return go_stage_b<T, DIM, ORDER, FV, TILE_HALF>(c, mode, a);
-      case TILE_QUARTER: return go_stage_b<T, DIM, ORDER, FV, TILE_QUARTER>(c, mode, a);
+      case TILE_HALF: return go_stage_b<T, DIM, ORDER, FV, TILE_HALF, SCAT>(c, mode, a);
+      case TILE_QUARTER: return go_stage_b<T, DIM, ORDER, FV, TILE_QUARTER, SCAT>(c, mode, a);
       default: break;
     }
   }
-  return go_stage_b<T, DIM, ORDER, FV, TILE_DEFAULT>(c, mode, a);
+  return go_stage_b<T, DIM, ORDER, FV, TILE_DEFAULT, SCAT>(c, mode, a);
+}
+
+template <typename T, int DIM, int ORDER, int FV>
+static hipError_t launch_stage_b(const LaunchCfg &c, int mode, const KArgs<T> &a) {
+  if constexpr (FV != FV_MORTAR)
+    if (c.variant_mask & SCATTER_EXCHANGE) return launch_stage_b_tiles<T, DIM, ORDER, FV, true>(c, mode, a);
+  return launch_stage_b_tiles<T, DIM, ORDER, FV, false>(c, mode, a);
 }
 
 template <typename T, int DIM, int ORDER>
@@ -1980,7 +2062,10 @@ static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, i
   const bool tensor = (c.variant_mask >> kernel) & 1;
   switch (kernel) {
     case K_INTERP:
-      if (tensor)
+      // the exchange by scatter wants the initial trace in the partners' slots: the
+      // sum-factorised trace kernel writes it there (a.scatter)
+      a.scatter = (c.variant_mask & SCATTER_EXCHANGE) && !d.MO ? 1 : 0;
+      if (tensor || a.scatter)
         hipLaunchKernelGGL((t_interp<T, DIM, ORDER>), dim3(c.nblk * (EB / TT::EW_INTERP)), blk, 0, c.stream, a, X);
       else
         hipLaunchKernelGGL((k_interp<T, DIM, ORDER>), dim3((c.nblk * S::RTF + 3) / 4), blk, 0, c.stream, a, X);
@@ -2016,8 +2101,11 @@ static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, i
       break;
     case K_STAGE_B:
       if (d.MO) return launch_stage_b<T, DIM, ORDER, FV_MORTAR>(c, mode, a);
-      // the extruded first launch scales the half fluxes by the area factor like FV_NODE
-      if (DIM == 3 && (((c.variant_mask & EXTRUDED_METRICS) && d.XC) || !(c.variant_mask & STORED_METRICS)))
+      // the extruded first launch scales the half fluxes by the area factor like FV_NODE,
+      // and the second takes 1/|J| from the column factors
+      if (DIM == 3 && (c.variant_mask & EXTRUDED_METRICS) && d.XC && d.IJC)
+        return launch_stage_b<T, DIM, ORDER, DIM == 3 ? FV_EXTR : FV_STORED>(c, mode, a);
+      if (DIM == 3 && !(c.variant_mask & STORED_METRICS))
         return launch_stage_b<T, DIM, ORDER, DIM == 3 ? FV_NODE : FV_STORED>(c, mode, a);
       return launch_stage_b<T, DIM, ORDER, FV_STORED>(c, mode, a);
     case K_DIVRK:

@@ -92,7 +92,7 @@ fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
     total += size_t(nwall) * D.nfp * 3 * 8;
     if (d->dim == 3)  // column metrics of groups of extruded elements, at the highest order
       total += size_t(d->n_elems + 8 * fr::EB) * 8 *
-               (size_t(D.n) * D.n * 4 + D.n + (4 * size_t(D.n) + size_t(D.n) * D.n) * 2);
+               (size_t(D.n) * D.n * 4 + D.n + (4 * size_t(D.n) + size_t(D.n) * D.n) * 2 + size_t(D.n) * D.n + D.n);
     // mortar data. Faces are matched by their corner node ids; a face shared by elements
     // of two orders carries nfp_H + nfp_L mortar points, nfp_H nfp_L interpolation entries
     // and, for its lower-order points, nfp_L nfp_H trace and nfp_L nfp_H projection
@@ -160,10 +160,11 @@ fr_status fr_footprint(const fr_mesh_desc *d, size_t *bytes) {
   // geometry and tables
   b += size_t(nblk) * D.nup * dim * dim * fr::EB * 8 + size_t(nblk) * D.nup * fr::EB * 8;
   b += size_t(nblk) * D.nfpad * dim * fr::EB * 8 + size_t(nblk) * D.nfpad * fr::EB * 8;
-  b += size_t(nblk) * D.nfpad * fr::EB * 4;
+  b += size_t(nblk) * D.nfpad * fr::EB * 4 + size_t(nblk) * 2 * dim * fr::EB * 4;  // per-point and per-face codes
   if (dim == 3) b += size_t(nblk) * 27 * 3 * fr::EB * 8 + size_t(6 * D.n) * 8;  // geometry nodes, basis
-  if (fr::desc_extruded(*d))  // column metrics
-    b += size_t(nblk) * fr::EB * 8 * (size_t(D.n) * D.n * 4 + D.n + (4 * size_t(D.n) + size_t(D.n) * D.n) * 2);
+  if (fr::desc_extruded(*d))  // column metrics and the reciprocal column and layer factors of |J|
+    b += size_t(nblk) * fr::EB * 8 *
+         (size_t(D.n) * D.n * 4 + D.n + (4 * size_t(D.n) + size_t(D.n) * D.n) * 2 + size_t(D.n) * D.n + D.n);
   b += r256(nblk * 4) * 2 + r256(nblk * 8) * 2 + r256(5 * 8) + r256(2 * 8) + r256(D.nfpad * 8);
   // state and stage arrays
   const size_t nU = size_t(nblk) * D.nup * nv * fr::EB, nF = size_t(nblk) * D.nfpad * nv * fr::EB;

@@ -40,14 +40,16 @@ def test_no_kernel_spills(src):
 def test_fused_fp32_stage_kernels_keep_their_occupancy():
     r = resources("fr_kernels.hip")
     # template arguments after the order: metric source (0 from the nodes, 1 stored, 2
-    # mortar groups, 3 extruded columns), then the tile shape (0 default, 1 half the
-    # elements, 2 a quarter)
+    # mortar groups, 3 extruded columns), the tile shape (0 default, 1 half the elements,
+    # 2 a quarter, 3 matrix cores), and the neighbour exchange (0 gather, 1 scatter)
     for fv, waves in ((0, 3), (1, 4), (3, 4)):
-        for tile in range(3):
-            a = r[f"_ZN2fr9k_stage_aIfLi3ELi3ELi{fv}ELi{tile}EEEvNS_5KArgsIT_EEPKS2_i"]
-            assert a["occupancy"] >= waves and waves * a["lds"] <= 160 * 1024, (fv, tile, a)
+        for tile in range(4):
+            for scat in (0, 1):
+                a = r[f"_ZN2fr9k_stage_aIfLi3ELi3ELi{fv}ELi{tile}ELb{scat}EEEvNS_5KArgsIT_EEPKS2_i"]
+                assert a["occupancy"] >= waves and waves * a["lds"] <= 160 * 1024, (fv, tile, scat, a)
     for fv in (0, 1):
-        for tile, want in ((0, 5), (1, 5), (2, 5)):
-            for mode in range(4):
-                b = r[f"_ZN2fr9k_stage_bIfLi3ELi3ELi{mode}ELi{fv}ELi{tile}EEEvNS_5KArgsIT_EE"]
-                assert b["occupancy"] >= want and want * b["lds"] <= 160 * 1024, (fv, tile, mode, b)
+        for tile in range(3):
+            for scat in (0, 1):
+                for mode in range(4):
+                    b = r[f"_ZN2fr9k_stage_bIfLi3ELi3ELi{mode}ELi{fv}ELi{tile}ELb{scat}EEEvNS_5KArgsIT_EE"]
+                    assert b["occupancy"] >= 5 and 5 * b["lds"] <= 160 * 1024, (fv, tile, scat, mode, b)

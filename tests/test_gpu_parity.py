@@ -325,6 +325,10 @@ def test_pool_results_bit_identical_to_solo():
 # (FP32, order 3) take the same fused multiply-adds in the same order as the vector ALUs,
 # so every shape must give the default's results bit for bit
 TILE_SHAPES = [(1, 0), (2, 0), (3, 0), (0, 1), (0, 2), (2, 2), (1, 1)]
+# bit 13: the neighbour exchange by scatter (each trace and viscous half flux written into
+# the partner's slot) instead of the gather through the neighbour codes: the same values
+# reach the same places, so again bit for bit
+SCATTER = 1 << 13
 
 
 @pytest.mark.parametrize("name", ["tgv_p1", "tgv_p2", "tgv_p3_one", "tgv_p4", "airfoil_p2", "airfoil_p3",
@@ -341,15 +345,48 @@ def test_tile_shapes_bit_identical(name, prec, metrics):
     g.set_state(u)
     g.step(3)
     s0, f0 = g.get_state(), g.forces()
-    for ta, tb in TILE_SHAPES:
-        g.select_kernels(VARIANTS[metrics] | (ta << 9) | (tb << 11))
-        r = g.residual(u)
-        g.set_state(u)
-        g.step(3)
-        assert np.array_equal(r, r0), (ta, tb)
-        assert np.array_equal(g.get_state(), s0), (ta, tb)
-        assert np.array_equal(g.forces(), f0, equal_nan=True), (ta, tb)  # NaN coefficients: no wall
-    print(f"{name} {prec} {metrics}: tiles {TILE_SHAPES} bit-identical to the default")
+    for ta, tb in [(0, 0)] + TILE_SHAPES:
+        for scat in (0, SCATTER):
+            if ta == tb == scat == 0:
+                continue
+            g.select_kernels(VARIANTS[metrics] | (ta << 9) | (tb << 11) | scat)
+            r = g.residual(u)
+            g.set_state(u)
+            g.step(3)
+            assert np.array_equal(r, r0), (ta, tb, scat)
+            assert np.array_equal(g.get_state(), s0), (ta, tb, scat)
+            assert np.array_equal(g.forces(), f0, equal_nan=True), (ta, tb, scat)  # NaN coefficients: no wall
+    print(f"{name} {prec} {metrics}: tiles {TILE_SHAPES}, gather and scatter, bit-identical to the default")
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["vortex2d_p3", "vortex2d_p1", "box2d_curved_p2"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_scatter_exchange_2d_bit_identical(name, prec):
+    m = case(name)
+    o = OracleMesh(m)
+    u = perturbed(o, m)
+    g = FRMesh(m, prec)
+    g.select_kernels(VARIANTS["fused"])
+    r0 = g.residual(u)
+    g.set_state(u)
+    g.step(3)
+    s0 = g.get_state()
+    g.select_kernels(VARIANTS["fused"] | SCATTER)
+    assert np.array_equal(g.residual(u), r0)
+    g.set_state(u)
+    g.step(3)
+    assert np.array_equal(g.get_state(), s0)
+    if prec == "fp64":
+        assert rel_err(r0, o.residual(u)) <= 1e-12
+    g.close()
+
+
+def test_scatter_exchange_rejected_without_fused_stage():
+    g = FRMesh(case("tgv_p2"), "fp64")
+    with pytest.raises(_lib.FRError) as e:
+        g.select_kernels(VARIANTS["tensor"] | SCATTER)
+    assert e.value.code == _lib.FR_E_UNSUPPORTED
     g.close()
 
 
