@@ -1085,6 +1085,9 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   constexpr bool NODEM = NM::ON;
   constexpr bool EXTR = DIM == 3 && FV == FV_EXTR;
   constexpr bool SCALED = NODEM || EXTR;  // Q and P stored times the area factor
+  // FP32 form: metric factors (formed in FP64) rounded to FP32 once per point or flux
+  // point, products in FP32
+  constexpr bool MP32 = sizeof(T) == 4;
   // the matrix-core tile: FP32 at p = 3 with 4 elements per workgroup of 4 waves (node
   // metrics keep their geometry passes in the LDS the gradient pass reuses)
   constexpr bool MFG =
@@ -1440,25 +1443,45 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       for (int c = 0; c < NG; ++c) Gs[(i * NG + c) * EW + e] = Fs[(i * NG + c) * EW + e] = 0;
       continue;
     }
-    // physical gradient S^T G / |J|; with column metrics the five nonzero entries of S
-    // are divided by |J| once per point (FP64), elsewhere each sum is
+    // physical gradient S^T G / |J| and transformed flux S (F_inv - F_vis). The metric
+    // factors of the point are formed in FP64. The FP64 form multiplies in FP64; the FP32
+    // form rounds the point's factors S/|J| and S to FP32 once and multiplies in FP32, as
+    // its operators and fluxes. Zeros of the block form of S are skipped on column metrics.
     T gu[DIM][NV];
     double Mj[DIM][DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k)
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) Mj[k][c] = EXTR ? Sm[it][k][c] * ijv[it] : Sm[it][k][c];
+      for (int c = 0; c < DIM; ++c) Mj[k][c] = (EXTR || MP32) ? Sm[it][k][c] * ijv[it] : Sm[it][k][c];
+    T Mt[DIM][DIM], St[DIM][DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        Mt[k][c] = T(Mj[k][c]);
+        St[k][c] = T(Sm[it][k][c]);
+      }
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        double sg = 0.0;
+        if constexpr (MP32) {
+          T sg = 0;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-          if (EXTR && (k == 2) != (c == 2)) continue;  // zero in the block form of S
-          sg += Mj[k][c] * double(Gr[it][k][v]);
+          for (int k = 0; k < DIM; ++k) {
+            if (EXTR && (k == 2) != (c == 2)) continue;
+            sg = fma(Mt[k][c], Gr[it][k][v], sg);
+          }
+          gu[c][v] = sg;
+        } else {
+          double sg = 0.0;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            if (EXTR && (k == 2) != (c == 2)) continue;  // zero in the block form of S
+            sg += Mj[k][c] * double(Gr[it][k][v]);
+          }
+          gu[c][v] = T(EXTR ? sg : sg * ijv[it]);
         }
-        gu[c][v] = T(EXTR ? sg : sg * ijv[it]);
         Gs[(i * NG + c * NV + v) * EW + e] = gu[c][v];
       }
     T Fi[DIM][NV], Fv[DIM][NV];
@@ -1468,13 +1491,23 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
     for (int k = 0; k < DIM; ++k)
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        double sf = 0.0;
+        if constexpr (MP32) {
+          T sf = 0;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-          if (EXTR && (k == 2) != (c == 2)) continue;
-          sf += Sm[it][k][c] * double(Fi[c][v] - Fv[c][v]);
+          for (int c = 0; c < DIM; ++c) {
+            if (EXTR && (k == 2) != (c == 2)) continue;
+            sf = fma(St[k][c], Fi[c][v] - Fv[c][v], sf);
+          }
+          Fs[(i * NG + k * NV + v) * EW + e] = sf;
+        } else {
+          double sf = 0.0;
+#pragma unroll
+          for (int c = 0; c < DIM; ++c) {
+            if (EXTR && (k == 2) != (c == 2)) continue;
+            sf += Sm[it][k][c] * double(Fi[c][v] - Fv[c][v]);
+          }
+          Fs[(i * NG + k * NV + v) * EW + e] = T(sf);
         }
-        Fs[(i * NG + k * NV + v) * EW + e] = T(sf);
       }
   }
   __syncthreads();
@@ -1503,12 +1536,13 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       gas.flux_vis_n(ufv[it], gf, nrm[it], fn, false);
       // P to the partner's slot (exchange by scatter) or to this one
       const size_t pbase = SCAT ? size_t(nb / SB) * NV * SB + (nb % SB) : at(blk, q, 0, eg, S::NFPAD, NV);
+      const T Af = T(Av[it]);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const T pv = T(0.5) * fn[v];
         const T qv = (FQL ? Lq[(q * NV + v) * EW + e] : fiv[it][v]) - pv;
-        a.PV[pbase + v * SB] = SCALED ? T(Av[it] * double(pv)) : pv;
-        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = SCALED ? T(Av[it] * double(qv)) : qv;
+        a.PV[pbase + v * SB] = SCALED ? (MP32 ? Af * pv : T(Av[it] * double(pv))) : pv;
+        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = SCALED ? (MP32 ? Af * qv : T(Av[it] * double(qv))) : qv;
       }
     } else {
       const int code = -nb;
@@ -1523,7 +1557,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const T qv = (FQL ? Lq[(q * NV + v) * EW + e] : fiv[it][v]) - fn[v];
-        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = SCALED ? T(Av[it] * double(qv)) : qv;
+        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = SCALED ? (MP32 ? T(Av[it]) * qv : T(Av[it] * double(qv))) : qv;
       }
       if (forces && (code & 3) == BC_WALL) {
         // traction of the fluid on the body: W A (p n - tau . n), interior trace
