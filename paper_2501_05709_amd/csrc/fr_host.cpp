@@ -865,7 +865,7 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
             extruded_jacobian(descs[di], e, gl.x[size_t(i0)], gl.x[size_t(i1)], jc);
             for (int c = 0; c < 4; ++c) XC[lay(blk, i0 + D.n * i1, c, s, ncol, 4)] = jc[c];
             FCX[lay(blk, 4 * D.n + i0 + D.n * i1, 0, s, nfc, 2)] = jc[0] * jc[3] - jc[2] * jc[1];
-            IJC[lay(blk, i0 + D.n * i1, 0, s, ncol, 1)] = 1.0 / (jc[0] * jc[3] - jc[2] * jc[1]);
+            IJC[lay(blk, i0 + D.n * i1, 0, s, ncol, 1)] = 1.0 / FCX[lay(blk, 4 * D.n + i0 + D.n * i1, 0, s, nfc, 2)];
             FCX[lay(blk, 4 * D.n + i0 + D.n * i1, 1, s, nfc, 2)] = 0.0;
           }
         for (int i2 = 0; i2 < D.n; ++i2) {
@@ -939,8 +939,8 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
           } else {
             // decode the partner of point 0: c0 = lay(pblk, q', 0, pslot, NFPAD, 1)
             const int64_t cs = c0 / SB, ps_blk = cs / (int64_t(NSB) * NFPAD);
-            const int pq = int((cs / 1) % (int64_t(NSB) * NFPAD) % NFPAD);
-            const int psl = int(((cs % (int64_t(NSB) * NFPAD)) / NFPAD) * SB + c0 % SB);
+            const int pq = int(cs % NFPAD);
+            const int psl = int(((cs / NFPAD) % NSB) * SB + c0 % SB);
             const int pf = pq / nfp;
             int map = -1;
             for (int o = 0; o < (dim == 2 ? 2 : 8) && map < 0; ++o) {
@@ -959,16 +959,8 @@ void build_solver(fr_mesh *M, const fr_mesh_desc *descs, int nd, const MortarMap
     for (int64_t blk = 0; blk < NB && ok; ++blk)
       for (int sl = 0; sl < bcount[size_t(blk)] && ok; ++sl)
         for (int q = 0; q < nf && ok; ++q) {
-          const int fc = NBFt[lay(blk, q / nfp, 0, sl, nfc, 1)], m = q % nfp;
-          int c;
-          if (fc < 0) {
-            const int kind = (-fc) & 3;
-            c = kind == FR_BC_WALL ? -(kind | ((((-fc) >> 2) + m) << 2)) : fc;
-          } else {
-            const int ps = fc >> 6, pf = (fc >> 3) & 7;
-            c = int(lay(ps / EB, pf * nfp + face_map(m, fc & 7, D.n, dim), 0, ps % EB, NFPAD, 1));
-          }
-          ok = c == NBt[lay(blk, q, 0, sl, NFPAD, 1)];
+          const int fc = NBFt[lay(blk, q / nfp, 0, sl, nfc, 1)];
+          ok = point_code(fc, q % nfp, D.n, nfp, NFPAD, dim) == NBt[lay(blk, q, 0, sl, NFPAD, 1)];
         }
     if (!ok) NBFt.clear();
   }

@@ -84,6 +84,16 @@ __host__ __device__ inline int face_map(int m, int map, int n, int dim) {
   if (map & 2) b = n - 1 - b;
   return a + n * b;
 }
+// Per-point neighbour code (NB's form) of point m of a face from the face's per-face code
+// (NBF's form); n points per line, nfp per face, nfpad per element in the NB layout.
+__host__ __device__ inline int point_code(int fc, int m, int n, int nfp, int nfpad, int dim) {
+  if (fc < 0) {
+    const int kind = (-fc) & 3;
+    return kind == BC_WALL ? -(kind | ((((-fc) >> 2) + m) << 2)) : fc;
+  }
+  const int ps = fc >> 6, pf = (fc >> 3) & 7;
+  return int(lay(ps / EB, pf * nfp + face_map(m, fc & 7, n, dim), 0, ps % EB, nfpad, 1));
+}
 
 // Modes of K_DIVRK
 enum { MODE_RK0 = 0, MODE_RK1 = 1, MODE_RK2 = 2, MODE_RK3 = 3, MODE_RESID = 4 };

@@ -978,16 +978,6 @@ __device__ inline void mortar_sum(const KArgs<T> &a, const T *const *grp, int64_
 // and neighbouring blocks, run on the same XCD (dispatch is round-robin over
 // the 8 XCDs), keeping partner traces and shared segments in one L2.
 // ---------------------------------------------------------------------------
-// Per-point neighbour code (NB's form) of point m of a face from its per-face code (NBF)
-template <int DIM, int N, int NFP, int NFPAD> __device__ inline int point_code(int fc, int m) {
-  if (fc < 0) {
-    const int kind = (-fc) & 3;
-    return kind == BC_WALL ? -(kind | ((((-fc) >> 2) + m) << 2)) : fc;
-  }
-  const int ps = fc >> 6, pf = (fc >> 3) & 7;
-  return int(lay(ps / EB, pf * NFP + face_map(m, fc & 7, N, DIM), 0, ps % EB, NFPAD, 1));
-}
-
 // Face of flux point q in a fused-stage flux-point pass (slot t = tid + it * WG, q = t / EW,
 // WG a multiple of 64). When a wavefront's 64 slots are exactly the NFP points of one face
 // for EW elements (NFP * EW = 64: FP32 at p = 3 with 4 elements per workgroup), the face is
@@ -1710,7 +1700,7 @@ void k_stage_b(KArgs<T> a) {
     if (!SKIP || (t < S::NF * EW && eg < nvalid)) {
       // per-face codes where the mesh has them (24 B per element in 3D instead of 384)
       if (!MORTAR && a.NBF)
-        nbv[it] = point_code<DIM, N, S::NFP, S::NFPAD>(a.NBF[lay(blk, q / S::NFP, 0, eg, 2 * DIM, 1)], q % S::NFP);
+        nbv[it] = point_code(a.NBF[lay(blk, q / S::NFP, 0, eg, 2 * DIM, 1)], q % S::NFP, N, S::NFP, S::NFPAD, DIM);
       else
         nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
     }
