@@ -92,7 +92,7 @@ template <typename T> struct KArgs {
   int ndesign;
   int xcd;      // fused stage: map consecutive tiles to one XCD
   int scatter;  // trace interpolation: write each trace into its partner's slot
-  T gam, mu, kappa;
+  T gam, mu, kappa, igm1;  // igm1 = 1/(gamma - 1)
 };
 
 // ---------------------------------------------------------------------------
@@ -108,7 +108,7 @@ __device__ inline double sqrtv(double x) { return sqrt(x); }
 
 template <typename T, int D> struct Gas {
   static constexpr int NV = D + 2;
-  T gam, mu, kappa;
+  T gam, mu, kappa, igm1;  // igm1 = 1/(gamma - 1), formed on the host
 
   // pressure from the conserved state and 1/rho
   __device__ inline T pressure(const T *u, T ir) const {
@@ -248,8 +248,8 @@ template <typename T, int D> struct Gas {
     const T pL = pressure(uL, irL);
     const T rhoI = T(fs[0]), pI = T(fs[4]);
     const T cL = sqrtv(gam * pL * irL), cI = sqrtv(gam * pI / rhoI);
-    const T Rp = vnL + T(2) * cL / (gam - T(1));
-    const T Rm = vnI - T(2) * cI / (gam - T(1));
+    const T Rp = vnL + T(2) * cL * igm1;
+    const T Rm = vnI - T(2) * cI * igm1;
     const T vnb = T(0.5) * (Rp + Rm);
     const T cb = T(0.25) * (gam - T(1)) * (Rp - Rm);
     T s, vt[D];
@@ -262,7 +262,7 @@ template <typename T, int D> struct Gas {
 #pragma unroll
       for (int j = 0; j < D; ++j) vt[j] = vL[j] - vnL * n[j];
     }
-    const T rhob = pow(cb * cb / (gam * s), T(1) / (gam - T(1)));
+    const T rhob = pow(cb * cb / (gam * s), igm1);
     const T pb = rhob * cb * cb / gam;
     T ke = 0;
     ub[0] = rhob;
@@ -272,7 +272,7 @@ template <typename T, int D> struct Gas {
       ub[1 + j] = rhob * vb;
       ke += vb * vb;
     }
-    ub[D + 1] = pb / (gam - T(1)) + T(0.5) * rhob * ke;
+    ub[D + 1] = pb * igm1 + T(0.5) * rhob * ke;
   }
 
   // no-slip adiabatic wall: common solution with zero velocity
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(256) void k_face(KArgs<T> a) {
   const int q = int((t >> 4) % S::NFPAD);
   const int64_t blk = (t >> 4) / S::NFPAD;
   if (blk >= a.nblk || q >= S::NF || e >= a.bcount[blk]) return;
-  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
+  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa, a.igm1};
   T uf[S::NV], du[S::NV], fi[S::NV];
 #pragma unroll
   for (int v = 0; v < S::NV; ++v) uf[v] = a.UF[at(blk, q, v, e, S::NFPAD, S::NV)];
@@ -612,7 +612,7 @@ __global__ __launch_bounds__(256) void k_grad(KArgs<T> a, const T *__restrict__ 
     }
   }
   if (e >= a.bcount[blk]) return;
-  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
+  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa, a.igm1};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int i = rt * 16 + M::row(g, j);
@@ -655,7 +655,7 @@ __global__ __launch_bounds__(256) void k_visc(KArgs<T> a, int forces) {
         acc[k][v] = M::mac(av, Gb[(pt * S::NG + k * S::NV + v) * SB], acc[k][v]);
   }
   if (e >= a.bcount[blk]) return;
-  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
+  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa, a.igm1};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int q = rt * 16 + M::row(g, j);
@@ -832,7 +832,7 @@ __global__ __launch_bounds__(256) void t_grad(KArgs<T> a, const T *__restrict__ 
   stage_in<T, S::NU, S::NUP, S::NV, EW>(Us, X + size_t(blk) * S::NUP * S::NV * EB, e0);
   stage_in<T, S::NF, S::NFPAD, S::NV, EW>(Ds, a.DU + size_t(blk) * S::NFPAD * S::NV * EB, e0);
   __syncthreads();
-  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
+  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa, a.igm1};
   for (int t = threadIdx.x; t < S::NU * EW; t += blockDim.x) {
     const int e = t % EW, i = t / EW;
     if (e0 + e >= nvalid) continue;
@@ -870,7 +870,7 @@ __global__ __launch_bounds__(256) void t_visc(KArgs<T> a, int forces) {
   B.load(a.basis);
   stage_in<T, S::NU, S::NUP, S::NG, EW>(Gs, a.GU + size_t(blk) * S::NUP * S::NG * EB, e0);
   __syncthreads();
-  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
+  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa, a.igm1};
   for (int t = threadIdx.x; t < S::NF * EW; t += blockDim.x) {
     const int e = t % EW, q = t / EW;
     if (e0 + e >= nvalid) continue;
@@ -1242,7 +1242,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
     if (t < S::NU * NV * EW) Us[t] = ust[r];
   }
   __syncthreads();
-  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa};
+  const Gas<T, DIM> gas{a.gam, a.mu, a.kappa, a.igm1};
 
   // ---- faces: own trace, common solution jump (LDS), Rusanov flux (registers)
   T ufv[FI][NV], fiv[FI][NV], nrm[FI][DIM];
@@ -1259,11 +1259,20 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       sk[0] = k == 0 ? w * z : (k == 1 ? -(z * w) : 0.0);
       sk[1] = k == 0 ? -(u * z) : (k == 1 ? z * u : 0.0);
       sk[2] = k == 2 ? u : 0.0;
-      const double area = sqrt(sk[0] * sk[0] + sk[1] * sk[1] + sk[2] * sk[2]);
-      const double ia = ((f & 1) ? 1.0 : -1.0) / area;
-      Av[it] = area;
+      const double a2 = sk[0] * sk[0] + sk[1] * sk[1] + sk[2] * sk[2];
+      if constexpr (MP32) {
+        // FP32 form: |S_k|^2 in FP64, rounded once; the area and the unit normal in FP32
+        const float area = sqrtv(float(a2)), ia = (f & 1) ? recip(area) : -recip(area);
+        Av[it] = area;
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) nrd[it][c] = sk[c] * ia;
+        for (int c = 0; c < DIM; ++c) nrd[it][c] = float(sk[c]) * ia;
+      } else {
+        const double area = sqrt(a2);
+        const double ia = ((f & 1) ? 1.0 : -1.0) / area;
+        Av[it] = area;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) nrd[it][c] = sk[c] * ia;
+      }
     }
   }
 #pragma unroll
@@ -1426,7 +1435,9 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       Sm[it][2][0] = 0.0;
       Sm[it][2][1] = 0.0;
       Sm[it][2][2] = xx * ye - yx * xe;
-      ijv[it] = 1.0 / (xx * Sm[it][0][0] + yx * Sm[it][0][1]);
+      // FP32 form: |J| rounded once, its reciprocal in FP32
+      const double jac = xx * Sm[it][0][0] + yx * Sm[it][0][1];
+      ijv[it] = MP32 ? double(recip(float(jac))) : 1.0 / jac;
     }
     if (eg >= nvalid) {
 #pragma unroll
@@ -1448,8 +1459,9 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
     for (int k = 0; k < DIM; ++k)
 #pragma unroll
       for (int c = 0; c < DIM; ++c) {
-        Mt[k][c] = T(Mj[k][c]);
         St[k][c] = T(Sm[it][k][c]);
+        // column metrics in the FP32 form: S/|J| from the rounded S and 1/|J|
+        Mt[k][c] = (MP32 && EXTR) ? St[k][c] * T(ijv[it]) : T(Mj[k][c]);
       }
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
@@ -1832,7 +1844,8 @@ void k_stage_b(KArgs<T> a) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const size_t x = at(blk, i, v, eg, S::NUP, NV);
-      const T r = T(-double(div[v]) * ijv[it]);
+      // FP32 form: 1/|J| rounded once, the product in FP32
+      const T r = sizeof(T) == 4 ? -div[v] * T(ijv[it]) : T(-double(div[v]) * ijv[it]);
       T next = 0;
       if (mode == MODE_RESID) {
         a.RES[x] = r;
@@ -2002,6 +2015,7 @@ template <typename T> static KArgs<T> make_args(const LaunchCfg &c, const DevArr
   a.xcd = (c.variant_mask & NO_XCD_REMAP) ? 0 : 1;
   a.scatter = 0;
   a.gam = T(c.gamma); a.mu = T(c.mu); a.kappa = T(c.mu * c.gamma / c.prandtl);
+  a.igm1 = T(1.0 / (c.gamma - 1.0));
   return a;
 }
 
