@@ -182,7 +182,11 @@ fr_status fr_get_state(const fr_mesh *m, double *u);
  * four-stage Runge-Kutta and a fixed step in place of the paper's
  * second-order scheme with adaptive steps (Section 3.1, whose coefficients
  * are not given).  After each step the wall force of the new state is added
- * to the running means.  FR_E_NONFINITE if any step produced a non-finite
+ * to the running means: in the next step's first stage, which reads that
+ * state anyway, or, for the last state, when fr_forces reads the sums (or
+ * a call that overwrites the trace, such as fr_residual, comes first); the
+ * sums are those of adding it at once.
+ * FR_E_NONFINITE if any step produced a non-finite
  * value (the state is left as computed); FR_E_STATE if no state was set;
  * FR_E_ARG for n < 0. */
 fr_status fr_step(fr_mesh *m, int64_t n);

@@ -615,6 +615,13 @@ struct fr_mesh {
   DevArrays a;
   LaunchCfg cfg;
   bool state_set = false;
+  // UF holds the trace of the current state (the last stage of a step writes it), so
+  // the next step need not interpolate it again
+  bool trace_valid = false;
+  // the wall forces of the state the last step left are not yet in the sums: the next
+  // step's first stage adds them (its force pass reads that state), or flush_forces does
+  // when they are read first
+  bool forces_pending = false;
   hipGraphExec_t graph_first = nullptr, graph_rest = nullptr, graph_multi = nullptr;
   bool extruded = false;  // 3D, every element z-extruded: column metrics present
 
@@ -1515,6 +1522,41 @@ hipGraphExec_t capture_step(fr_mesh *M, bool forces, int64_t steps = 1) {
   return ex;
 }
 
+// The wall forces of the state the last steps left, added to the sums if they are not
+// there yet: one force pass over that state (its trace is current) and the reduction.
+void flush_forces(fr_mesh *M) {
+  if (!M->forces_pending) return;
+  hip_check(hipSetDevice(M->device), "hipSetDevice");
+  if (M->mixed()) {
+    for (auto &G : M->groups)
+      if (G->nwall > 0) {
+        lk(G.get(), K_STAGE_A, 0, 0, true);
+        hip_check(launch_force_reduce(G->cfg, G->a), "force reduce");
+      }
+  } else if (M->cfg.variant_mask & FUSED) {
+    lk(M, K_STAGE_A, 0, 0, true);
+    hip_check(launch_force_reduce(M->cfg, M->a), "force reduce");
+  } else {
+    lk(M, K_FACE, 0, 0, false);
+    lk(M, K_GRAD, 0, 0, false);
+    lk(M, K_VISC, 0, 0, true);
+    hip_check(launch_force_reduce(M->cfg, M->a), "force reduce");
+  }
+  M->forces_pending = false;
+}
+
+// Before anything overwrites the trace or the state outside a step: the pending forces
+// are taken while their state and trace are still there, and the next step interpolates
+// the trace again.
+void release_trace(fr_mesh *M) {
+  flush_forces(M);
+  M->trace_valid = false;
+}
+
+// n steps. The state's trace is interpolated only if no step left it; the first step
+// adds the wall forces of its input state to the sums only if the previous steps left
+// them pending (the input state of the first step after the state was set is not
+// averaged), every later step does. The forces of the last state stay pending.
 void step_async(fr_mesh *M, int64_t n, bool clear_flag = true) {
   if (!M->state_set) fail(FR_E_STATE, "no state set");
   if (n < 0) fail(FR_E_ARG, "negative step count");
@@ -1523,9 +1565,9 @@ void step_async(fr_mesh *M, int64_t n, bool clear_flag = true) {
   if (!M->graph_first) M->graph_first = capture_step(M, false);
   if (!M->graph_rest) M->graph_rest = capture_step(M, true);
   if (!M->graph_multi && n > GRAPH_STEPS) M->graph_multi = capture_step(M, true, GRAPH_STEPS);
-  // the first step's input state is not averaged; then GRAPH_STEPS steps per launch
+  const bool pending = M->forces_pending;
   auto launch_steps = [&] {
-    hip_check(hipGraphLaunch(M->graph_first, M->stream), "graph launch");
+    hip_check(hipGraphLaunch(pending ? M->graph_rest : M->graph_first, M->stream), "graph launch");
     int64_t left = n - 1;
     for (; left >= GRAPH_STEPS && M->graph_multi; left -= GRAPH_STEPS)
       hip_check(hipGraphLaunch(M->graph_multi, M->stream), "graph launch");
@@ -1534,31 +1576,15 @@ void step_async(fr_mesh *M, int64_t n, bool clear_flag = true) {
   if (M->mixed()) {
     for (auto &G : M->groups) {
       if (clear_flag) hip_check(launch_clear_flag(G->cfg, G->a), "clear flag");
-      lk(G.get(), K_INTERP, 0, 0, false);
+      if (!M->trace_valid) lk(G.get(), K_INTERP, 0, 0, false);
     }
-    launch_steps();
-    if (M->nwall > 0) {  // wall force of the final state
-      for (auto &G : M->groups)
-        if (G->nwall > 0) {
-          lk(G.get(), K_STAGE_A, 0, 0, true);
-          hip_check(launch_force_reduce(G->cfg, G->a), "force reduce");
-        }
-    }
-    return;
+  } else {
+    if (clear_flag) hip_check(launch_clear_flag(M->cfg, M->a), "clear flag");
+    if (!M->trace_valid) lk(M, K_INTERP, 0, 0, false);
   }
-  if (clear_flag) hip_check(launch_clear_flag(M->cfg, M->a), "clear flag");
-  lk(M, K_INTERP, 0, 0, false);
   launch_steps();
-  if (M->nwall > 0) {  // wall force of the final state
-    if (M->cfg.variant_mask & FUSED) {
-      lk(M, K_STAGE_A, 0, 0, true);
-    } else {
-      lk(M, K_FACE, 0, 0, false);
-      lk(M, K_GRAD, 0, 0, false);
-      lk(M, K_VISC, 0, 0, true);
-    }
-    hip_check(launch_force_reduce(M->cfg, M->a), "force reduce");
-  }
+  M->trace_valid = true;
+  M->forces_pending = M->nwall > 0;
 }
 
 void sync_check(fr_mesh *M) {
@@ -1716,6 +1742,7 @@ fr_status fr_set_state(fr_mesh *m, const double *u) {
         if (st != FR_OK) fail(st, g_err);
       }
       m->state_set = true;
+      m->trace_valid = m->forces_pending = false;
       return;
     }
     hip_check(hipSetDevice(m->device), "hipSetDevice");
@@ -1725,6 +1752,7 @@ fr_status fr_set_state(fr_mesh *m, const double *u) {
     hip_check(hipMemsetAsync(m->a.fsum, 0, m->designs.size() * 8 * sizeof(double), m->stream), "clear sums");
     hip_check(hipStreamSynchronize(m->stream), "set state");
     m->state_set = true;
+    m->trace_valid = m->forces_pending = false;
   });
 }
 
@@ -1775,6 +1803,7 @@ fr_status fr_step(fr_mesh *m, int64_t n) {
 fr_status fr_forces(const fr_mesh *m, int32_t design, double *out) {
   return guarded([&] {
     if (!m || !out || design < 0 || design >= int(m->designs.size())) fail(FR_E_ARG, "bad argument");
+    flush_forces(const_cast<fr_mesh *>(m));  // the sums are read on the same stream
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (m->mixed()) {  // the design's wall sums in every group add up; their step counts agree
       for (size_t g = 0; g < m->groups.size(); ++g) {
@@ -1815,6 +1844,7 @@ fr_status fr_residual(fr_mesh *m, const double *u, double *r) {
   return guarded([&] {
     if (!m || !u || !r) fail(FR_E_ARG, "null argument");
     hip_check(hipSetDevice(m->device), "hipSetDevice");
+    release_trace(m);  // the residual's input takes the trace arrays
     if (m->mixed()) {
       std::vector<std::vector<double>> ug(m->groups.size());
       for (size_t g = 0; g < m->groups.size(); ++g) {
@@ -1860,6 +1890,7 @@ fr_status fr_state_device(const fr_mesh *m, void **ptr, int64_t *bytes) {
   return guarded([&] {
     if (!m || !ptr || !bytes) fail(FR_E_ARG, "null argument");
     if (m->mixed()) fail(FR_E_UNSUPPORTED, "a variable-order state lives in several arrays");
+    release_trace(const_cast<fr_mesh *>(m));  // the caller may write the state through it
     *ptr = m->a.U;
     *bytes = int64_t(m->nblk) * m->dm.nup * m->dm.nv * EB * int64_t(m->real_size());
   });
@@ -1880,6 +1911,7 @@ fr_status fr_select_kernels(fr_mesh *m, int32_t mask) {
       fail(FR_E_UNSUPPORTED, "tile shapes other than the default exist for 3D meshes of order 1 to 4 only");
     if ((unsigned(mask) & SCATTER_EXCHANGE) && !(unsigned(mask) & FUSED))
       fail(FR_E_UNSUPPORTED, "the exchange by scatter belongs to the fused stage");
+    release_trace(m);  // the trace layout may change with the structure (exchange by scatter)
     m->cfg.variant_mask = unsigned(mask) & (FUSED | (1u << K_INTERP) | (1u << K_GRAD) | (1u << K_VISC) |
                                             (1u << K_DIVRK) | STORED_METRICS | NO_XCD_REMAP | EXTRUDED_METRICS |
                                             TILE_BITS | SCATTER_EXCHANGE);
@@ -1903,6 +1935,7 @@ fr_status fr_autotune(fr_mesh *m, int64_t steps, int32_t *mask_out) {
       return;
     }
     hip_check(hipSetDevice(m->device), "hipSetDevice");
+    release_trace(m);  // the timed steps run on a copy of the state and leave their own trace
     const size_t nb = size_t(m->nblk) * m->dm.nup * m->dm.nv * EB * m->real_size();
     // keep the state: time on a copy, restore it afterwards
     hip_check(hipMemcpyAsync(m->a.RES, m->a.U, nb, hipMemcpyDeviceToDevice, m->stream), "save state");
@@ -1985,6 +2018,7 @@ fr_status fr_profile_kernels(fr_mesh *m, int64_t steps, double *ms, int64_t *lau
     if (m->mixed()) fail(FR_E_UNSUPPORTED, "per-kernel profile of a variable-order mesh");
     if (!m->state_set) fail(FR_E_STATE, "no state set");
     hip_check(hipSetDevice(m->device), "hipSetDevice");
+    release_trace(m);  // the profiled steps advance the state and leave no force sums
     profile_steps(m, steps, ms, launches);
   });
 }
@@ -2332,6 +2366,7 @@ fr_status fr::means_clear(::fr_mesh *m) {
   return guarded([&] {
     if (!m) fail(FR_E_ARG, "null mesh");
     hip_check(hipSetDevice(m->device), "hipSetDevice");
+    m->forces_pending = false;  // the current state is not part of the new means
     if (m->mixed()) {  // every order group keeps its own wall sums
       for (auto &G : m->groups)
         hip_check(hipMemsetAsync(G->a.fsum, 0, G->designs.size() * 8 * sizeof(double), m->stream), "clear sums");

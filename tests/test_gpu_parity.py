@@ -261,6 +261,43 @@ def test_set_get_roundtrip_and_resume_bit_identical():
     assert np.array_equal(g.get_state(), a)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("orders", ["uniform", "p3_to_p0"])
+def test_steps_split_across_calls_bit_identical(prec, orders):
+    """Nine steps in one call, or split over five calls with reads of the forces and the
+    state, a residual evaluation and a re-selected kernel structure between them: the same
+    state, instantaneous forces, running means and averaged-step count, bit for bit. A call
+    reuses the trace the previous step left, and the wall forces of a call's last state
+    are added in the next call's first stage, or when they are read first."""
+    ni, nj, nk = 16, 4, 2
+    m = W.config_airfoil(4, ni=ni, nj=nj, nk=nk)
+    if orders != "uniform":
+        m["orders"] = W.ring_orders(ni, nj, nk, ((1, 3), (2, 2), (3, 1), (4, 0)))
+    g = FRMesh(m, prec)
+    u0 = np.ascontiguousarray(m["init"](g.solution_points().reshape(-1, 3)).reshape(g.shape))
+    u0 = u0 * (1.0 + 0.02 * np.random.default_rng(3).standard_normal(u0.shape))
+    g.set_state(u0)
+    g.step(9)
+    ua, fa = g.get_state(), g.forces()
+    assert fa[7] == 9
+    g.set_state(u0)
+    g.step(2)
+    assert g.forces()[7] == 2
+    g.step(1)
+    g.get_state()
+    g.residual(u0)
+    g.step(4)
+    if orders == "uniform":
+        g.select_kernels(g.selected_kernels())
+    g.step_async(1)
+    g.step(1)
+    ub, fb = g.get_state(), g.forces()
+    print(f"{orders} {prec}: forces {fb[:2]}, means {fb[5:7]}, count {fb[7]:.0f}")
+    assert np.array_equal(ua, ub)
+    assert np.array_equal(fa, fb)
+    g.close()
+
+
 def test_nonfinite_state_is_reported():
     m = W.config_vortex(1)
     g = FRMesh(m, "fp32")
