@@ -291,6 +291,21 @@ __device__ inline size_t at(int64_t blk, int pt, int ch, int e, int NPT, int NCH
   return lay(blk, pt, ch, e, NPT, NCH);
 }
 
+// The same arrays addressed as the block's base (wave-uniform: scalar registers) plus a
+// 32-bit byte offset per lane within the block, so that loads and stores take the
+// global "scalar base + vector offset" form instead of 64-bit address arithmetic in
+// every lane. One block of any per-element array spans far less than 4 GiB.
+template <typename T> __device__ inline T *blk_base(T *p, int64_t blk, int NPT, int NCH) {
+  return p + size_t(blk) * size_t(NSB * NPT * NCH * SB);
+}
+__device__ inline unsigned lay_in(int pt, int ch, int e, int NPT, int NCH) {
+  return ((unsigned(e) / SB * unsigned(NPT) + unsigned(pt)) * unsigned(NCH) + unsigned(ch)) * SB + unsigned(e) % SB;
+}
+template <typename T> __device__ inline T &in_blk(T *base, unsigned off) {
+  using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return *reinterpret_cast<T *>(reinterpret_cast<C *>(base) + off * unsigned(sizeof(T)));
+}
+
 // ---------------------------------------------------------------------------
 // reference-element index maps (conventions of include/fr.h)
 // ---------------------------------------------------------------------------
@@ -1104,6 +1119,13 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   const int nvalid = a.bcount[blk];
   if (e0 >= nvalid) return;
   const int tid = threadIdx.x;
+  // this block's part of the per-element arrays (uniform); lanes add 32-bit offsets
+  const int *NBb = blk_base(a.NB, blk, S::NFPAD, 1);
+  const T *UFb = blk_base<const T>(a.UF, blk, S::NFPAD, NV);
+  const double *FCXb = blk_base(a.FCX, blk, NFC, 2), *XCb = blk_base(a.XC, blk, NCOL, 4);
+  const double *ZZb = blk_base(a.ZZ, blk, N, 1);
+  T *PVb = blk_base(a.PV, blk, S::NFPAD, NV), *FIb = blk_base(a.FI, blk, S::NFPAD, NV);
+  T *FTb = blk_base(a.FT, blk, S::NUP, NV);
 
   // ---- prefetch in the order of first use: basis, neighbour codes, stage state,
   // normals, partner traces (once the codes are back); the metrics of the solution
@@ -1131,7 +1153,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
-    nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
+    nbv[it] = in_blk(NBb, lay_in(q, 0, eg, S::NFPAD, 1));
   }
   T ust[SI];
   const T *Xb = X + size_t(blk) * S::NUP * NV * EB;
@@ -1139,7 +1161,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
   for (int r = 0; r < SI; ++r) {
     const int t = min(tid + r * WG, S::NU * NV * EW - 1);
     const int e = e0 + t % EW;
-    ust[r] = Xb[(size_t(e / SB) * S::NUP * NV + t / EW) * SB + e % SB];
+    ust[r] = in_blk(Xb, (unsigned(e) / SB * (S::NUP * NV) + unsigned(t) / EW) * SB + unsigned(e) % SB);
   }
   double nrd[FI][DIM], Av[FI];
   double fcv[EXTR ? FI : 1][2], fzv[EXTR ? FI : 1];  // column metrics of the flux point's face
@@ -1149,9 +1171,9 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
       const int f = face_of<S::NFP, EW>(q), m = q % S::NFP, k = f / 2, sd = f & 1;
       const int col = k == 0 ? sd * N + m % N : (k == 1 ? 2 * N + sd * N + m % N : 4 * N + m);
-      fcv[it][0] = a.FCX[lay(blk, col, 0, eg, NFC, 2)];
-      fcv[it][1] = a.FCX[lay(blk, col, 1, eg, NFC, 2)];
-      fzv[it] = a.ZZ[lay(blk, m / N, 0, eg, N, 1)];
+      fcv[it][0] = in_blk(FCXb, lay_in(col, 0, eg, NFC, 2));
+      fcv[it][1] = in_blk(FCXb, lay_in(col, 1, eg, NFC, 2));
+      fzv[it] = in_blk(ZZb, lay_in(m / N, 0, eg, N, 1));
     }
   } else if constexpr (!NODEM) {
 #pragma unroll
@@ -1170,7 +1192,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       // the partner's trace, written into this slot (never used at a boundary point)
       const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) ur[it][v] = a.UF[at(blk, q, v, eg, S::NFPAD, NV)];
+      for (int v = 0; v < NV; ++v) ur[it][v] = in_blk(UFb, lay_in(q, v, eg, S::NFPAD, NV));
     } else if (MORTAR && nb < 0 && ((-nb) & 3) == BC_MORTAR) {
       // the other side's trace at this point: its face points' traces interpolated
       // (higher-order side) or projected (lower-order side)
@@ -1190,8 +1212,8 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
     for (int it = 0; it < PI; ++it) {
       const int t = tid + it * WG, i = min(t / EW, S::NU - 1), eg = e0 + t % EW;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) xcv[it][c] = a.XC[lay(blk, i % NCOL, c, eg, NCOL, 4)];
-      zzv[it] = a.ZZ[lay(blk, i / NCOL, 0, eg, N, 1)];
+      for (int c = 0; c < 4; ++c) xcv[it][c] = in_blk(XCb, lay_in(i % NCOL, c, eg, NCOL, 4));
+      zzv[it] = in_blk(ZZb, lay_in(i / NCOL, 0, eg, N, 1));
     }
   } else if constexpr (!NODEM) {
 #pragma unroll
@@ -1537,14 +1559,19 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
     if (nb >= 0 || (MORTAR && ((-nb) & 3) == BC_MORTAR)) {
       gas.flux_vis_n(ufv[it], gf, nrm[it], fn, false);
       // P to the partner's slot (exchange by scatter) or to this one
-      const size_t pbase = SCAT ? size_t(nb / SB) * NV * SB + (nb % SB) : at(blk, q, 0, eg, S::NFPAD, NV);
+      T *pdst = SCAT ? a.PV + (size_t(nb / SB) * NV * SB + (nb % SB)) : nullptr;
+      const unsigned own = lay_in(q, 0, eg, S::NFPAD, NV);
       const T Af = T(Av[it]);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const T pv = T(0.5) * fn[v];
         const T qv = (FQL ? Lq[(q * NV + v) * EW + e] : fiv[it][v]) - pv;
-        a.PV[pbase + v * SB] = SCALED ? (MP32 ? Af * pv : T(Av[it] * double(pv))) : pv;
-        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = SCALED ? (MP32 ? Af * qv : T(Av[it] * double(qv))) : qv;
+        const T ps = SCALED ? (MP32 ? Af * pv : T(Av[it] * double(pv))) : pv;
+        if constexpr (SCAT)
+          pdst[v * SB] = ps;
+        else
+          in_blk(PVb, own + v * SB) = ps;
+        in_blk(FIb, own + v * SB) = SCALED ? (MP32 ? Af * qv : T(Av[it] * double(qv))) : qv;
       }
     } else {
       const int code = -nb;
@@ -1559,7 +1586,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const T qv = (FQL ? Lq[(q * NV + v) * EW + e] : fiv[it][v]) - fn[v];
-        a.FI[at(blk, q, v, eg, S::NFPAD, NV)] = SCALED ? (MP32 ? T(Av[it]) * qv : T(Av[it] * double(qv))) : qv;
+        in_blk(FIb, lay_in(q, v, eg, S::NFPAD, NV)) = SCALED ? (MP32 ? T(Av[it]) * qv : T(Av[it] * double(qv))) : qv;
       }
       if (forces && (code & 3) == BC_WALL) {
         // traction of the fluid on the body: W A (p n - tau . n), interior trace
@@ -1632,7 +1659,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
         T div = 0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) div += Pk[((k * S::NU + i) * NV + v) * EW + e];
-        a.FT[at(blk, i, v, eg, S::NUP, NV)] = div;
+        in_blk(FTb, lay_in(i, v, eg, S::NUP, NV)) = div;
       }
     }
     return;
@@ -1659,7 +1686,7 @@ void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
       }
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) a.FT[at(blk, i, v, eg, S::NUP, NV)] = div[v];
+    for (int v = 0; v < NV; ++v) in_blk(FTb, lay_in(i, v, eg, S::NUP, NV)) = div[v];
   }
 }
 
@@ -1691,6 +1718,16 @@ void k_stage_b(KArgs<T> a) {
   const int nvalid = a.bcount[blk];
   if (e0 >= nvalid) return;
   const int tid = threadIdx.x;
+  // this block's part of the per-element arrays (uniform); lanes add 32-bit offsets
+  const int *NBb = blk_base(a.NB, blk, S::NFPAD, 1), *NBFb = blk_base(a.NBF, blk, 2 * DIM, 1);
+  const double *FAb = blk_base(a.FA, blk, S::NFPAD, 1);
+  const T *FIb = blk_base<const T>(a.FI, blk, S::NFPAD, NV), *PVb = blk_base<const T>(a.PV, blk, S::NFPAD, NV);
+  const T *FTb = blk_base<const T>(a.FT, blk, S::NUP, NV);
+  T *Ub = blk_base(a.U, blk, S::NUP, NV), *USb = blk_base(a.US, blk, S::NUP, NV);
+  T *ACCb = blk_base(a.ACC, blk, S::NUP, NV), *RESb = blk_base(a.RES, blk, S::NUP, NV);
+  T *UFb = blk_base(a.UF, blk, S::NFPAD, NV);
+  const double *IJCb = blk_base(a.IJC, blk, S::N * S::N, 1), *IZb = blk_base(a.IZ, blk, S::N, 1);
+  const double *IJb = blk_base(a.IJ, blk, S::NUP, 1);
   const T dt = T(a.bdt[blk]);
 
   // ---- prefetch in the order of first use: basis, face inputs (codes first, so that
@@ -1712,18 +1749,18 @@ void k_stage_b(KArgs<T> a) {
     if (!SKIP || (t < S::NF * EW && eg < nvalid)) {
       // per-face codes where the mesh has them (24 B per element in 3D instead of 384)
       if (!MORTAR && a.NBF)
-        nbv[it] = point_code(a.NBF[lay(blk, q / S::NFP, 0, eg, 2 * DIM, 1)], q % S::NFP, N, S::NFP, S::NFPAD, DIM);
+        nbv[it] = point_code(in_blk(NBFb, lay_in(q / S::NFP, 0, eg, 2 * DIM, 1)), q % S::NFP, N, S::NFP, S::NFPAD, DIM);
       else
-        nbv[it] = a.NB[lay(blk, q, 0, eg, S::NFPAD, 1)];
+        nbv[it] = in_blk(NBb, lay_in(q, 0, eg, S::NFPAD, 1));
     }
   }
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
     if (!SKIP || (t < S::NF * EW && eg < nvalid)) {
-      Av[it] = NODEM ? 1.0 : a.FA[lay(blk, q, 0, eg, S::NFPAD, 1)];
+      Av[it] = NODEM ? 1.0 : in_blk(FAb, lay_in(q, 0, eg, S::NFPAD, 1));
 #pragma unroll
-      for (int v = 0; v < NV; ++v) qv[it][v] = a.FI[at(blk, q, v, eg, S::NFPAD, NV)];
+      for (int v = 0; v < NV; ++v) qv[it][v] = in_blk(FIb, lay_in(q, v, eg, S::NFPAD, NV));
     }
   }
 #pragma unroll
@@ -1733,7 +1770,7 @@ void k_stage_b(KArgs<T> a) {
       const int t = tid + it * WG, q = min(t / EW, S::NF - 1), eg = e0 + t % EW;
       if (!SKIP || (t < S::NF * EW && eg < nvalid)) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) pn[it][v] = a.PV[at(blk, q, v, eg, S::NFPAD, NV)];
+        for (int v = 0; v < NV; ++v) pn[it][v] = in_blk(PVb, lay_in(q, v, eg, S::NFPAD, NV));
       }
     } else if (MORTAR && nb < 0 && ((-nb) & 3) == BC_MORTAR) {
       const int64_t pt = (-nb) >> 3;
@@ -1771,14 +1808,15 @@ void k_stage_b(KArgs<T> a) {
   for (int it = 0; it < PI; ++it) {
     const int t = tid + it * WG, i = min(t / EW, S::NU - 1), eg = e0 + t % EW;
     if (!SKIP || (t < S::NU * EW && eg < nvalid)) {
-      ijv[it] = COLJ ? a.IJC[lay(blk, i % (S::N * S::N), 0, eg, S::N * S::N, 1)] * a.IZ[lay(blk, i / (S::N * S::N), 0, eg, S::N, 1)]
-                     : a.IJ[lay(blk, i, 0, eg, S::NUP, 1)];
+      ijv[it] = COLJ ? in_blk(IJCb, lay_in(i % (S::N * S::N), 0, eg, S::N * S::N, 1)) *
+                           in_blk(IZb, lay_in(i / (S::N * S::N), 0, eg, S::N, 1))
+                     : in_blk(IJb, lay_in(i, 0, eg, S::NUP, 1));
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const size_t x = at(blk, i, v, eg, S::NUP, NV);
-        rv[it][v] = a.FT[x];
-        un[it][v] = mode == MODE_RESID ? T(0) : a.U[x];
-        ac[it][v] = (mode == MODE_RK1 || mode == MODE_RK2 || mode == MODE_RK3) ? a.ACC[x] : T(0);
+        const unsigned x = lay_in(i, v, eg, S::NUP, NV);
+        rv[it][v] = in_blk(FTb, x);
+        un[it][v] = mode == MODE_RESID ? T(0) : in_blk(Ub, x);
+        ac[it][v] = (mode == MODE_RK1 || mode == MODE_RK2 || mode == MODE_RK3) ? in_blk(ACCb, x) : T(0);
       }
     }
   }
@@ -1843,27 +1881,27 @@ void k_stage_b(KArgs<T> a) {
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const size_t x = at(blk, i, v, eg, S::NUP, NV);
+      const unsigned x = lay_in(i, v, eg, S::NUP, NV);
       // FP32 form: 1/|J| rounded once, the product in FP32
       const T r = sizeof(T) == 4 ? -div[v] * T(ijv[it]) : T(-double(div[v]) * ijv[it]);
       T next = 0;
       if (mode == MODE_RESID) {
-        a.RES[x] = r;
+        in_blk(RESb, x) = r;
       } else if (mode == MODE_RK0) {
-        a.ACC[x] = r;
+        in_blk(ACCb, x) = r;
         next = un[it][v] + T(0.5) * dt * r;
-        a.US[x] = next;
+        in_blk(USb, x) = next;
       } else if (mode == MODE_RK1) {
-        a.ACC[x] = ac[it][v] + T(2) * r;
+        in_blk(ACCb, x) = ac[it][v] + T(2) * r;
         next = un[it][v] + T(0.5) * dt * r;
-        a.US[x] = next;
+        in_blk(USb, x) = next;
       } else if (mode == MODE_RK2) {
-        a.ACC[x] = ac[it][v] + T(2) * r;
+        in_blk(ACCb, x) = ac[it][v] + T(2) * r;
         next = un[it][v] + dt * r;
-        a.US[x] = next;
+        in_blk(USb, x) = next;
       } else {
         next = un[it][v] + dt / T(6) * (ac[it][v] + r);
-        a.U[x] = next;
+        in_blk(Ub, x) = next;
         bad |= !isfinite(next);
       }
       Un[(i * NV + v) * EW + e] = next;
@@ -1882,14 +1920,17 @@ void k_stage_b(KArgs<T> a) {
     if (SCAT && nbv[it] < 0) continue;  // a boundary point has no partner to receive it
     const int f = q / S::NFP, m = q % S::NFP, k = f / 2;
     const T *l = (f & 1) ? B.lp : B.lm;
-    const size_t ubase =
-        SCAT ? size_t(nbv[it] / SB) * NV * SB + (nbv[it] % SB) : at(blk, q, 0, eg, S::NFPAD, NV);
+    T *pdst = SCAT ? a.UF + (size_t(nbv[it] / SB) * NV * SB + (nbv[it] % SB)) : nullptr;
+    const unsigned own = lay_in(q, 0, eg, S::NFPAD, NV);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       T sv = 0;
 #pragma unroll
       for (int j = 0; j < N; ++j) sv += l[j] * Un[(Ref<DIM, N>::line(k, m, j) * NV + v) * EW + e];
-      a.UF[ubase + v * SB] = sv;
+      if constexpr (SCAT)
+        pdst[v * SB] = sv;
+      else
+        in_blk(UFb, own + v * SB) = sv;
     }
   }
 
