@@ -203,8 +203,10 @@ fr_status fr_sync(fr_mesh *m);
  * Lift and drag come from the wall traction integral of (p n - tau . n),
  * with p and the stress tau of Eqs. (5)-(6) of Section 2.1; the means are
  * the time-averaged lift and drag coefficients of the objective of Section
- * 3.4 (summed in FP64).  out is host memory of 8 doubles; FR_E_ARG for a
- * design index outside the batch. */
+ * 3.4 (summed in FP64).  If the wall forces of the last step's state are
+ * not yet in the sums (fr_step adds them in the next step), this call first
+ * runs their force pass on the mesh's stream.  out is host memory of 8
+ * doubles; FR_E_ARG for a design index outside the batch. */
 fr_status fr_forces(const fr_mesh *m, int32_t design, double *out);
 
 /* Test hook: R(u) = du/dt of the semi-discretisation, i.e. -div F of Eq. (1)
