@@ -30,3 +30,19 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], capture_output=True, text=True,
                        cwd=bench.ROOT, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_counter_traffic_is_tied_to_the_variant_it_was_taken_on():
+    """The committed batch counters cover the gather exchange with the default tiles and
+    column metrics (variant mask 417); any other variant reports no counter traffic."""
+    assert bench.stage_kernel_name("k_stage_a", 417) == "k_stage_a<float, 3, 3, 3, 0, false>"
+    assert bench.stage_kernel_name("k_stage_b", 417 | (2 << 11)) == "k_stage_b<float, 3, 3, 0, 3, 2, false>"
+    assert bench.stage_kernel_name("k_stage_a", 417 | (1 << 13)) == "k_stage_a<float, 3, 3, 3, 0, true>"
+    assert bench.stage_kernel_name("k_stage_b", 1 | (1 << 6)) == "k_stage_b<float, 3, 3, 0, 1, 0, false>"
+    for kernel in ("k_stage_a", "k_stage_b"):
+        t = bench.counters_traffic("batch", kernel, 417)
+        if t is None:
+            pytest.skip("the committed counters were taken on another kernel source")
+        assert t > 0
+        assert bench.counters_traffic("batch", kernel, 417 | (1 << 13)) is None
+        assert bench.counters_traffic("batch", kernel, 417 | (1 << 9) | (1 << 11)) is None
