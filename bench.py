@@ -136,22 +136,27 @@ def stage_kernel_name(kernel, mask, real="float", dim=3, order=3):
 
 def counters_traffic(workload, kernel, mask=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or
-    None if it is missing, the kernel source changed since it was taken, or (given the
-    selected variant mask) the counters were taken on another variant of the kernel."""
+    None if it is missing or the kernel source changed since it was taken. Given the
+    selected variant mask, the entry taken on that variant (the entries of a kernel are
+    keyed `kernel` and `kernel_<variant>`, each with the kernel names it matched), else
+    None."""
     import re
     path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
     try:
-        data = json.load(open(path))
+        data = json.load(open(path)).get(workload, {})
         src = open(os.path.join(ROOT, "paper_2501_05709_amd", "csrc", "fr_kernels.hip"), "rb").read()
         sha = hashlib.sha256(src).hexdigest()
-        entry = data.get(workload, {}).get(kernel)
-        if not entry or entry.get("source_sha256") != sha:
-            return None
-        if mask is not None and not re.search(entry.get("kernel_match", ""), stage_kernel_name(kernel, mask)):
-            return None
-        return entry.get("hbm_bytes_per_launch")
+        keys = [kernel] if mask is None else [k for k in sorted(data) if k == kernel or k.startswith(kernel + "_")]
+        for key in keys:
+            entry = data.get(key)
+            if not entry or entry.get("source_sha256") != sha:
+                continue
+            if mask is not None and not re.search(entry.get("kernel_match", ""), stage_kernel_name(kernel, mask)):
+                continue
+            return entry.get("hbm_bytes_per_launch")
+        return None
     except Exception:
         return None
 

@@ -33,8 +33,9 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_counter_traffic_is_tied_to_the_variant_it_was_taken_on():
-    """The committed batch counters cover the gather exchange with the default tiles and
-    column metrics (variant mask 417); any other variant reports no counter traffic."""
+    """The committed batch counters cover the gather exchange on column metrics (variant mask
+    417) with the default tiles, the second launch's half tile and the matrix-core first
+    launch; any other variant reports no counter traffic."""
     assert bench.stage_kernel_name("k_stage_a", 417) == "k_stage_a<float, 3, 3, 3, 0, false>"
     assert bench.stage_kernel_name("k_stage_b", 417 | (2 << 11)) == "k_stage_b<float, 3, 3, 0, 3, 2, false>"
     assert bench.stage_kernel_name("k_stage_a", 417 | (1 << 13)) == "k_stage_a<float, 3, 3, 3, 0, true>"
@@ -45,4 +46,8 @@ def test_counter_traffic_is_tied_to_the_variant_it_was_taken_on():
             pytest.skip("the committed counters were taken on another kernel source")
         assert t > 0
         assert bench.counters_traffic("batch", kernel, 417 | (1 << 13)) is None
-        assert bench.counters_traffic("batch", kernel, 417 | (1 << 9) | (1 << 11)) is None
+        assert bench.counters_traffic("batch", kernel, 417 | (2 << 9) | (2 << 11)) is None
+    # the second launch's half tile and the matrix-core first launch have entries of their own
+    b1 = bench.counters_traffic("batch", "k_stage_b", 417 | (1 << 11))
+    a3 = bench.counters_traffic("batch", "k_stage_a", 417 | (3 << 9))
+    assert b1 and a3 and b1 != bench.counters_traffic("batch", "k_stage_b", 417)
