@@ -1008,7 +1008,9 @@ __device__ inline int64_t xcd_remap(int64_t wg, int64_t nwg) {
   return wg < full ? (wg % 8) * (nwg / 8) + wg / 8 : wg;
 }
 
-enum { FV_NODE = 0, FV_STORED = 1, FV_MORTAR = 2, FV_EXTR = 3 };
+enum { FV_NODE = 0, FV_STORED = 1, FV_MORTAR = 2, FV_EXTR = 3, FV_MORTAR_EXTR = 4 };
+// an order group of a variable-order mesh (mortar points), with stored or column metrics
+template <int FV> constexpr bool mortar_fv() { return FV == FV_MORTAR || FV == FV_MORTAR_EXTR; }
 
 // Tile shapes of the fused stage, one per launch (picked by the autotuner): TILE_DEFAULT
 // sizes the workgroup from the LDS budgets below; TILE_HALF and TILE_QUARTER give it a
@@ -1055,7 +1057,11 @@ template <typename T, int DIM, int ORDER, int TILE = TILE_DEFAULT> struct FS {
 // variable-order mesh with mortar points (stored metrics); FV_EXTR, a mesh of z-extruded
 // elements, forms S, 1/|J|, normals and area factors from its column metrics (the 2D
 // Jacobian at the n^2 solution-point columns, z_zeta at the n layers, the face columns)
-// with a few FP64 products, and scales the half fluxes as FV_NODE does.
+// with a few FP64 products, and scales the half fluxes as FV_NODE does. FV_MORTAR_EXTR is an
+// order group on z-extruded elements: the first launch forms its metrics from the column
+// data as FV_EXTR does but stores Q and P unscaled, as the mortar interpolation and
+// projection take them; the second launch scales them by the stored face areas and takes
+// 1/|J| from the column factors.
 template <typename T, int DIM, int ORDER, int FV, int TILE = TILE_DEFAULT> struct NodeMetrics {
   using S = Shape<DIM, ORDER>;
   using F = FS<T, DIM, ORDER, TILE>;
@@ -1082,14 +1088,14 @@ template <typename T, int DIM, int ORDER, int FV, int TILE, bool SCAT>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (NodeMetrics<T, DIM, ORDER, FV>::ON ? 3 : 4) : 2, 8)))
 void k_stage_a(KArgs<T> a, const T *__restrict__ X, int forces) {
-  constexpr bool MORTAR = FV == FV_MORTAR;
+  constexpr bool MORTAR = mortar_fv<FV>();
   static_assert(!(SCAT && MORTAR), "mortar faces exchange by gather");
   using S = Shape<DIM, ORDER>;
   using F = FS<T, DIM, ORDER, TILE>;
   using NM = NodeMetrics<T, DIM, ORDER, FV, TILE>;
   constexpr bool NODEM = NM::ON;
-  constexpr bool EXTR = DIM == 3 && FV == FV_EXTR;
-  constexpr bool SCALED = NODEM || EXTR;  // Q and P stored times the area factor
+  constexpr bool EXTR = DIM == 3 && (FV == FV_EXTR || FV == FV_MORTAR_EXTR);
+  constexpr bool SCALED = NODEM || (EXTR && !MORTAR);  // Q and P stored times the area factor
   // FP32 form: metric factors (formed in FP64) rounded to FP32 once per point or flux
   // point, products in FP32
   constexpr bool MP32 = sizeof(T) == 4;
@@ -1698,15 +1704,16 @@ template <typename T, int DIM, int ORDER, int MODE, int FV, int TILE, bool SCAT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 2, 8)))
 void k_stage_b(KArgs<T> a) {
   constexpr int mode = MODE;  // RK stage or residual: fixes what is read and written
-  constexpr bool MORTAR = FV == FV_MORTAR;
+  constexpr bool MORTAR = mortar_fv<FV>();
   static_assert(!(SCAT && MORTAR), "mortar faces exchange by gather");
   using S = Shape<DIM, ORDER>;
   using F = FS<T, DIM, ORDER, TILE>;
   // the first launch stored the half fluxes times the area factor (metrics from the
   // geometry nodes or the extruded columns); with the columns, 1/|J| is the product of
   // the column's and the layer's reciprocal factors (FP64)
-  constexpr bool COLJ = DIM == 3 && FV == FV_EXTR;
-  constexpr bool NODEM = NodeMetrics<T, DIM, ORDER, FV>::ON || COLJ;
+  constexpr bool COLJ = DIM == 3 && (FV == FV_EXTR || FV == FV_MORTAR_EXTR);
+  // NODEM: the first launch stored Q and P times the area factor
+  constexpr bool NODEM = NodeMetrics<T, DIM, ORDER, FV>::ON || (COLJ && !MORTAR);
   constexpr int EW = F::EW_B, WG = F::WG_B, NS = EB / EW, N = S::N, NV = S::NV;
   constexpr int FI = (S::NF * EW + WG - 1) / WG, PI = (S::NU * EW + WG - 1) / WG;
   __shared__ T Cs[S::NF * NV * EW];
@@ -2069,7 +2076,7 @@ static void go_stage_a(const LaunchCfg &c, const KArgs<T> &a, const T *X, bool f
 }
 
 // tile shapes other than the default are compiled for 3D one-order meshes of order 1 up
-template <int DIM, int ORDER, int FV> constexpr bool tiled() { return DIM == 3 && ORDER >= 1 && FV != FV_MORTAR; }
+template <int DIM, int ORDER, int FV> constexpr bool tiled() { return DIM == 3 && ORDER >= 1 && !mortar_fv<FV>(); }
 
 template <typename T, int DIM, int ORDER, int FV, bool SCAT>
 static void launch_stage_a_tiles(const LaunchCfg &c, const KArgs<T> &a, const T *X, bool forces) {
@@ -2090,7 +2097,7 @@ static void launch_stage_a_tiles(const LaunchCfg &c, const KArgs<T> &a, const T 
 // the exchange by scatter exists for one-order meshes (no mortar faces)
 template <typename T, int DIM, int ORDER, int FV>
 static void launch_stage_a(const LaunchCfg &c, const KArgs<T> &a, const T *X, bool forces) {
-  if constexpr (FV != FV_MORTAR)
+  if constexpr (!mortar_fv<FV>())
     if (c.variant_mask & SCATTER_EXCHANGE) return launch_stage_a_tiles<T, DIM, ORDER, FV, true>(c, a, X, forces);
   launch_stage_a_tiles<T, DIM, ORDER, FV, false>(c, a, X, forces);
 }
@@ -2125,7 +2132,7 @@ static hipError_t launch_stage_b_tiles(const LaunchCfg &c, int mode, const KArgs
 
 template <typename T, int DIM, int ORDER, int FV>
 static hipError_t launch_stage_b(const LaunchCfg &c, int mode, const KArgs<T> &a) {
-  if constexpr (FV != FV_MORTAR)
+  if constexpr (!mortar_fv<FV>())
     if (c.variant_mask & SCATTER_EXCHANGE) return launch_stage_b_tiles<T, DIM, ORDER, FV, true>(c, mode, a);
   return launch_stage_b_tiles<T, DIM, ORDER, FV, false>(c, mode, a);
 }
@@ -2169,7 +2176,9 @@ static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, i
                            int(forces));
       break;
     case K_STAGE_A:
-      if (d.MO)
+      if (d.MO && DIM == 3 && (c.variant_mask & EXTRUDED_METRICS) && d.XC && d.IJC)
+        launch_stage_a<T, DIM, ORDER, DIM == 3 ? FV_MORTAR_EXTR : FV_MORTAR>(c, a, X, forces);
+      else if (d.MO)
         launch_stage_a<T, DIM, ORDER, FV_MORTAR>(c, a, X, forces);
       else if (DIM == 3 && (c.variant_mask & EXTRUDED_METRICS) && d.XC)
         launch_stage_a<T, DIM, ORDER, DIM == 3 ? FV_EXTR : FV_STORED>(c, a, X, forces);
@@ -2179,6 +2188,8 @@ static hipError_t launch_t(int kernel, const LaunchCfg &c, const DevArrays &d, i
         launch_stage_a<T, DIM, ORDER, FV_STORED>(c, a, X, forces);
       break;
     case K_STAGE_B:
+      if (d.MO && DIM == 3 && (c.variant_mask & EXTRUDED_METRICS) && d.XC && d.IJC)
+        return launch_stage_b<T, DIM, ORDER, DIM == 3 ? FV_MORTAR_EXTR : FV_MORTAR>(c, mode, a);
       if (d.MO) return launch_stage_b<T, DIM, ORDER, FV_MORTAR>(c, mode, a);
       // the extruded first launch scales the half fluxes by the area factor like FV_NODE,
       // and the second takes 1/|J| from the column factors
