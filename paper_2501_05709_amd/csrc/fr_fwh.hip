@@ -518,8 +518,8 @@ struct fr_fwh {
       if (free) free(p, ctx, stream);
       else (void)hipFree(p);
     }
-    if (ev0) hipEventDestroy(ev0);
-    if (ev1) hipEventDestroy(ev1);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
   }
   // device scratch that grows on demand: partial sums and outputs
   double *grow(double *&p, size_t &have, size_t need) {

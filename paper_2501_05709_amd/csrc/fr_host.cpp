@@ -659,19 +659,20 @@ struct fr_mesh {
     hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, stream), "upload");
     return p;
   }
+  // teardown: errors are not reported from a destructor
   ~fr_mesh() {
-    if (graph_first) hipGraphExecDestroy(graph_first);
-    if (graph_rest) hipGraphExecDestroy(graph_rest);
-    if (graph_multi) hipGraphExecDestroy(graph_multi);
+    if (graph_first) (void)hipGraphExecDestroy(graph_first);
+    if (graph_rest) (void)hipGraphExecDestroy(graph_rest);
+    if (graph_multi) (void)hipGraphExecDestroy(graph_multi);
     groups.clear();  // they run on this handle's stream
-    if (stream) hipStreamSynchronize(stream);
+    if (stream) (void)hipStreamSynchronize(stream);
     for (void *p : allocations) {
       if (dfree)
         dfree(p, alloc_ctx, stream);
       else
-        hipFree(p);
+        (void)hipFree(p);
     }
-    if (own_stream && stream) hipStreamDestroy(stream);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
 
@@ -1449,9 +1450,9 @@ void build_mixed(fr_mesh *M, const fr_mesh_desc *descs, int nd) {
 void profile_steps(fr_mesh *m, int64_t steps, double *ms, int64_t *launches);
 
 void drop_graphs(fr_mesh *M) {
-  if (M->graph_first) hipGraphExecDestroy(M->graph_first);
-  if (M->graph_rest) hipGraphExecDestroy(M->graph_rest);
-  if (M->graph_multi) hipGraphExecDestroy(M->graph_multi);
+  if (M->graph_first) (void)hipGraphExecDestroy(M->graph_first);
+  if (M->graph_rest) (void)hipGraphExecDestroy(M->graph_rest);
+  if (M->graph_multi) (void)hipGraphExecDestroy(M->graph_multi);
   M->graph_first = M->graph_rest = M->graph_multi = nullptr;
 }
 
@@ -1511,14 +1512,14 @@ hipGraphExec_t capture_step(fr_mesh *M, bool forces, int64_t steps = 1) {
   try {
     for (int64_t s = 0; s < steps; ++s) enqueue_step(M, forces);
   } catch (...) {
-    hipStreamEndCapture(M->stream, &g);
-    if (g) hipGraphDestroy(g);
+    (void)hipStreamEndCapture(M->stream, &g);  // the launch error is the one reported
+    if (g) (void)hipGraphDestroy(g);
     throw;
   }
   hip_check(hipStreamEndCapture(M->stream, &g), "end capture");
   hipGraphExec_t ex = nullptr;
   hip_check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate");
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   return ex;
 }
 
@@ -2066,7 +2067,7 @@ void profile_steps(fr_mesh *m, int64_t steps, double *ms, int64_t *launches) {
       launches[kid[i]] += 1;
       launches[0] += 1;
     }
-    for (auto e : ev) hipEventDestroy(e);
+    for (auto e : ev) (void)hipEventDestroy(e);
   }
 }
 }  // namespace

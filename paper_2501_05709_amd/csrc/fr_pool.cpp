@@ -186,7 +186,7 @@ fr_status fr_pool_create(size_t budget, int32_t device, fr_pool **out) {
   for (int i = 0; i < 4; ++i) {
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-      for (auto t : p->streams) hipStreamDestroy(t);
+      for (auto t : p->streams) (void)hipStreamDestroy(t);
       delete p;
       return FR_E_DEVICE;
     }
@@ -200,8 +200,8 @@ void fr_pool_destroy(fr_pool *p) {
   if (!p) return;
   for (auto &kv : p->reqs) kv.second.release();
   for (auto s : p->streams) {
-    hipStreamSynchronize(s);
-    hipStreamDestroy(s);
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
   }
   delete p;
 }
